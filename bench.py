@@ -1,0 +1,196 @@
+"""Throughput of the fluctuating Shan-Chen hot path on one MI355X.
+
+Workload (default): the batched metastable ensemble -- 64 D2Q9 replicas of
+side 128/256/512 (seeded draw), FP32 shifted populations, E4 force stencil,
+T_hat stratified over [0.6, 0.99], mean densities between binodal and
+spinodal, kBT = 1e-13, one fused kernel launch per step over all replicas,
+S(k) of every replica accumulated in FP64 every 100 steps, replayed as
+captured hipGraphs.  A "step" advances every replica by one time step.
+
+Prints one JSON line (value = MLUPS over the whole ensemble) with the
+roofline of the fused step kernel (HIP events on the library's stream) and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline (FP32 D2Q9 fluct. SC); surrogate speedup at 5% S(k) err"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2212_07848_amd/csrc/fsc_step_kernel.h",
+                  "paper_2212_07848_amd/csrc/fsc_device.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_lup(D: int, precision: str) -> int:
+    Q = 9 if D == 2 else 19
+    return 2 * Q * (4 if precision == "fp32" else 8)
+
+
+def traffic_from_profile(name: str, lups_per_launch: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        doc = json.load(fh)
+    if doc.get("kernel_hash") != kernel_hash():
+        return None
+    return doc.get("bytes_per_launch")
+
+
+def time_steps(obj, steps: int, stream, torch):
+    """Average duration of one fused step launch (HIP events on the library's
+    stream), over `steps` launches without measurement."""
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    obj.run(steps, 0)
+    stop.record(stream)
+    stop.synchronize()
+    return start.elapsed_time(stop) / steps * 1e-3  # s per step
+
+
+def run_ensemble(args, torch, fsc, I):
+    reps = I.ensemble_replicas(n=args.replicas, seed=0, kBT=1e-13)
+    plist = [fsc.make_params(**{k: v for k, v in r.items() if k != "precision"}, precision="fp32")
+             for r in reps]
+    lups = sum(r["nx"] * r["ny"] for r in reps)
+    stream = torch.cuda.Stream()
+    ens = fsc.Ensemble(plist, stream=stream)
+    ens.init_uniform()
+    ens.run(args.warmup, I.ENSEMBLE["sk_every"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.run(args.steps, I.ENSEMBLE["sk_every"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # kernel-only timing of the fused step (same launch configuration)
+    t_step = time_steps(ens, args.kernel_steps, stream, torch)
+    st = ens.stats(0)
+    ens.close()
+    return dict(lups=lups, dt=dt, t_step=t_step, stats_ok=st["bad"] == 0,
+                sides=sorted({r["nx"] for r in reps}), nrep=len(reps))
+
+
+def run_single(cfg, steps, torch, fsc, kBT=None):
+    p = fsc.make_params(D=cfg["D"], nx=cfg["nx"], ny=cfg["ny"], nz=cfg["nz"],
+                        stencil=cfg["stencil"], precision=cfg["precision"], T_hat=cfg["T_hat"],
+                        rho0=cfg["rho0"], kBT=cfg["kBT"] if kBT is None else kBT, seed=cfg["seed"])
+    stream = torch.cuda.Stream()
+    lat = fsc.Lattice(p, stream=stream)
+    lat.init_uniform()
+    lat.run(64, 0)
+    t = time_steps(lat, steps, stream, torch)
+    lat.close()
+    n = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    return dict(mlups=n / t / 1e6, gbs=n * bytes_per_lup(cfg["D"], cfg["precision"]) / t / 1e9,
+                ms_per_step=t * 1e3)
+
+
+def cpu_baseline(I, budget_s: float):
+    """The FP64 oracle on a bounded sample of the ensemble workload: whole
+    replicas of the same workload, stepped until the time budget is used."""
+    import oracle as O
+    reps = I.ensemble_replicas(n=64, seed=0, kBT=1e-13)
+    done_lups, t_used, sample = 0, 0.0, []
+    for r in reps:
+        if t_used > budget_s:
+            break
+        G = O.coupling_from_reduced_temperature(r["T_hat"])
+        f = O.uniform_state(2, (r["ny"], r["nx"]), r["rho0"])
+        nsteps = 5
+        t0 = time.perf_counter()
+        O.step(f, nsteps, G=G, kind=4, kBT=r["kBT"], seed=r["seed"], replica=r["replica"])
+        dt = time.perf_counter() - t0
+        t_used += dt
+        done_lups += r["nx"] * r["ny"] * nsteps
+        sample.append(f"r{r['replica']}:{r['nx']}^2x{nsteps}")
+    return dict(value=done_lups / t_used / 1e6, unit="MLUPS", cores=O.max_threads(),
+                kind="oracle",
+                sample=f"{len(sample)} ensemble replicas x 5 steps ({', '.join(sample)}), "
+                       f"{t_used:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--kernel-steps", type=int, default=1000)
+    ap.add_argument("--replicas", type=int, default=64)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import fsc_inputs as I
+    import paper_2212_07848_amd as fsc
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+
+    r = run_ensemble(args, torch, fsc, I)
+    mlups = r["lups"] * args.steps / r["dt"] / 1e6
+    bpl = bytes_per_lup(2, "fp32")
+    achieved = r["lups"] * bpl / r["t_step"] / 1e9
+    traffic = traffic_from_profile("step_ensemble64", r["lups"])
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["dt"] / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": I.ENSEMBLE["name"], "replicas": r["nrep"], "sides": r["sides"],
+                   "lattice_updates_per_step": r["lups"], "stencil": "E4", "sk_every": 100,
+                   "kBT": 1e-13, "collision": "MRT all rates 1 (BGK tau=1)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_step<D2Q9,E4,float,noise>",
+                     "algorithmic_bytes_per_lup": bpl,
+                     "avg_launch_us": round(r["t_step"] * 1e6, 2)},
+    }
+    if not args.no_extra:
+        extra = {}
+        for cfg, steps in ((I.DEEP_QUENCH, 300), (I.METASTABLE_3D, 200)):
+            e = run_single(cfg, steps, torch, fsc)
+            e["frac_hbm"] = round(e["gbs"] / HBM_PEAK_GBS, 4)
+            extra[cfg["name"]] = {k: round(v, 3) for k, v in e.items()}
+        e = run_single(I.DEEP_QUENCH, 300, torch, fsc, kBT=0.0)
+        extra[I.DEEP_QUENCH["name"] + "_noise_free"] = {k: round(v, 3) for k, v in e.items()}
+        out["extra"] = extra
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(I, args.cpu_budget)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

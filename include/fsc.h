@@ -1,0 +1,205 @@
+/*
+ * fsc.h -- C ABI of the MI355X (gfx950) fluctuating Shan-Chen lattice
+ * Boltzmann library.
+ *
+ * Method: Lulli, Biferale, Falcucci, Sbragaglia, Yang, Shan, "Metastable and
+ * Unstable Dynamics in multi-phase lattice Boltzmann", arXiv:2212.07848.
+ *   - the fluctuating lattice Boltzmann equation, Eq. (12):
+ *       f_i(x + c_i, t + 1) - f_i(x, t) = Omega_i + F_i + eta_i
+ *     with Omega a relaxation collision, F_i the Guo forcing of the Shan-Chen
+ *     force and eta_i Gaussian noise whose covariance is diagonal in moment
+ *     space and zero on the conserved moments (text following Eq. 16);
+ *   - the Shan-Chen force, Eq. (1): F(x) = G psi(x) sum_a w(|e_a|^2) psi(x+e_a) e_a,
+ *     with psi = exp(-1/n) and weights normalised to sum_a w e_ax^2 = 1, so that
+ *     the bulk pressure is Eq. (2): p = n T - (G/2) psi^2, T = c_s^2 = 1/3;
+ *   - the structure factor S(k) = <|dn(k)|^2> measured against Eq. (16).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an int: FSC_OK (0) or a negative FSC_E_* code; no
+ *     exception crosses the ABI.  fsc_last_error() gives a message for the
+ *     last failure on a context; fsc_strerror() names a code.
+ *   - Lattices are periodic.  D = 2 uses D2Q9 (nz = 1), D = 3 uses D3Q19.
+ *   - Population order (the index i of every f array):
+ *       D2Q9 : (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
+ *       D3Q19: (0,0,0) (1,0,0) (-1,0,0) (0,1,0) (0,-1,0) (0,0,1) (0,0,-1)
+ *              (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1)
+ *              (1,0,-1) (-1,0,1) (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+ *   - Host population arrays are double, layout f[i][z][y][x] (x fastest),
+ *     Q * nx * ny * nz values, holding the populations right after streaming
+ *     at the context's current time step.  Node index = x + nx*(y + ny*z).
+ *   - Host buffers are owned by the caller and only read/written during the
+ *     call.  Device buffers are owned by the library unless passed in through
+ *     fsc_create_external (then the caller keeps ownership and must keep them
+ *     alive until fsc_destroy).
+ *   - All device work is enqueued on the hipStream_t given at creation (NULL =
+ *     the null stream).  Calls that return host data synchronise that stream.
+ *     A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef FSC_H
+#define FSC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSC_OK 0
+#define FSC_E_INVAL (-1)    /* invalid argument or parameter combination */
+#define FSC_E_HIP (-2)      /* a HIP runtime call failed */
+#define FSC_E_OOM (-3)      /* device or host allocation failed */
+#define FSC_E_DIVERGED (-4) /* non-finite or non-positive density detected */
+#define FSC_E_STATE (-5)    /* call not valid in the current state */
+#define FSC_E_NOTSUP (-6)   /* combination not supported by this build */
+
+#define FSC_E4 4 /* 2D: |e|^2 in {1,2} (8 neighbours); 3D: {1,2} (18) */
+#define FSC_E8 8 /* 2D only: |e|^2 in {1,2,4,5,8} (24 neighbours, 5x5 block) */
+
+#define FSC_FP32_SHIFTED 0 /* populations stored as float deviations f_i - w_i rho0 */
+#define FSC_FP64 1         /* populations stored as double deviations f_i - w_i rho0 */
+
+#define FSC_SK_AXIS 0   /* bins [D][n/2 + 1]: modes +-m along each lattice axis */
+#define FSC_SK_RADIAL 1 /* bins [nb]: shells b = round(|m|), equal sides only */
+
+/*
+ * Run parameters.  Layout is fixed: 6 x int32, 7 x double, uint64, 2 x uint32
+ * (96 bytes, natural alignment).
+ *   D, nx, ny, nz  lattice dimension and sides (nz = 1 when D = 2); sides >= 1
+ *   stencil        FSC_E4 or FSC_E8 (interaction set of Eq. 1)
+ *   precision      FSC_FP32_SHIFTED or FSC_FP64
+ *   T_hat          reduced temperature T/T_c; used when G is NaN:
+ *                  G = e^2 / (3 T_hat) (critical point of Eq. 3-4 with b = 1)
+ *   G              coupling of Eq. (1), G > 0 attractive; NaN = from T_hat
+ *   rho0           homogeneous initial density n0 (> 0), also the storage shift
+ *   lambda_bulk    relaxation rate (1/tau) of the bulk (trace) moment
+ *   lambda_shear   relaxation rate of the deviatoric second moments
+ *   lambda_ghost   relaxation rate of the higher (kinetic) moments
+ *                  all three in (0, 2); all equal 1 is BGK with tau = 1
+ *   kBT            fluctuation energy k_B theta in lattice units (>= 0); 0 = no noise
+ *   seed, replica  key of the counter-based noise generator (see fsc_normals)
+ */
+typedef struct fsc_params {
+    int32_t D, nx, ny, nz;
+    int32_t stencil, precision;
+    double T_hat, G, rho0;
+    double lambda_bulk, lambda_shear, lambda_ghost;
+    double kBT;
+    uint64_t seed;
+    uint32_t replica, reserved;
+} fsc_params;
+
+typedef struct fsc_ctx fsc_ctx;
+typedef struct fsc_ens fsc_ens;
+
+/* ----------------------------------------------------------------------- */
+/* Single lattice.                                                          */
+/* ----------------------------------------------------------------------- */
+
+/* Creates a context and allocates its two population buffers (pull
+ * streaming ping-pong).  `stream` is a hipStream_t or NULL.  The state is
+ * undefined until fsc_init_uniform or fsc_set_populations.  Errors:
+ * FSC_E_INVAL (bad parameters), FSC_E_NOTSUP (E8 in 3D), FSC_E_OOM, FSC_E_HIP. */
+int fsc_create(const fsc_params *p, void *stream, fsc_ctx **out);
+
+/* As fsc_create, but uses two caller-owned device buffers of at least
+ * Q * nx * ny * nz elements each (float for FSC_FP32_SHIFTED, double for
+ * FSC_FP64), 256-byte aligned. */
+int fsc_create_external(const fsc_params *p, void *stream, void *dev_buf_a, void *dev_buf_b,
+                        fsc_ctx **out);
+
+int fsc_destroy(fsc_ctx *ctx);
+const char *fsc_last_error(const fsc_ctx *ctx);
+const char *fsc_strerror(int code);
+
+/* Copies the effective parameters (G resolved from T_hat) into *out. */
+int fsc_get_params(const fsc_ctx *ctx, fsc_params *out);
+
+/* Homogeneous initial condition of the runs (paper, simulation protocol):
+ * f_i = w_i rho0, time step 0, S(k) accumulators cleared. */
+int fsc_init_uniform(fsc_ctx *ctx);
+
+/* Sets the streamed populations f (host, double, layout above) as the state
+ * at time step `step` (0 <= step < 2^32).  Clears nothing else. */
+int fsc_set_populations(fsc_ctx *ctx, const double *host_f, int64_t step);
+
+/* Reads the streamed populations of the current state into host_f and the
+ * current time step into *step (may be NULL). */
+int fsc_get_populations(fsc_ctx *ctx, double *host_f, int64_t *step);
+
+/* Advances the state by nsteps >= 0 time steps of Eq. (12), one fused kernel
+ * launch per step.  The noise of step t at node s uses counter (s, t, block,
+ * seed >> 32) and key (seed & 0xffffffff, replica).  Fails with FSC_E_INVAL
+ * if the step count would pass 2^32. */
+int fsc_step(fsc_ctx *ctx, int64_t nsteps);
+
+/* Advances nsteps and accumulates one S(k) sample after every `sk_every`
+ * steps (sk_every <= 0: no samples).  Whole chunks are replayed as one
+ * captured hipGraph.  Equivalent to alternating fsc_step / fsc_measure_sk. */
+int fsc_run(fsc_ctx *ctx, int64_t nsteps, int64_t sk_every);
+
+int fsc_get_step(const fsc_ctx *ctx, int64_t *step);
+
+/* Density n(x) = sum_i f_i of the current state, host double [nz][ny][nx]. */
+int fsc_density(fsc_ctx *ctx, double *host_rho);
+
+/* FP64 reductions of the current state: out[0] = sum n, out[1..3] = sum j
+ * (x, y, z; z = 0 in 2D), out[4] = min n, out[5] = max n, out[6] = number of
+ * nodes with a non-finite or non-positive density, out[7] = node count.
+ * Returns FSC_E_DIVERGED (after filling out) when out[6] > 0. */
+int fsc_stats(fsc_ctx *ctx, double *out8);
+
+/* Structure factor.  One sample adds, for every wave vector k != 0 of the
+ * lattice (k_d = 2 pi m_d / n_d), P(k) = |sum_x n(x) e^{-i k.x}|^2 / N to the
+ * FP64 accumulators of its bins (sum and sum of squares); count holds the
+ * number of (mode, sample) pairs per bin.
+ *   FSC_SK_AXIS   nbins = D * (max side / 2 + 1); bin [d][m] collects the
+ *                 modes with m_d = +-m and all other components 0.
+ *   FSC_SK_RADIAL nbins = round(sqrt(D) * n / 2) + 1 when all sides equal n,
+ *                 else 0; shell b collects the modes with round(|m|) = b,
+ *                 decided in exact integer arithmetic.
+ * Mean S(k) of a bin = sum / count. */
+int fsc_sk_reset(fsc_ctx *ctx);
+int fsc_measure_sk(fsc_ctx *ctx);
+int fsc_sk_nbins(const fsc_ctx *ctx, int kind, int *nbins);
+int fsc_read_sk(fsc_ctx *ctx, int kind, double *sum, double *sumsq, int64_t *count, int nbins);
+
+/* ----------------------------------------------------------------------- */
+/* Ensemble: many independent replicas (uneven sides, couplings, densities, */
+/* seeds) advanced together, one kernel launch per step over all replicas'  */
+/* tiles; fsc_ens_run replays captured hipGraphs.  All replicas must share   */
+/* D, stencil and precision.                                                */
+/* ----------------------------------------------------------------------- */
+int fsc_ens_create(const fsc_params *reps, int nrep, void *stream, fsc_ens **out);
+int fsc_ens_destroy(fsc_ens *ens);
+const char *fsc_ens_last_error(const fsc_ens *ens);
+int fsc_ens_init_uniform(fsc_ens *ens);
+int fsc_ens_run(fsc_ens *ens, int64_t nsteps, int64_t sk_every);
+int fsc_ens_get_step(const fsc_ens *ens, int64_t *step);
+int fsc_ens_get_populations(fsc_ens *ens, int replica, double *host_f);
+int fsc_ens_set_populations(fsc_ens *ens, int replica, const double *host_f);
+int fsc_ens_stats(fsc_ens *ens, int replica, double *out8);
+int fsc_ens_sk_nbins(const fsc_ens *ens, int replica, int kind, int *nbins);
+int fsc_ens_read_sk(fsc_ens *ens, int replica, int kind, double *sum, double *sumsq,
+                    int64_t *count, int nbins);
+int fsc_ens_sk_reset(fsc_ens *ens);
+
+/* ----------------------------------------------------------------------- */
+/* Generator checks.                                                        */
+/* ----------------------------------------------------------------------- */
+
+/* Evaluates the device Philox4x32-10 (Salmon et al., SC'11) for n counters
+ * (host arrays: ctr[4n], key[2n], out[4n]).  Synchronous. */
+int fsc_philox(const uint32_t *host_ctr, const uint32_t *host_key, uint32_t *host_out, int64_t n);
+
+/* The Q-D-1 standard normals the step kernel draws for each (node, step)
+ * pair (host arrays node[n], step[n]; out[n][Q-D-1] as double), computed in
+ * the given precision (FSC_FP32_SHIFTED: float, FSC_FP64: double):
+ *   u(r) = (floor(r/2^9) + 1/2) / 2^23; pairs sqrt(-2 ln u_a) (cos, sin)(2 pi u_b)
+ *   from (r0, r1), (r2, r3) of blocks 0, 1, ... .  Synchronous. */
+int fsc_normals(int D, int precision, uint64_t seed, uint32_t replica, const int64_t *host_node,
+                const int64_t *host_step, int64_t n, double *host_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSC_H */

@@ -1,4 +1,4 @@
-"""Closed forms and linear theory used to pin the oracle (test helpers only).
+"""Thermodynamics and exact linear theory of the method (part of the CPU oracle).
 
 Everything here is written from the paper's equations (Lulli et al.,
 arXiv:2212.07848) or from linear algebra on the linearised lattice update; none

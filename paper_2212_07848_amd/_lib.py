@@ -1,0 +1,340 @@
+"""ctypes binding of ``libfsc.so`` (include/fsc.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels; this module converts
+numpy arrays and Python scalars to the C ABI and raises on error codes.  The
+library must have been built (``__graft_entry__.build()``); importing the
+binding without it raises, so there is no silent fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libfsc.so")
+
+FSC_E4, FSC_E8 = 4, 8
+FSC_FP32_SHIFTED, FSC_FP64 = 0, 1
+FSC_SK_AXIS, FSC_SK_RADIAL = 0, 1
+
+ERRORS = {0: "ok", -1: "invalid argument", -2: "HIP runtime error", -3: "out of memory",
+          -4: "diverged", -5: "invalid state", -6: "not supported"}
+
+# Every symbol include/fsc.h declares.
+EXPORTS = [
+    "fsc_create", "fsc_create_external", "fsc_destroy", "fsc_last_error", "fsc_strerror",
+    "fsc_get_params", "fsc_init_uniform", "fsc_set_populations", "fsc_get_populations",
+    "fsc_step", "fsc_run", "fsc_get_step", "fsc_density", "fsc_stats", "fsc_sk_reset",
+    "fsc_measure_sk", "fsc_sk_nbins", "fsc_read_sk",
+    "fsc_ens_create", "fsc_ens_destroy", "fsc_ens_last_error", "fsc_ens_init_uniform",
+    "fsc_ens_run", "fsc_ens_get_step", "fsc_ens_get_populations", "fsc_ens_set_populations",
+    "fsc_ens_stats", "fsc_ens_sk_nbins", "fsc_ens_read_sk", "fsc_ens_sk_reset",
+    "fsc_philox", "fsc_normals",
+]
+
+
+class FscError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        super().__init__(f"{ERRORS.get(code, code)} ({code}){': ' + msg if msg else ''}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("D", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("stencil", C.c_int32), ("precision", C.c_int32),
+                ("T_hat", C.c_double), ("G", C.c_double), ("rho0", C.c_double),
+                ("lambda_bulk", C.c_double), ("lambda_shear", C.c_double),
+                ("lambda_ghost", C.c_double), ("kBT", C.c_double),
+                ("seed", C.c_uint64), ("replica", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+assert C.sizeof(Params) == 96
+
+
+def make_params(*, D=2, nx=64, ny=64, nz=1, stencil=4, precision="fp32", T_hat=0.9,
+                G=math.nan, rho0=0.5, lam=(1.0, 1.0, 1.0), kBT=0.0, seed=0, replica=0) -> Params:
+    prec = {"fp32": FSC_FP32_SHIFTED, "fp64": FSC_FP64}.get(precision, precision)
+    return Params(D, nx, ny, 1 if D == 2 else nz, stencil, prec, T_hat, G, rho0,
+                  lam[0], lam[1], lam[2], kBT, seed, replica, 0)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"{LIBPATH} is not built; run __graft_entry__.build() first")
+    L = C.CDLL(LIBPATH)
+    vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
+    pp = C.POINTER(Params)
+    u32p = C.POINTER(C.c_uint32)
+    sig = {
+        "fsc_create": ([pp, vp, C.POINTER(vp)], C.c_int),
+        "fsc_create_external": ([pp, vp, vp, vp, C.POINTER(vp)], C.c_int),
+        "fsc_destroy": ([vp], C.c_int),
+        "fsc_last_error": ([vp], C.c_char_p),
+        "fsc_strerror": ([C.c_int], C.c_char_p),
+        "fsc_get_params": ([vp, pp], C.c_int),
+        "fsc_init_uniform": ([vp], C.c_int),
+        "fsc_set_populations": ([vp, dp, C.c_int64], C.c_int),
+        "fsc_get_populations": ([vp, dp, i64p], C.c_int),
+        "fsc_step": ([vp, C.c_int64], C.c_int),
+        "fsc_run": ([vp, C.c_int64, C.c_int64], C.c_int),
+        "fsc_get_step": ([vp, i64p], C.c_int),
+        "fsc_density": ([vp, dp], C.c_int),
+        "fsc_stats": ([vp, dp], C.c_int),
+        "fsc_sk_reset": ([vp], C.c_int),
+        "fsc_measure_sk": ([vp], C.c_int),
+        "fsc_sk_nbins": ([vp, C.c_int, C.POINTER(C.c_int)], C.c_int),
+        "fsc_read_sk": ([vp, C.c_int, dp, dp, i64p, C.c_int], C.c_int),
+        "fsc_ens_create": ([pp, C.c_int, vp, C.POINTER(vp)], C.c_int),
+        "fsc_ens_destroy": ([vp], C.c_int),
+        "fsc_ens_last_error": ([vp], C.c_char_p),
+        "fsc_ens_init_uniform": ([vp], C.c_int),
+        "fsc_ens_run": ([vp, C.c_int64, C.c_int64], C.c_int),
+        "fsc_ens_get_step": ([vp, i64p], C.c_int),
+        "fsc_ens_get_populations": ([vp, C.c_int, dp], C.c_int),
+        "fsc_ens_set_populations": ([vp, C.c_int, dp], C.c_int),
+        "fsc_ens_stats": ([vp, C.c_int, dp], C.c_int),
+        "fsc_ens_sk_nbins": ([vp, C.c_int, C.c_int, C.POINTER(C.c_int)], C.c_int),
+        "fsc_ens_read_sk": ([vp, C.c_int, C.c_int, dp, dp, i64p, C.c_int], C.c_int),
+        "fsc_ens_sk_reset": ([vp], C.c_int),
+        "fsc_philox": ([u32p, u32p, u32p, C.c_int64], C.c_int),
+        "fsc_normals": ([C.c_int, C.c_int, C.c_uint64, C.c_uint32, i64p, i64p, C.c_int64, dp],
+                        C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _check(rc, errfn=None, handle=None):
+    if rc != 0:
+        msg = ""
+        if errfn is not None:
+            m = errfn(handle)
+            msg = m.decode() if m else ""
+        raise FscError(rc, msg)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):  # torch.cuda.Stream
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _q(D):
+    return 9 if D == 2 else 19
+
+
+class Lattice:
+    """One periodic lattice (fsc_ctx)."""
+
+    def __init__(self, p: Params, stream=None, buffers=None):
+        L = lib()
+        self._h = C.c_void_p()
+        if buffers is None:
+            rc = L.fsc_create(C.byref(p), _stream_handle(stream), C.byref(self._h))
+        else:
+            a, b = buffers
+            rc = L.fsc_create_external(C.byref(p), _stream_handle(stream), C.c_void_p(a.data_ptr()),
+                                       C.c_void_p(b.data_ptr()), C.byref(self._h))
+            self._keep = buffers
+        _check(rc, L.fsc_last_error, None)
+        self.p = Params()
+        _check(L.fsc_get_params(self._h, C.byref(self.p)))
+        self.D, self.Q = p.D, _q(p.D)
+        self.shape = (p.ny, p.nx) if p.D == 2 else (p.nz, p.ny, p.nx)
+
+    def _c(self, rc):
+        _check(rc, lib().fsc_last_error, self._h)
+
+    def close(self):
+        if self._h:
+            lib().fsc_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def G(self):
+        return self.p.G
+
+    def init_uniform(self):
+        self._c(lib().fsc_init_uniform(self._h))
+
+    def set_populations(self, f: np.ndarray, step: int = 0):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == (self.Q,) + self.shape
+        self._c(lib().fsc_set_populations(self._h, _dp(f), int(step)))
+
+    def get_populations(self):
+        f = np.empty((self.Q,) + self.shape)
+        st = C.c_int64()
+        self._c(lib().fsc_get_populations(self._h, _dp(f), C.byref(st)))
+        return f
+
+    @property
+    def t(self) -> int:
+        st = C.c_int64()
+        self._c(lib().fsc_get_step(self._h, C.byref(st)))
+        return st.value
+
+    def step(self, n: int):
+        self._c(lib().fsc_step(self._h, int(n)))
+
+    def run(self, n: int, sk_every: int = 0):
+        self._c(lib().fsc_run(self._h, int(n), int(sk_every)))
+
+    def density(self):
+        n = np.empty(self.shape)
+        self._c(lib().fsc_density(self._h, _dp(n)))
+        return n
+
+    def stats(self, allow_diverged: bool = False):
+        out = np.empty(8)
+        rc = lib().fsc_stats(self._h, _dp(out))
+        if rc != 0 and not (allow_diverged and rc == -4):
+            self._c(rc)
+        return dict(mass=out[0], mom=out[1:1 + self.D].copy(), rho_min=out[4], rho_max=out[5],
+                    bad=int(out[6]), nodes=int(out[7]))
+
+    def sk_reset(self):
+        self._c(lib().fsc_sk_reset(self._h))
+
+    def measure_sk(self):
+        self._c(lib().fsc_measure_sk(self._h))
+
+    def read_sk(self, kind=FSC_SK_AXIS):
+        nb = C.c_int()
+        self._c(lib().fsc_sk_nbins(self._h, kind, C.byref(nb)))
+        s, q = np.zeros(nb.value), np.zeros(nb.value)
+        c = np.zeros(nb.value, dtype=np.int64)
+        self._c(lib().fsc_read_sk(self._h, kind, _dp(s), _dp(q),
+                                  c.ctypes.data_as(C.POINTER(C.c_int64)), nb.value))
+        if kind == FSC_SK_AXIS:
+            s, q, c = (v.reshape(self.D, -1) for v in (s, q, c))
+        return s, q, c
+
+
+class Ensemble:
+    """Many replicas advanced by one launch per step (fsc_ens)."""
+
+    def __init__(self, plist, stream=None):
+        L = lib()
+        arr = (Params * len(plist))(*plist)
+        self._h = C.c_void_p()
+        _check(L.fsc_ens_create(arr, len(plist), _stream_handle(stream), C.byref(self._h)),
+               L.fsc_ens_last_error, None)
+        self.plist = list(plist)
+        self.n = len(plist)
+
+    def _c(self, rc):
+        _check(rc, lib().fsc_ens_last_error, self._h)
+
+    def close(self):
+        if self._h:
+            lib().fsc_ens_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _shape(self, r):
+        p = self.plist[r]
+        return (_q(p.D),) + ((p.ny, p.nx) if p.D == 2 else (p.nz, p.ny, p.nx))
+
+    def init_uniform(self):
+        self._c(lib().fsc_ens_init_uniform(self._h))
+
+    def run(self, n: int, sk_every: int = 0):
+        self._c(lib().fsc_ens_run(self._h, int(n), int(sk_every)))
+
+    @property
+    def t(self) -> int:
+        st = C.c_int64()
+        self._c(lib().fsc_ens_get_step(self._h, C.byref(st)))
+        return st.value
+
+    def get_populations(self, r: int):
+        f = np.empty(self._shape(r))
+        self._c(lib().fsc_ens_get_populations(self._h, r, _dp(f)))
+        return f
+
+    def set_populations(self, r: int, f: np.ndarray):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == self._shape(r)
+        self._c(lib().fsc_ens_set_populations(self._h, r, _dp(f)))
+
+    def stats(self, r: int):
+        out = np.empty(8)
+        self._c(lib().fsc_ens_stats(self._h, r, _dp(out)))
+        return dict(mass=out[0], mom=out[1:4].copy(), rho_min=out[4], rho_max=out[5],
+                    bad=int(out[6]), nodes=int(out[7]))
+
+    def sk_reset(self):
+        self._c(lib().fsc_ens_sk_reset(self._h))
+
+    def read_sk(self, r: int, kind=FSC_SK_AXIS):
+        nb = C.c_int()
+        self._c(lib().fsc_ens_sk_nbins(self._h, r, kind, C.byref(nb)))
+        s, q = np.zeros(nb.value), np.zeros(nb.value)
+        c = np.zeros(nb.value, dtype=np.int64)
+        self._c(lib().fsc_ens_read_sk(self._h, r, kind, _dp(s), _dp(q),
+                                      c.ctypes.data_as(C.POINTER(C.c_int64)), nb.value))
+        if kind == FSC_SK_AXIS:
+            D = self.plist[r].D
+            s, q, c = (v.reshape(D, -1) for v in (s, q, c))
+        return s, q, c
+
+
+def philox(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
+    n = ctr.shape[0]
+    out = np.zeros((n, 4), dtype=np.uint32)
+    u32p = C.POINTER(C.c_uint32)
+    _check(lib().fsc_philox(ctr.ctypes.data_as(u32p), key.ctypes.data_as(u32p),
+                            out.ctypes.data_as(u32p), n))
+    return out
+
+
+def normals(D: int, precision: str, seed: int, replica: int, nodes, steps) -> np.ndarray:
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    steps = np.ascontiguousarray(steps, dtype=np.int64)
+    n = nodes.size
+    nn = 6 if D == 2 else 15
+    out = np.zeros((n, nn))
+    prec = {"fp32": 0, "fp64": 1}[precision]
+    i64p = C.POINTER(C.c_int64)
+    _check(lib().fsc_normals(D, prec, C.c_uint64(seed), C.c_uint32(replica),
+                             nodes.ctypes.data_as(i64p), steps.ctypes.data_as(i64p), n, _dp(out)))
+    return out

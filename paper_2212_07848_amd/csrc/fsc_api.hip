@@ -1,0 +1,845 @@
+// fsc_api.hip -- the C ABI of include/fsc.h: contexts, ensembles, graph
+// replay, state transfer, measurement bookkeeping.  Host code only; all
+// per-node work is done by the kernels of fsc_step.hip / fsc_measure.hip.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fsc.h"
+#include "fsc_internal.h"
+
+using namespace fsc;
+
+namespace {
+
+constexpr double CS2 = 1.0 / 3.0;
+
+int q_of(int D) { return D == 2 ? 9 : 19; }
+
+template <class L>
+void lattice_tables(std::vector<int> &c, std::vector<double> &w, std::vector<double> &b,
+                    std::vector<int> &cls) {
+    c.resize(3 * L::Q);
+    w.resize(L::Q);
+    b.resize(L::Q);
+    cls.resize(L::Q);
+    for (int i = 0; i < L::Q; ++i) {
+        for (int d = 0; d < 3; ++d) c[3 * i + d] = L::c(i, d);
+        w[i] = L::w(i);
+        b[i] = moment_norm<L>(i);
+        cls[i] = L::cls(i);
+    }
+}
+
+struct Rep {
+    fsc_params p{};
+    int Q = 0;
+    int64_t N = 0;
+    size_t esz = 4;
+    void *buf[2] = {nullptr, nullptr};
+    bool own = true;
+    // lattice tables
+    std::vector<int> c;
+    std::vector<double> w, b;
+    std::vector<int> cls;
+    // structure factor
+    int n_axis = 0, n_rad = 0;
+    std::vector<int64_t> axis_modes, rad_modes;
+    int64_t nsamples = 0;
+    double *d_sk = nullptr;  // axis_sum, axis_sq, rad_sum, rad_sq
+    void *cbuf = nullptr, *ctmp = nullptr;
+    void *tw[3] = {nullptr, nullptr, nullptr};
+    double *d_stats = nullptr, *d_partials = nullptr;
+    Geometry geom() const { return Geometry{p.D, p.nx, p.ny, p.nz, N}; }
+};
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    int64_t samples = 0;
+};
+
+}  // namespace
+
+struct fsc_ens {
+    std::vector<Rep> reps;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int D = 2, stencil = 4, precision = 0;
+    bool noise = false;
+    TileShape tile{128, 1};
+    std::vector<RepDesc> desc;
+    RepDesc *d_desc = nullptr;
+    int *d_tile_begin = nullptr;
+    uint64_t *d_step = nullptr;
+    int64_t step = 0;
+    int total_tiles = 0;
+    std::string err;
+    std::map<std::pair<int, std::pair<int64_t, int64_t>>, GraphEntry> graphs;
+};
+
+struct fsc_ctx {
+    fsc_ens *e;
+};
+
+namespace {
+thread_local std::string g_create_error;
+}
+
+namespace {
+
+void ens_free(fsc_ens *e);
+
+int fail(fsc_ens *e, int code, const std::string &msg) {
+    if (e) e->err = msg;
+    return code;
+}
+
+#define HIPCHK(ens, expr)                                                            \
+    do {                                                                             \
+        hipError_t _e = (expr);                                                      \
+        if (_e != hipSuccess)                                                        \
+            return fail((ens), FSC_E_HIP,                                            \
+                        std::string(#expr) + ": " + hipGetErrorString(_e));          \
+    } while (0)
+
+int resolve_params(const fsc_params &in, fsc_params &out, std::string &err) {
+    out = in;
+    if (in.D != 2 && in.D != 3) return err = "D must be 2 or 3", FSC_E_INVAL;
+    if (in.nx < 1 || in.ny < 1 || in.nz < 1) return err = "sides must be >= 1", FSC_E_INVAL;
+    if (in.D == 2 && in.nz != 1) return err = "nz must be 1 in 2D", FSC_E_INVAL;
+    if (in.stencil != FSC_E4 && in.stencil != FSC_E8) return err = "stencil must be 4 or 8", FSC_E_INVAL;
+    if (in.D == 3 && in.stencil == FSC_E8) return err = "E8 is 2D only", FSC_E_NOTSUP;
+    if (in.precision != FSC_FP32_SHIFTED && in.precision != FSC_FP64)
+        return err = "bad precision", FSC_E_INVAL;
+    if (!(in.rho0 > 0.0) || !std::isfinite(in.rho0)) return err = "rho0 must be > 0", FSC_E_INVAL;
+    const double lams[3] = {in.lambda_bulk, in.lambda_shear, in.lambda_ghost};
+    for (double l : lams)
+        if (!(l > 0.0 && l < 2.0)) return err = "relaxation rates must lie in (0, 2)", FSC_E_INVAL;
+    if (!(in.kBT >= 0.0) || !std::isfinite(in.kBT)) return err = "kBT must be >= 0", FSC_E_INVAL;
+    if (std::isnan(in.G)) {
+        if (!(in.T_hat > 0.0) || !std::isfinite(in.T_hat))
+            return err = "T_hat must be > 0 when G is NaN", FSC_E_INVAL;
+        // critical point of p = nT - (G/2) exp(-2/n): T_c = G/e^2; T = 1/3
+        out.G = std::exp(2.0) * CS2 / in.T_hat;
+    } else {
+        if (!std::isfinite(in.G)) return err = "G must be finite", FSC_E_INVAL;
+        out.T_hat = in.G != 0.0 ? std::exp(2.0) * CS2 / in.G : INFINITY;
+    }
+    const int64_t N = int64_t(in.nx) * in.ny * in.nz;
+    if (N * q_of(in.D) >= (int64_t(1) << 31)) return err = "lattice too large", FSC_E_INVAL;
+    return FSC_OK;
+}
+
+int init_rep(Rep &r, const fsc_params &p, void *ext_a, void *ext_b, fsc_ens *e) {
+    r.p = p;
+    r.Q = q_of(p.D);
+    r.N = int64_t(p.nx) * p.ny * p.nz;
+    r.esz = p.precision == FSC_FP32_SHIFTED ? 4 : 8;
+    if (p.D == 2) lattice_tables<D2Q9>(r.c, r.w, r.b, r.cls);
+    else lattice_tables<D3Q19>(r.c, r.w, r.b, r.cls);
+    const size_t bytes = r.esz * size_t(r.Q) * size_t(r.N);
+    if (ext_a || ext_b) {
+        if (!ext_a || !ext_b || ext_a == ext_b) return fail(e, FSC_E_INVAL, "need two distinct buffers");
+        r.buf[0] = ext_a;
+        r.buf[1] = ext_b;
+        r.own = false;
+    } else {
+        for (int k = 0; k < 2; ++k)
+            if (hipMalloc(&r.buf[k], bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(e, FSC_E_OOM, "population buffer allocation failed");
+            }
+    }
+    // S(k) geometry: modes per bin, exact integer rounding of |m|
+    const int D = p.D;
+    const int nmax = std::max(p.nx, std::max(p.ny, p.nz));
+    r.n_axis = nmax / 2 + 1;
+    const bool cubic = p.nx == p.ny && (D == 2 || p.ny == p.nz);
+    auto round_sqrt = [](int64_t m) {
+        int64_t b = int64_t(std::sqrt(double(m)));
+        while (b * b > m) --b;
+        while ((b + 1) * (b + 1) <= m) ++b;
+        if (m - b * b > b) ++b;
+        return int(b);
+    };
+    r.n_rad = cubic ? round_sqrt(int64_t(D) * (p.nx / 2) * (p.nx / 2)) + 1 : 0;
+    r.axis_modes.assign(size_t(D) * r.n_axis, 0);
+    r.rad_modes.assign(size_t(r.n_rad), 0);
+    const int sides[3] = {p.nx, p.ny, p.nz};
+    for (int d = 0; d < D; ++d)
+        for (int q = 1; q < sides[d]; ++q) {
+            const int m = q <= sides[d] / 2 ? q : sides[d] - q;
+            r.axis_modes[size_t(d) * r.n_axis + m] += 1;
+        }
+    if (cubic) {
+        const int L = p.nx;
+        std::vector<int64_t> sq(L);
+        for (int q = 0; q < L; ++q) {
+            const int64_t m = q <= L / 2 ? q : q - L;
+            sq[q] = m * m;
+        }
+        const int zmax = D == 3 ? L : 1;
+        for (int z = 0; z < zmax; ++z)
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    const int64_t m2 = sq[x] + sq[y] + (D == 3 ? sq[z] : 0);
+                    if (m2) r.rad_modes[round_sqrt(m2)] += 1;
+                }
+    }
+    const size_t nsk = 2 * size_t(D) * r.n_axis + 2 * size_t(r.n_rad);
+    if (hipMalloc(&r.d_sk, sizeof(double) * nsk) != hipSuccess ||
+        hipMalloc(&r.d_stats, sizeof(double) * 8) != hipSuccess ||
+        hipMalloc(&r.d_partials, sizeof(double) * stats_partials_len()) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e, FSC_E_OOM, "accumulator allocation failed");
+    }
+    HIPCHK(e, hipMemsetAsync(r.d_sk, 0, sizeof(double) * nsk, e->stream));
+    return FSC_OK;
+}
+
+int ensure_fft(Rep &r, fsc_ens *e) {
+    if (r.cbuf) return FSC_OK;
+    const size_t csz = 2 * r.esz * size_t(r.N);
+    if (hipMalloc(&r.cbuf, csz) != hipSuccess || hipMalloc(&r.ctmp, csz) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e, FSC_E_OOM, "FFT buffer allocation failed");
+    }
+    const int sides[3] = {r.p.nx, r.p.ny, r.p.nz};
+    for (int d = 0; d < r.p.D; ++d) {
+        if (sides[d] > 8192) return fail(e, FSC_E_NOTSUP, "S(k) needs sides <= 8192");
+        if (hipMalloc(&r.tw[d], 2 * r.esz * twiddle_len(sides[d])) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(e, FSC_E_OOM, "twiddle allocation failed");
+        }
+        HIPCHK(e, launch_twiddles(r.p.precision, r.tw[d], sides[d], e->stream));
+    }
+    return FSC_OK;
+}
+
+// enqueues one S(k) sample of replica r from buffer `par`
+int enqueue_measure(Rep &r, int par, fsc_ens *e) {
+    const Geometry g = r.geom();
+    HIPCHK(e, launch_density_complex(g, r.p.precision, r.buf[par], r.cbuf, e->stream));
+    void *a = r.cbuf, *b = r.ctmp;
+    int dims[3] = {r.p.nx, r.p.ny, r.p.nz};
+    // pass d transforms the contiguous axis then rotates (n0,n1,n2) -> (n1,n2,n0)
+    int n0 = dims[0], n1 = dims[1], n2 = dims[2];
+    for (int d = 0; d < r.p.D; ++d) {
+        // lattice axis d is contiguous in pass d; a unit middle axis makes the
+        // rotation a plain transpose of (n2 x n0)
+        if (n1 == 1) HIPCHK(e, launch_fft_axis(r.p.precision, a, b, r.tw[d], n0, n2, 1, e->stream));
+        else HIPCHK(e, launch_fft_axis(r.p.precision, a, b, r.tw[d], n0, n1, n2, e->stream));
+        const int t0 = n0;
+        n0 = n1;
+        n1 = n2;
+        n2 = t0;
+        std::swap(a, b);
+    }
+    BinTargets t;
+    const size_t na = size_t(r.p.D) * r.n_axis;
+    t.axis_sum = r.d_sk;
+    t.axis_sq = r.d_sk + na;
+    t.rad_sum = r.n_rad ? r.d_sk + 2 * na : nullptr;
+    t.rad_sq = r.n_rad ? r.d_sk + 2 * na + r.n_rad : nullptr;
+    t.n_axis = r.n_axis;
+    t.n_rad = r.n_rad;
+    HIPCHK(e, launch_bin(g, r.p.precision, a, t, e->stream));
+    return FSC_OK;
+}
+
+// -------------------------------------------------------------------------
+// Tiling of the fused step.
+// -------------------------------------------------------------------------
+void build_desc(fsc_ens *e) {
+    e->desc.clear();
+    int64_t work = 0;  // cross tiles x planes over the ensemble
+    for (auto &r : e->reps) {
+        const int tx = (r.p.nx + e->tile.tx - 1) / e->tile.tx;
+        const int ty = r.p.D == 3 ? (r.p.ny + e->tile.ty - 1) / e->tile.ty : 1;
+        const int ns = r.p.D == 3 ? r.p.nz : r.p.ny;
+        work += int64_t(tx) * ty * ns;
+    }
+    // marching length: enough blocks to fill 256 CUs several times over,
+    // but long marches so that the 2R halo planes stay a small overhead
+    const int64_t target_blocks = 2048;
+    int H = int(std::min<int64_t>(256, std::max<int64_t>(16, work / target_blocks)));
+    int tile_begin = 0;
+    for (auto &r : e->reps) {
+        RepDesc d{};
+        d.buf[0] = r.buf[0];
+        d.buf[1] = r.buf[1];
+        d.N = r.N;
+        d.nx = r.p.nx;
+        d.ny = r.p.ny;
+        d.nz = r.p.nz;
+        d.ns = r.p.D == 3 ? r.p.nz : r.p.ny;
+        d.plane = r.p.D == 3 ? r.p.nx * r.p.ny : r.p.nx;
+        d.tiles_x = (r.p.nx + e->tile.tx - 1) / e->tile.tx;
+        d.tiles_y = r.p.D == 3 ? (r.p.ny + e->tile.ty - 1) / e->tile.ty : 1;
+        const int h = std::min(H, d.ns);
+        const int nch = (d.ns + h - 1) / h;
+        d.H = (d.ns + nch - 1) / nch;            // balanced chunk length
+        d.nchunk = (d.ns + d.H - 1) / d.H;       // no empty trailing chunk
+        d.tile_begin = tile_begin;
+        tile_begin += d.tiles_x * d.tiles_y * d.nchunk;
+        d.noise = r.p.kBT > 0.0;
+        d.G = r.p.G;
+        d.rho0 = r.p.rho0;
+        d.psi0 = std::exp(-1.0 / r.p.rho0);
+        for (int a = 0; a < 19; ++a) {
+            d.lam[a] = 1.0;
+            d.amp[a] = 0.0;
+        }
+        for (int a = 0; a < r.Q; ++a) {
+            const int k = r.cls[a];
+            const double lam = k == 0 ? 1.0
+                                      : (k == 1 ? r.p.lambda_bulk
+                                                : (k == 2 ? r.p.lambda_shear : r.p.lambda_ghost));
+            d.lam[a] = lam;
+            if (k != 0) {
+                const double g = 1.0 - lam;
+                d.amp[a] = std::sqrt(r.p.kBT / CS2 * r.b[a] * (1.0 - g * g));
+            }
+        }
+        d.key0 = uint32_t(r.p.seed & 0xffffffffu);
+        d.key1 = r.p.replica;
+        d.seed_hi = uint32_t(r.p.seed >> 32);
+        e->desc.push_back(d);
+    }
+    e->total_tiles = tile_begin;
+}
+
+int upload_desc(fsc_ens *e) {
+    build_desc(e);
+    const size_t n = e->desc.size();
+    if (!e->d_desc) {
+        if (hipMalloc(&e->d_desc, sizeof(RepDesc) * n) != hipSuccess ||
+            hipMalloc(&e->d_tile_begin, sizeof(int) * n) != hipSuccess ||
+            hipMalloc(&e->d_step, sizeof(uint64_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(e, FSC_E_OOM, "descriptor allocation failed");
+        }
+    }
+    std::vector<int> tb(n);
+    for (size_t k = 0; k < n; ++k) tb[k] = e->desc[k].tile_begin;
+    HIPCHK(e, hipMemcpyAsync(e->d_desc, e->desc.data(), sizeof(RepDesc) * n, hipMemcpyHostToDevice,
+                             e->stream));
+    HIPCHK(e, hipMemcpyAsync(e->d_tile_begin, tb.data(), sizeof(int) * n, hipMemcpyHostToDevice,
+                             e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    return FSC_OK;
+}
+
+int set_step_device(fsc_ens *e, int64_t step) {
+    const uint64_t s = uint64_t(step);
+    HIPCHK(e, hipMemcpyAsync(e->d_step, &s, sizeof(s), hipMemcpyHostToDevice, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    e->step = step;
+    return FSC_OK;
+}
+
+void drop_graphs(fsc_ens *e) {
+    for (auto &kv : e->graphs)
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    e->graphs.clear();
+}
+
+int enqueue_steps(fsc_ens *e, int parity, int64_t n, int64_t sk_every, int64_t *samples) {
+    for (int64_t k = 0; k < n; ++k) {
+        StepLaunch L;
+        L.reps = e->d_desc;
+        L.tile_begin = e->d_tile_begin;
+        L.nrep = int(e->reps.size());
+        L.total_tiles = e->total_tiles;
+        L.parity = (parity + int(k & 1)) & 1;
+        L.step_base = e->d_step;
+        L.step_off = uint32_t(k);
+        L.D = e->D;
+        L.stencil = e->stencil;
+        L.precision = e->precision;
+        L.noise = e->noise;
+        L.tile = e->tile;
+        HIPCHK(e, launch_step(L, e->stream));
+        if (sk_every > 0 && (k + 1) % sk_every == 0) {
+            const int par = (parity + int((k + 1) & 1)) & 1;
+            for (auto &r : e->reps) {
+                int rc = enqueue_measure(r, par, e);
+                if (rc) return rc;
+            }
+            if (samples) ++*samples;
+        }
+    }
+    HIPCHK(e, launch_step_advance(e->d_step, uint64_t(n), e->stream));
+    return FSC_OK;
+}
+
+int ens_run(fsc_ens *e, int64_t nsteps, int64_t sk_every) {
+    if (nsteps < 0) return fail(e, FSC_E_INVAL, "nsteps < 0");
+    if (nsteps == 0) return FSC_OK;
+    if (e->step + nsteps > (int64_t(1) << 32)) return fail(e, FSC_E_INVAL, "step counter would pass 2^32");
+    if (sk_every > 0)
+        for (auto &r : e->reps) {
+            int rc = ensure_fft(r, e);
+            if (rc) return rc;
+        }
+    // whole chunks as graph replays
+    int64_t chunk = sk_every > 0 ? sk_every : 64;
+    if (chunk & 1) chunk *= 2;
+    int64_t done = 0;
+    const int64_t nchunks = nsteps / chunk;
+    if (nchunks >= 2) {
+        const int parity = int(e->step & 1);
+        auto key = std::make_pair(parity, std::make_pair(chunk, sk_every));
+        auto it = e->graphs.find(key);
+        if (it == e->graphs.end()) {
+            GraphEntry ge;
+            hipGraph_t graph;
+            HIPCHK(e, hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue_steps(e, parity, chunk, sk_every, &ge.samples);
+            hipError_t ec = hipStreamEndCapture(e->stream, &graph);
+            if (rc) return rc;
+            if (ec != hipSuccess) return fail(e, FSC_E_HIP, std::string("capture: ") + hipGetErrorString(ec));
+            ec = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ec != hipSuccess) return fail(e, FSC_E_HIP, std::string("instantiate: ") + hipGetErrorString(ec));
+            it = e->graphs.emplace(key, ge).first;
+        }
+        for (int64_t c = 0; c < nchunks; ++c) HIPCHK(e, hipGraphLaunch(it->second.exec, e->stream));
+        for (auto &r : e->reps) r.nsamples += nchunks * it->second.samples;
+        done = nchunks * chunk;
+        e->step += done;
+    }
+    const int64_t rest = nsteps - done;
+    if (rest > 0) {
+        int64_t samples = 0;
+        int rc = enqueue_steps(e, int(e->step & 1), rest, sk_every, &samples);
+        if (rc) return rc;
+        for (auto &r : e->reps) r.nsamples += samples;
+        e->step += rest;
+    }
+    return FSC_OK;
+}
+
+int ens_create(const fsc_params *ps, int nrep, void *stream, void *ext_a, void *ext_b,
+               fsc_ens **out) {
+    if (!out || !ps || nrep < 1) return FSC_E_INVAL;
+    *out = nullptr;
+    // validate everything before touching the device
+    std::string err;
+    std::vector<fsc_params> rp(nrep);
+    for (int k = 0; k < nrep; ++k) {
+        int rc = resolve_params(ps[k], rp[k], err);
+        if (rc) {
+            g_create_error = err;
+            return rc;
+        }
+        if (rp[k].D != rp[0].D || rp[k].stencil != rp[0].stencil ||
+            rp[k].precision != rp[0].precision) {
+            g_create_error = "replicas must share D, stencil and precision";
+            return FSC_E_INVAL;
+        }
+    }
+    fsc_ens *e = new fsc_ens();
+    e->stream = static_cast<hipStream_t>(stream);
+    if (!e->stream) {
+        // graphs cannot be captured on the null stream: use a private one
+        if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            delete e;
+            g_create_error = "stream creation failed";
+            return FSC_E_HIP;
+        }
+        e->own_stream = true;
+    }
+    e->D = rp[0].D;
+    e->stencil = rp[0].stencil;
+    e->precision = rp[0].precision;
+    TileShape shapes[4];
+    tile_shapes(e->D, e->stencil, shapes, 4);
+    e->tile = shapes[0];
+    e->reps.resize(nrep);
+    for (int k = 0; k < nrep; ++k) {
+        e->noise = e->noise || rp[k].kBT > 0.0;
+        int rc = init_rep(e->reps[k], rp[k], ext_a, ext_b, e);
+        if (rc) {
+            g_create_error = e->err;
+            ens_free(e);
+            return rc;
+        }
+    }
+    int rc = upload_desc(e);
+    if (rc == FSC_OK) rc = set_step_device(e, 0);
+    if (rc) {
+        g_create_error = e->err;
+        ens_free(e);
+        return rc;
+    }
+    *out = e;
+    return FSC_OK;
+}
+
+void ens_free(fsc_ens *e) {
+    if (!e) return;
+    (void)hipStreamSynchronize(e->stream);
+    drop_graphs(e);
+    for (auto &r : e->reps) {
+        if (r.own) {
+            if (r.buf[0]) (void)hipFree(r.buf[0]);
+            if (r.buf[1]) (void)hipFree(r.buf[1]);
+        }
+        void *ptrs[] = {r.d_sk, r.cbuf, r.ctmp, r.tw[0], r.tw[1], r.tw[2], r.d_stats, r.d_partials};
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+    }
+    if (e->d_desc) (void)hipFree(e->d_desc);
+    if (e->d_tile_begin) (void)hipFree(e->d_tile_begin);
+    if (e->d_step) (void)hipFree(e->d_step);
+    if (e->own_stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+}
+
+int rep_index(fsc_ens *e, int replica) {
+    if (replica < 0 || replica >= int(e->reps.size())) return fail(e, FSC_E_INVAL, "bad replica");
+    return FSC_OK;
+}
+
+int ens_set_pop(fsc_ens *e, int ri, const double *host_f, int64_t step) {
+    Rep &r = e->reps[ri];
+    const int nx = r.p.nx, ny = r.p.ny, nz = r.p.nz;
+    const int par = int(step & 1);
+    std::vector<unsigned char> raw(r.esz * size_t(r.Q) * size_t(r.N));
+    for (int i = 0; i < r.Q; ++i) {
+        const int cx = r.c[3 * i], cy = r.c[3 * i + 1], cz = r.c[3 * i + 2];
+        const double shift = r.w[i] * r.p.rho0;
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    // stored f*_i(x) is the streamed f_i(x + c_i)
+                    const int xs = wrap_any(x + cx, nx), ys = wrap_any(y + cy, ny), zs = wrap_any(z + cz, nz);
+                    const size_t src = size_t(i) * r.N + xs + size_t(nx) * (ys + size_t(ny) * zs);
+                    const size_t dst = size_t(i) * r.N + x + size_t(nx) * (y + size_t(ny) * z);
+                    const double v = host_f[src] - shift;
+                    if (r.esz == 4) reinterpret_cast<float *>(raw.data())[dst] = float(v);
+                    else reinterpret_cast<double *>(raw.data())[dst] = v;
+                }
+    }
+    HIPCHK(e, hipMemcpyAsync(r.buf[par], raw.data(), raw.size(), hipMemcpyHostToDevice, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    return FSC_OK;
+}
+
+int ens_get_pop(fsc_ens *e, int ri, double *host_f) {
+    Rep &r = e->reps[ri];
+    const int nx = r.p.nx, ny = r.p.ny, nz = r.p.nz;
+    const int par = int(e->step & 1);
+    std::vector<unsigned char> raw(r.esz * size_t(r.Q) * size_t(r.N));
+    HIPCHK(e, hipMemcpyAsync(raw.data(), r.buf[par], raw.size(), hipMemcpyDeviceToHost, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    for (int i = 0; i < r.Q; ++i) {
+        const int cx = r.c[3 * i], cy = r.c[3 * i + 1], cz = r.c[3 * i + 2];
+        const double shift = r.w[i] * r.p.rho0;
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const int xs = wrap_any(x - cx, nx), ys = wrap_any(y - cy, ny), zs = wrap_any(z - cz, nz);
+                    const size_t src = size_t(i) * r.N + xs + size_t(nx) * (ys + size_t(ny) * zs);
+                    const size_t dst = size_t(i) * r.N + x + size_t(nx) * (y + size_t(ny) * z);
+                    const double v = r.esz == 4 ? double(reinterpret_cast<float *>(raw.data())[src])
+                                                : reinterpret_cast<double *>(raw.data())[src];
+                    host_f[dst] = shift + v;
+                }
+    }
+    return FSC_OK;
+}
+
+int ens_stats(fsc_ens *e, int ri, double *out8) {
+    Rep &r = e->reps[ri];
+    HIPCHK(e, launch_stats(r.geom(), r.p.precision, r.buf[e->step & 1], r.p.rho0, r.d_partials,
+                           r.d_stats, e->stream));
+    HIPCHK(e, hipMemcpyAsync(out8, r.d_stats, sizeof(double) * 8, hipMemcpyDeviceToHost, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    if (out8[6] > 0.0) return fail(e, FSC_E_DIVERGED, "non-finite or non-positive density");
+    return FSC_OK;
+}
+
+int ens_nbins(const fsc_ens *e, int ri, int kind, int *nbins) {
+    const Rep &r = e->reps[ri];
+    if (kind == FSC_SK_AXIS) *nbins = r.p.D * r.n_axis;
+    else if (kind == FSC_SK_RADIAL) *nbins = r.n_rad;
+    else return FSC_E_INVAL;
+    return FSC_OK;
+}
+
+int ens_read_sk(fsc_ens *e, int ri, int kind, double *sum, double *sumsq, int64_t *count, int nbins) {
+    Rep &r = e->reps[ri];
+    int nb = 0;
+    if (ens_nbins(e, ri, kind, &nb)) return fail(e, FSC_E_INVAL, "bad S(k) kind");
+    if (nbins != nb) return fail(e, FSC_E_INVAL, "nbins does not match fsc_sk_nbins");
+    if (nb == 0) return FSC_OK;
+    const size_t na = size_t(r.p.D) * r.n_axis;
+    const double *s = kind == FSC_SK_AXIS ? r.d_sk : r.d_sk + 2 * na;
+    const double *q = kind == FSC_SK_AXIS ? r.d_sk + na : r.d_sk + 2 * na + r.n_rad;
+    std::vector<double> hs(nb), hq(nb);
+    HIPCHK(e, hipMemcpyAsync(hs.data(), s, sizeof(double) * nb, hipMemcpyDeviceToHost, e->stream));
+    HIPCHK(e, hipMemcpyAsync(hq.data(), q, sizeof(double) * nb, hipMemcpyDeviceToHost, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    const auto &modes = kind == FSC_SK_AXIS ? r.axis_modes : r.rad_modes;
+    for (int k = 0; k < nb; ++k) {
+        if (sum) sum[k] = hs[k];
+        if (sumsq) sumsq[k] = hq[k];
+        if (count) count[k] = modes[k] * r.nsamples;
+    }
+    return FSC_OK;
+}
+
+int ens_sk_reset(fsc_ens *e) {
+    for (auto &r : e->reps) {
+        const size_t nsk = 2 * size_t(r.p.D) * r.n_axis + 2 * size_t(r.n_rad);
+        HIPCHK(e, hipMemsetAsync(r.d_sk, 0, sizeof(double) * nsk, e->stream));
+        r.nsamples = 0;
+    }
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    return FSC_OK;
+}
+
+int ens_init_uniform(fsc_ens *e) {
+    for (auto &r : e->reps) {
+        const size_t bytes = r.esz * size_t(r.Q) * size_t(r.N);
+        HIPCHK(e, hipMemsetAsync(r.buf[0], 0, bytes, e->stream));
+        HIPCHK(e, hipMemsetAsync(r.buf[1], 0, bytes, e->stream));
+    }
+    int rc = set_step_device(e, 0);
+    if (rc) return rc;
+    return ens_sk_reset(e);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *fsc_strerror(int code) {
+    switch (code) {
+    case FSC_OK: return "ok";
+    case FSC_E_INVAL: return "invalid argument";
+    case FSC_E_HIP: return "HIP runtime error";
+    case FSC_E_OOM: return "out of memory";
+    case FSC_E_DIVERGED: return "diverged (non-finite or non-positive density)";
+    case FSC_E_STATE: return "invalid state";
+    case FSC_E_NOTSUP: return "not supported";
+    default: return "unknown error";
+    }
+}
+
+int fsc_create(const fsc_params *p, void *stream, fsc_ctx **out) {
+    return fsc_create_external(p, stream, nullptr, nullptr, out);
+}
+
+int fsc_create_external(const fsc_params *p, void *stream, void *a, void *b, fsc_ctx **out) {
+    if (!out || !p) return FSC_E_INVAL;
+    *out = nullptr;
+    fsc_ens *e = nullptr;
+    int rc = ens_create(p, 1, stream, a, b, &e);
+    if (rc) return rc;
+    *out = new fsc_ctx{e};
+    return FSC_OK;
+}
+
+int fsc_destroy(fsc_ctx *ctx) {
+    if (!ctx) return FSC_E_INVAL;
+    ens_free(ctx->e);
+    delete ctx;
+    return FSC_OK;
+}
+
+const char *fsc_last_error(const fsc_ctx *ctx) {
+    return ctx ? ctx->e->err.c_str() : g_create_error.c_str();
+}
+
+int fsc_get_params(const fsc_ctx *ctx, fsc_params *out) {
+    if (!ctx || !out) return FSC_E_INVAL;
+    *out = ctx->e->reps[0].p;
+    return FSC_OK;
+}
+
+int fsc_init_uniform(fsc_ctx *ctx) {
+    if (!ctx) return FSC_E_INVAL;
+    return ens_init_uniform(ctx->e);
+}
+
+int fsc_set_populations(fsc_ctx *ctx, const double *host_f, int64_t step) {
+    if (!ctx || !host_f) return FSC_E_INVAL;
+    if (step < 0 || step >= (int64_t(1) << 32)) return fail(ctx->e, FSC_E_INVAL, "step out of range");
+    int rc = ens_set_pop(ctx->e, 0, host_f, step);
+    if (rc) return rc;
+    return set_step_device(ctx->e, step);
+}
+
+int fsc_get_populations(fsc_ctx *ctx, double *host_f, int64_t *step) {
+    if (!ctx || !host_f) return FSC_E_INVAL;
+    if (step) *step = ctx->e->step;
+    return ens_get_pop(ctx->e, 0, host_f);
+}
+
+int fsc_step(fsc_ctx *ctx, int64_t nsteps) {
+    if (!ctx) return FSC_E_INVAL;
+    return ens_run(ctx->e, nsteps, 0);
+}
+
+int fsc_run(fsc_ctx *ctx, int64_t nsteps, int64_t sk_every) {
+    if (!ctx) return FSC_E_INVAL;
+    return ens_run(ctx->e, nsteps, sk_every);
+}
+
+int fsc_get_step(const fsc_ctx *ctx, int64_t *step) {
+    if (!ctx || !step) return FSC_E_INVAL;
+    *step = ctx->e->step;
+    return FSC_OK;
+}
+
+int fsc_density(fsc_ctx *ctx, double *host_rho) {
+    if (!ctx || !host_rho) return FSC_E_INVAL;
+    fsc_ens *e = ctx->e;
+    Rep &r = e->reps[0];
+    void *tmp = nullptr;
+    if (hipMalloc(&tmp, r.esz * size_t(r.N)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e, FSC_E_OOM, "density buffer");
+    }
+    hipError_t ec = launch_density_real(r.geom(), r.p.precision, r.buf[e->step & 1], tmp, e->stream);
+    std::vector<unsigned char> raw(r.esz * size_t(r.N));
+    if (ec == hipSuccess) ec = hipMemcpyAsync(raw.data(), tmp, raw.size(), hipMemcpyDeviceToHost, e->stream);
+    if (ec == hipSuccess) ec = hipStreamSynchronize(e->stream);
+    (void)hipFree(tmp);
+    if (ec != hipSuccess) return fail(e, FSC_E_HIP, hipGetErrorString(ec));
+    for (int64_t s = 0; s < r.N; ++s)
+        host_rho[s] = r.p.rho0 + (r.esz == 4 ? double(reinterpret_cast<float *>(raw.data())[s])
+                                             : reinterpret_cast<double *>(raw.data())[s]);
+    return FSC_OK;
+}
+
+int fsc_stats(fsc_ctx *ctx, double *out8) {
+    if (!ctx || !out8) return FSC_E_INVAL;
+    return ens_stats(ctx->e, 0, out8);
+}
+
+int fsc_sk_reset(fsc_ctx *ctx) {
+    if (!ctx) return FSC_E_INVAL;
+    return ens_sk_reset(ctx->e);
+}
+
+int fsc_measure_sk(fsc_ctx *ctx) {
+    if (!ctx) return FSC_E_INVAL;
+    fsc_ens *e = ctx->e;
+    Rep &r = e->reps[0];
+    int rc = ensure_fft(r, e);
+    if (rc) return rc;
+    rc = enqueue_measure(r, int(e->step & 1), e);
+    if (rc) return rc;
+    r.nsamples += 1;
+    return FSC_OK;
+}
+
+int fsc_sk_nbins(const fsc_ctx *ctx, int kind, int *nbins) {
+    if (!ctx || !nbins) return FSC_E_INVAL;
+    return ens_nbins(ctx->e, 0, kind, nbins);
+}
+
+int fsc_read_sk(fsc_ctx *ctx, int kind, double *sum, double *sumsq, int64_t *count, int nbins) {
+    if (!ctx) return FSC_E_INVAL;
+    return ens_read_sk(ctx->e, 0, kind, sum, sumsq, count, nbins);
+}
+
+// ---- ensemble -------------------------------------------------------------
+int fsc_ens_create(const fsc_params *reps, int nrep, void *stream, fsc_ens **out) {
+    return ens_create(reps, nrep, stream, nullptr, nullptr, out);
+}
+int fsc_ens_destroy(fsc_ens *ens) {
+    if (!ens) return FSC_E_INVAL;
+    ens_free(ens);
+    return FSC_OK;
+}
+const char *fsc_ens_last_error(const fsc_ens *ens) {
+    return ens ? ens->err.c_str() : g_create_error.c_str();
+}
+int fsc_ens_init_uniform(fsc_ens *ens) { return ens ? ens_init_uniform(ens) : FSC_E_INVAL; }
+int fsc_ens_run(fsc_ens *ens, int64_t nsteps, int64_t sk_every) {
+    return ens ? ens_run(ens, nsteps, sk_every) : FSC_E_INVAL;
+}
+int fsc_ens_get_step(const fsc_ens *ens, int64_t *step) {
+    if (!ens || !step) return FSC_E_INVAL;
+    *step = ens->step;
+    return FSC_OK;
+}
+int fsc_ens_get_populations(fsc_ens *ens, int replica, double *host_f) {
+    if (!ens || !host_f) return FSC_E_INVAL;
+    int rc = rep_index(ens, replica);
+    return rc ? rc : ens_get_pop(ens, replica, host_f);
+}
+int fsc_ens_set_populations(fsc_ens *ens, int replica, const double *host_f) {
+    if (!ens || !host_f) return FSC_E_INVAL;
+    int rc = rep_index(ens, replica);
+    return rc ? rc : ens_set_pop(ens, replica, host_f, ens->step);
+}
+int fsc_ens_stats(fsc_ens *ens, int replica, double *out8) {
+    if (!ens || !out8) return FSC_E_INVAL;
+    int rc = rep_index(ens, replica);
+    return rc ? rc : ens_stats(ens, replica, out8);
+}
+int fsc_ens_sk_nbins(const fsc_ens *ens, int replica, int kind, int *nbins) {
+    if (!ens || !nbins || replica < 0 || replica >= int(ens->reps.size())) return FSC_E_INVAL;
+    return ens_nbins(ens, replica, kind, nbins);
+}
+int fsc_ens_read_sk(fsc_ens *ens, int replica, int kind, double *sum, double *sumsq, int64_t *count,
+                    int nbins) {
+    if (!ens) return FSC_E_INVAL;
+    int rc = rep_index(ens, replica);
+    return rc ? rc : ens_read_sk(ens, replica, kind, sum, sumsq, count, nbins);
+}
+int fsc_ens_sk_reset(fsc_ens *ens) { return ens ? ens_sk_reset(ens) : FSC_E_INVAL; }
+
+// ---- generator checks ---------------------------------------------------
+int fsc_philox(const uint32_t *host_ctr, const uint32_t *host_key, uint32_t *host_out, int64_t n) {
+    if (n < 0 || (n > 0 && (!host_ctr || !host_key || !host_out))) return FSC_E_INVAL;
+    if (n == 0) return FSC_OK;
+    uint32_t *d = nullptr;
+    const size_t bytes = sizeof(uint32_t) * size_t(n) * 10;
+    if (hipMalloc(&d, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return FSC_E_OOM;
+    }
+    hipError_t ec = hipMemcpy(d, host_ctr, sizeof(uint32_t) * 4 * n, hipMemcpyHostToDevice);
+    if (ec == hipSuccess) ec = hipMemcpy(d + 4 * n, host_key, sizeof(uint32_t) * 2 * n, hipMemcpyHostToDevice);
+    if (ec == hipSuccess) ec = launch_philox(d, d + 4 * n, d + 6 * n, n, nullptr);
+    if (ec == hipSuccess) ec = hipMemcpy(host_out, d + 6 * n, sizeof(uint32_t) * 4 * n, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    return ec == hipSuccess ? FSC_OK : FSC_E_HIP;
+}
+
+int fsc_normals(int D, int precision, uint64_t seed, uint32_t replica, const int64_t *host_node,
+                const int64_t *host_step, int64_t n, double *host_out) {
+    if ((D != 2 && D != 3) || (precision != 0 && precision != 1) || n < 0) return FSC_E_INVAL;
+    if (n == 0) return FSC_OK;
+    if (!host_node || !host_step || !host_out) return FSC_E_INVAL;
+    const int nn = D == 2 ? D2Q9::NNORM : D3Q19::NNORM;
+    int64_t *d = nullptr;
+    const size_t bytes = sizeof(int64_t) * size_t(n) * 2 + sizeof(double) * size_t(n) * nn;
+    if (hipMalloc(&d, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return FSC_E_OOM;
+    }
+    double *dout = reinterpret_cast<double *>(d + 2 * n);
+    hipError_t ec = hipMemcpy(d, host_node, sizeof(int64_t) * n, hipMemcpyHostToDevice);
+    if (ec == hipSuccess) ec = hipMemcpy(d + n, host_step, sizeof(int64_t) * n, hipMemcpyHostToDevice);
+    if (ec == hipSuccess) ec = launch_normals(D, precision, seed, replica, d, d + n, n, dout, nullptr);
+    if (ec == hipSuccess) ec = hipMemcpy(host_out, dout, sizeof(double) * n * nn, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    return ec == hipSuccess ? FSC_OK : FSC_E_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,271 @@
+// fsc_device.h -- lattice tables, moment basis, counter-based generator and
+// small device helpers shared by the library's kernels (gfx950, wave64).
+//
+// Everything is constexpr so that the per-node collision, written as loops
+// over populations and moments, folds into straight-line code with the
+// integer moment coefficients as immediates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsc {
+
+// ---------------------------------------------------------------------------
+// Lattices (c_s^2 = 1/3).  Population order is the ABI order of include/fsc.h.
+// ---------------------------------------------------------------------------
+struct D2Q9 {
+    static constexpr int D = 2, Q = 9;
+    static constexpr int NNORM = 6;  // non-conserved moments that receive noise
+    __host__ __device__ static constexpr int c(int i, int d) {
+        constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+        constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        return d == 0 ? cx[i] : (d == 1 ? cy[i] : 0);
+    }
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+    // Moment rows, orthogonal under the weights w_i:
+    //   1, cx, cy, 3c^2-2, cx^2-cy^2, cx cy, (3c^2-4)cx, (3c^2-4)cy, 9c^4-15c^2+2
+    __host__ __device__ static constexpr int M(int a, int i) {
+        int x = c(i, 0), y = c(i, 1), q = x * x + y * y;
+        switch (a) {
+        case 0: return 1;
+        case 1: return x;
+        case 2: return y;
+        case 3: return 3 * q - 2;
+        case 4: return x * x - y * y;
+        case 5: return x * y;
+        case 6: return (3 * q - 4) * x;
+        case 7: return (3 * q - 4) * y;
+        default: return 9 * q * q - 15 * q + 2;
+        }
+    }
+    // class: 0 conserved, 1 bulk, 2 shear, 3 ghost
+    __host__ __device__ static constexpr int cls(int a) {
+        return a <= 2 ? 0 : (a == 3 ? 1 : (a <= 5 ? 2 : 3));
+    }
+    // Second-moment rows a = 3..5 are u^T A u quadratic forms: A(a, p, q).
+    __host__ __device__ static constexpr double A(int a, int p, int q) {
+        if (a == 3) return p == q ? 3.0 : 0.0;
+        if (a == 4) return p == q ? (p == 0 ? 1.0 : -1.0) : 0.0;
+        if (a == 5) return p != q ? 0.5 : 0.0;
+        return 0.0;
+    }
+};
+
+struct D3Q19 {
+    static constexpr int D = 3, Q = 19;
+    static constexpr int NNORM = 15;
+    __host__ __device__ static constexpr int c(int i, int d) {
+        constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+        constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+        constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+        return d == 0 ? cx[i] : (d == 1 ? cy[i] : cz[i]);
+    }
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+    // Rows orthogonal under w_i: 1, c, c^2-1, 3cx^2-c^2, cy^2-cz^2, cxcy, cycz,
+    // czcx, (3c^2-5)c, cx(cy^2-cz^2) and cyclic, 3c^4-6c^2+1,
+    // (2c^2-3)(3cx^2-c^2), (2c^2-3)(cy^2-cz^2).
+    __host__ __device__ static constexpr int M(int a, int i) {
+        int x = c(i, 0), y = c(i, 1), z = c(i, 2), q = x * x + y * y + z * z;
+        switch (a) {
+        case 0: return 1;
+        case 1: return x;
+        case 2: return y;
+        case 3: return z;
+        case 4: return q - 1;
+        case 5: return 3 * x * x - q;
+        case 6: return y * y - z * z;
+        case 7: return x * y;
+        case 8: return y * z;
+        case 9: return z * x;
+        case 10: return (3 * q - 5) * x;
+        case 11: return (3 * q - 5) * y;
+        case 12: return (3 * q - 5) * z;
+        case 13: return x * (y * y - z * z);
+        case 14: return y * (z * z - x * x);
+        case 15: return z * (x * x - y * y);
+        case 16: return 3 * q * q - 6 * q + 1;
+        case 17: return (2 * q - 3) * (3 * x * x - q);
+        default: return (2 * q - 3) * (y * y - z * z);
+        }
+    }
+    __host__ __device__ static constexpr int cls(int a) {
+        return a <= 3 ? 0 : (a == 4 ? 1 : (a <= 9 ? 2 : 3));
+    }
+    __host__ __device__ static constexpr double A(int a, int p, int q) {
+        switch (a) {
+        case 4: return p == q ? 1.0 : 0.0;
+        case 5: return p == q ? (p == 0 ? 2.0 : -1.0) : 0.0;
+        case 6: return p == q ? (p == 0 ? 0.0 : (p == 1 ? 1.0 : -1.0)) : 0.0;
+        case 7: return ((p == 0 && q == 1) || (p == 1 && q == 0)) ? 0.5 : 0.0;
+        case 8: return ((p == 1 && q == 2) || (p == 2 && q == 1)) ? 0.5 : 0.0;
+        case 9: return ((p == 2 && q == 0) || (p == 0 && q == 2)) ? 0.5 : 0.0;
+        default: return 0.0;
+        }
+    }
+};
+
+// b_a = sum_i w_i M_ai^2 and the back-transform K(i, a) = w_i M_ai / b_a.
+template <class L>
+__host__ __device__ constexpr double moment_norm(int a) {
+    double s = 0.0;
+    for (int i = 0; i < L::Q; ++i) s += L::w(i) * double(L::M(a, i)) * double(L::M(a, i));
+    return s;
+}
+template <class L>
+__host__ __device__ constexpr double back_coef(int i, int a) {
+    return L::w(i) * double(L::M(a, i)) / moment_norm<L>(a);
+}
+
+// ---------------------------------------------------------------------------
+// Interaction stencils of Eq. (1), as half sets (one of each +-e pair).
+// Weights are normalised to sum_a w e_x^2 = 1 over the full set.
+// ---------------------------------------------------------------------------
+struct StencilE4_2D {
+    static constexpr int R = 1, NH = 4;
+    __host__ __device__ static constexpr int e(int a, int d) {
+        constexpr int ex[4] = {1, 0, 1, -1};
+        constexpr int ey[4] = {0, 1, 1, 1};
+        return d == 0 ? ex[a] : (d == 1 ? ey[a] : 0);
+    }
+    __host__ __device__ static constexpr double w(int a) { return a < 2 ? 1.0 / 3.0 : 1.0 / 12.0; }
+};
+
+struct StencilE8_2D {
+    static constexpr int R = 2, NH = 12;
+    __host__ __device__ static constexpr int e(int a, int d) {
+        // |e|^2 = 1: (1,0) (0,1); 2: (1,1) (-1,1); 4: (2,0) (0,2);
+        // 5: (2,1) (1,2) (-1,2) (-2,1); 8: (2,2) (-2,2)
+        constexpr int ex[12] = {1, 0, 1, -1, 2, 0, 2, 1, -1, -2, 2, -2};
+        constexpr int ey[12] = {0, 1, 1, 1, 0, 2, 1, 2, 2, 1, 2, 2};
+        return d == 0 ? ex[a] : (d == 1 ? ey[a] : 0);
+    }
+    __host__ __device__ static constexpr double w(int a) {
+        return a < 2 ? 4.0 / 21.0
+                     : (a < 4 ? 4.0 / 45.0
+                              : (a < 6 ? 1.0 / 60.0 : (a < 10 ? 2.0 / 315.0 : 1.0 / 5040.0)));
+    }
+};
+
+struct StencilE4_3D {
+    static constexpr int R = 1, NH = 9;
+    __host__ __device__ static constexpr int e(int a, int d) {
+        // |e|^2 = 1: x, y, z; 2: (1,1,0) (1,-1,0) (1,0,1) (1,0,-1) (0,1,1) (0,1,-1)
+        constexpr int ex[9] = {1, 0, 0, 1, 1, 1, 1, 0, 0};
+        constexpr int ey[9] = {0, 1, 0, 1, -1, 0, 0, 1, 1};
+        constexpr int ez[9] = {0, 0, 1, 0, 0, 1, -1, 1, -1};
+        return d == 0 ? ex[a] : (d == 1 ? ey[a] : ez[a]);
+    }
+    __host__ __device__ static constexpr double w(int a) { return a < 3 ? 1.0 / 6.0 : 1.0 / 12.0; }
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The 32x32->64 products
+// are single v_mad_u64_u32 operations; the key schedule is wave-uniform.
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+    constexpr uint32_t MA = 0xD2511F53u, MB = 0xCD9E8D57u;
+    constexpr uint32_t WA = 0x9E3779B9u, WB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = uint64_t(MA) * c.x;
+        const uint64_t pb = uint64_t(MB) * c.z;
+        U4 n;
+        n.x = uint32_t(pb >> 32) ^ c.y ^ k0;
+        n.y = uint32_t(pb);
+        n.z = uint32_t(pa >> 32) ^ c.w ^ k1;
+        n.w = uint32_t(pa);
+        c = n;
+        k0 += WA;
+        k1 += WB;
+    }
+    return c;
+}
+
+// Uniform in (0,1): (floor(r / 2^9) + 1/2) 2^-23, i.e. the odd 24-bit integer
+// (r >> 8) | 1 times 2^-24 -- exact in float and double.
+template <typename real>
+__device__ inline real unit_open(uint32_t r) {
+    return real((r >> 8) | 1u) * real(5.9604644775390625e-08);
+}
+
+__device__ inline void box_muller(float ua, float ub, float &z0, float &z1) {
+    const float rad = sqrtf(-2.0f * logf(ua));
+    float s, c;
+    sincospif(2.0f * ub, &s, &c);
+    z0 = rad * c;
+    z1 = rad * s;
+}
+__device__ inline void box_muller(double ua, double ub, double &z0, double &z1) {
+    const double rad = sqrt(-2.0 * log(ua));
+    double s, c;
+    sincospi(2.0 * ub, &s, &c);
+    z0 = rad * c;
+    z1 = rad * s;
+}
+
+// The NN normals of node `node` at step `step`: pairs (r0,r1), (r2,r3) of
+// Philox blocks 0, 1, ... with counter (node, step, block, seed_hi).
+template <int NN, typename real>
+__device__ inline void node_normals(uint32_t node, uint32_t step, uint32_t seed_hi, uint32_t k0,
+                                    uint32_t k1, real (&z)[NN]) {
+#pragma unroll
+    for (int blk = 0; blk < (NN + 3) / 4; ++blk) {
+        const U4 r = philox4x32_10(U4{node, step, uint32_t(blk), seed_hi}, k0, k1);
+        const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int k = 4 * blk + 2 * p;
+            if (k < NN) {
+                real z0, z1;
+                box_muller(unit_open<real>(rr[2 * p]), unit_open<real>(rr[2 * p + 1]), z0, z1);
+                z[k] = z0;
+                if (k + 1 < NN) z[k + 1] = z1;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-replica description, resident in device memory and read by the kernels
+// with wave-uniform (scalar) loads.
+// ---------------------------------------------------------------------------
+struct RepDesc {
+    void *buf[2];            // population buffers; state at step t is in buf[t & 1]
+    int64_t N;               // nodes
+    int32_t nx, ny, nz;      // sides
+    int32_t ns;              // extent of the marching axis (ny in 2D, nz in 3D)
+    int32_t plane;           // nodes per plane orthogonal to the marching axis
+    int32_t tiles_x, tiles_y;  // cross-section tiles (tiles_y = 1 in 2D)
+    int32_t nchunk, H;       // chunks along the marching axis and their length
+    int32_t tile_begin;      // first global tile index of this replica
+    int32_t noise;           // kBT > 0
+    int32_t pad0;
+    double G, rho0, psi0;
+    double lam[19];          // relaxation rate per moment row
+    double amp[19];          // sqrt(kBT/c_s^2 * b_a * (1 - (1-lam_a)^2)) per row (0: conserved)
+    uint32_t key0, key1, seed_hi, pad1;
+};
+
+// Block index -> logical tile index so that each XCD (blocks are dealt to the
+// 8 XCDs round-robin) receives one contiguous range of tiles, which keeps
+// neighbouring tiles' halo reads inside one L2.
+__device__ inline int xcd_remap(int b, int B) {
+    const int q = B >> 3, r = B & 7, x = b & 7, i = b >> 3;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+__host__ __device__ inline int wrap_any(int v, int n) {
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+}  // namespace fsc

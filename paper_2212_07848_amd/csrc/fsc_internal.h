@@ -1,0 +1,86 @@
+// fsc_internal.h -- declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fsc_device.h"
+
+namespace fsc {
+
+// Tile shape of the fused step kernel: a TX x TY cross-section (TY = 1 in 2D)
+// marching along the slowest axis.
+struct TileShape {
+    int tx, ty;
+};
+
+// Launch of one step over every replica of an ensemble.
+struct StepLaunch {
+    const RepDesc *reps;       // device
+    const int *tile_begin;     // device, [nrep]
+    int nrep;
+    int total_tiles;
+    int parity;                // source buffer index
+    const uint64_t *step_base; // device
+    uint32_t step_off;
+    int D, stencil, precision; // selects the instantiation
+    bool noise;
+    TileShape tile;
+};
+
+// Returns hipErrorInvalidValue when no instantiation matches.
+hipError_t launch_step(const StepLaunch &L, hipStream_t s);
+// Tile shapes compiled for a lattice/stencil; the first is the default.
+int tile_shapes(int D, int stencil, TileShape *out, int max);
+
+// Adds k to the device step counter (one thread).
+hipError_t launch_step_advance(uint64_t *step_base, uint64_t k, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Measurement kernels (fsc_measure.hip).
+// ---------------------------------------------------------------------------
+struct Geometry {
+    int D, nx, ny, nz;
+    int64_t N;
+};
+
+// dn(x) = sum_i f_i(x) - rho0 of the streamed state, gathered from the stored
+// post-collision buffer; written as complex (re = dn, im = 0).
+hipError_t launch_density_complex(const Geometry &g, int precision, const void *buf, void *cplx,
+                                  hipStream_t s);
+// Real density deviation dn(x) (float or double by precision).
+hipError_t launch_density_real(const Geometry &g, int precision, const void *buf, void *out,
+                               hipStream_t s);
+// FP64 state reductions into out[8] (see fsc_stats); `partials` holds
+// stats_partials_len() doubles.
+size_t stats_partials_len();
+hipError_t launch_stats(const Geometry &g, int precision, const void *buf, double rho0,
+                        double *partials, double *out, hipStream_t s);
+
+// In-place complex FFT of every line along the contiguous axis of a
+// [n2][n1][n0] array, then a rotation to [n0][n2][n1]; after D calls the
+// array is back in its original axis order and transformed along every axis.
+// `twiddle` holds n0/2 complex values exp(-2 pi i k / n0) (power-of-two n0)
+// or n0 values (other n0).  `tmp` is a second complex buffer of equal size.
+hipError_t launch_fft_axis(int precision, void *data, void *tmp, const void *twiddle, int n0,
+                           int n1, int n2, hipStream_t s);
+hipError_t launch_twiddles(int precision, void *tw, int n, hipStream_t s);
+size_t twiddle_len(int n);
+
+// Adds |X(k)|^2 / N of one spectrum to the FP64 axis and radial accumulators.
+struct BinTargets {
+    double *axis_sum, *axis_sq;  // [D][n_axis]
+    double *rad_sum, *rad_sq;    // [n_rad] or null
+    int n_axis, n_rad;
+};
+hipError_t launch_bin(const Geometry &g, int precision, const void *spec, const BinTargets &t,
+                      hipStream_t s);
+
+// Device Philox / normals checks.
+hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n,
+                         hipStream_t s);
+hipError_t launch_normals(int D, int precision, uint64_t seed, uint32_t replica,
+                          const int64_t *node, const int64_t *step, int64_t n, double *out,
+                          hipStream_t s);
+
+}  // namespace fsc

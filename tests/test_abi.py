@@ -1,0 +1,50 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+function include/fsc.h declares (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fsc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fsc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_documented_calls():
+    names = declared_functions()
+    for must in ("fsc_create", "fsc_init_uniform", "fsc_step", "fsc_density", "fsc_measure_sk",
+                 "fsc_read_sk", "fsc_stats", "fsc_ens_create", "fsc_ens_run", "fsc_philox"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2212_07848_amd as fsc
+    L = fsc.lib()
+    raw = ctypes.CDLL(fsc._lib.LIBPATH)
+    for name in declared_functions():
+        assert hasattr(raw, name), name
+        assert name in fsc.EXPORTS, name
+    assert sorted(fsc.EXPORTS) == declared_functions()
+    assert L.fsc_strerror(-4).decode().startswith("diverged")
+
+
+def test_params_layout_matches_header():
+    import paper_2212_07848_amd as fsc
+    assert ctypes.sizeof(fsc.Params) == 96
+    assert fsc.Params.T_hat.offset == 24
+    assert fsc.Params.seed.offset == 80
+    assert fsc.Params.replica.offset == 88
+
+
+def test_creation_errors_are_reported_without_touching_the_device():
+    import paper_2212_07848_amd as fsc
+    with pytest.raises(fsc.FscError) as ei:
+        fsc.Lattice(fsc.make_params(D=4))
+    assert ei.value.code == -1
+    assert "D must be" in str(ei.value)

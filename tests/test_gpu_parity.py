@@ -1,0 +1,336 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: FP64 populations agree to 1e-11 relative; FP32-shifted populations
+agree to 1e-5 relative, measured on the full f_i with a floor of w_i n0 (the
+deviations f_i - w_i n0 themselves can be ~1e-7).  Integer work (Philox
+words, node indexing, streaming) is compared bit for bit.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import fsc_inputs as I
+import oracle as O
+from oracle import theory as T
+
+pytestmark = pytest.mark.gpu
+
+fsc = pytest.importorskip("paper_2212_07848_amd")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _params(D, shape, stencil, precision, T_hat=0.9, rho0=0.5, kBT=0.0, lam=(1, 1, 1), seed=0,
+            replica=0):
+    if D == 2:
+        ny, nx = shape
+        nz = 1
+    else:
+        nz, ny, nx = shape
+    return fsc.make_params(D=D, nx=nx, ny=ny, nz=nz, stencil=stencil, precision=precision,
+                           T_hat=T_hat, rho0=rho0, lam=lam, kBT=kBT, seed=seed, replica=replica)
+
+
+def assert_pop_close(got, ref, D, rho0, precision):
+    _, w = O.lattice(D)
+    scale = np.maximum(np.abs(ref), (w * rho0).reshape((-1,) + (1,) * (ref.ndim - 1)))
+    rel = np.abs(got - ref) / scale
+    tol = 1e-11 if precision == "fp64" else 1e-5
+    assert np.isfinite(got).all()
+    assert rel.max() <= tol, f"max rel err {rel.max():.3e} > {tol:.0e}"
+    return rel.max()
+
+
+# --------------------------------------------------------------- generator --
+def test_philox_bitexact_against_oracle_and_published_vectors():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(v, 16) for v in line.split()])
+    rng = np.random.default_rng(1)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2 ** 32, size=(4096, 2), dtype=np.uint64).astype(np.uint32)
+    ctr = np.vstack([np.array([r[0:4] for r in rows], dtype=np.uint32), ctr])
+    key = np.vstack([np.array([r[4:6] for r in rows], dtype=np.uint32), key])
+    got = fsc.philox(ctr, key)
+    for k, r in enumerate(rows):
+        assert list(got[k]) == r[6:10]
+    ref = np.array([O.philox4x32_10(c, kk) for c, kk in zip(ctr[:600], key[:600])], dtype=np.uint32)
+    assert np.array_equal(got[:600], ref)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+@pytest.mark.parametrize("precision,atol", [("fp64", 1e-13), ("fp32", 4e-6)])
+def test_normals_match_oracle(D, precision, atol):
+    rng = np.random.default_rng(2)
+    nodes = rng.integers(0, 2 ** 24, size=3000)
+    steps = rng.integers(0, 2 ** 32, size=3000)
+    seed = (7 << 32) | 12345
+    got = fsc.normals(D, precision, seed, 3, nodes, steps)
+    ref = np.array([O.normals(D, int(n), int(s), seed, 3) for n, s in zip(nodes, steps)])
+    assert np.abs(got - ref).max() <= atol
+
+
+# ------------------------------------------------------------ one step -------
+CASES = [
+    # D, shape (slow..fast), stencil
+    (2, (37, 150), 4),     # ragged x tail (150 = 128 + 22), odd rows
+    (2, (61, 300), 8),     # E8 halo of 2, three x tiles with a ragged tail
+    (2, (1, 7), 4),        # single row: every neighbour wraps onto itself
+    (2, (3, 5), 8),        # lattice smaller than the E8 halo
+    (3, (9, 17, 40), 4),   # ragged in x (32 + 8) and y (8 + 8 + 1)
+    (3, (2, 3, 1), 4),     # degenerate 3D
+]
+
+
+@pytest.mark.parametrize("D,shape,stencil", CASES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_steps_from_random_state(D, shape, stencil, precision):
+    Q = 9 if D == 2 else 19
+    rho0 = 0.8
+    f0 = I.random_populations(Q, shape, rho0, 0.3, seed=11)
+    lam = (0.9, 1.25, 1.6)
+    kw = dict(T_hat=0.85, rho0=rho0, kBT=2e-4, lam=lam, seed=(3 << 32) | 5, replica=2)
+    with fsc.Lattice(_params(D, shape, stencil, precision, **kw)) as lat:
+        lat.set_populations(f0, step=17)
+        lat.step(1)
+        g1 = lat.get_populations()
+        lat.step(2)
+        g3 = lat.get_populations()
+        assert lat.t == 20
+        G = lat.G
+    r1 = O.step(f0, 1, G=G, kind=stencil, kBT=2e-4, lam_bulk=lam[0], lam_shear=lam[1],
+                lam_ghost=lam[2], seed=(3 << 32) | 5, replica=2, t0=17)
+    r3 = O.step(r1, 2, G=G, kind=stencil, kBT=2e-4, lam_bulk=lam[0], lam_shear=lam[1],
+                lam_ghost=lam[2], seed=(3 << 32) | 5, replica=2, t0=18)
+    assert_pop_close(g1, r1, D, rho0, precision)
+    assert_pop_close(g3, r3, D, rho0, precision)
+
+
+def test_coupling_from_reduced_temperature():
+    with fsc.Lattice(_params(2, (8, 8), 4, "fp32", T_hat=0.8)) as lat:
+        assert lat.G == pytest.approx(O.coupling_from_reduced_temperature(0.8), rel=1e-15)
+
+
+# ------------------------------------------------------- long stable runs ----
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_small_parity_workload(precision):
+    c = dict(I.SMALL_PARITY)
+    p = _params(2, (c["ny"], c["nx"]), c["stencil"], precision, T_hat=c["T_hat"], rho0=c["rho0"],
+                kBT=c["kBT"], seed=c["seed"])
+    with fsc.Lattice(p) as lat:
+        lat.init_uniform()
+        lat.step(c["steps"])
+        got = lat.get_populations()
+        G = lat.G
+        st = lat.stats()
+    ref = O.step(O.uniform_state(2, (c["ny"], c["nx"]), c["rho0"]), c["steps"], G=G,
+                 kind=c["stencil"], kBT=c["kBT"], seed=c["seed"])
+    err = assert_pop_close(got, ref, 2, c["rho0"], precision)
+    print(f"{precision}: max rel err {err:.3e}")
+    m_ref, p_ref = O.conserved(ref)
+    M0 = c["rho0"] * c["nx"] * c["ny"]
+    assert abs(st["mass"] - M0) / M0 <= (1e-12 if precision == "fp64" else 1e-6)
+    assert np.abs(st["mom"]).max() / M0 <= (1e-12 if precision == "fp64" else 1e-6)
+    assert abs(m_ref - M0) / M0 < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("D,shape,stencil,T_hat,rho0",
+                         [(2, (32, 64), 8, 0.7, 1.0), (2, (20, 30), 4, 0.9, 0.5),
+                          (3, (8, 12, 16), 4, 0.8, 0.62)])
+def test_noise_free_flat_state_is_bit_exact(precision, D, shape, stencil, T_hat, rho0):
+    with fsc.Lattice(_params(D, shape, stencil, precision, T_hat=T_hat, rho0=rho0)) as lat:
+        lat.init_uniform()
+        lat.step(101)
+        n = lat.density()
+        f = lat.get_populations()
+    assert np.all(n == rho0)
+    assert np.array_equal(f, O.uniform_state(D, shape, rho0))
+
+
+def test_fp32_mass_drift_over_long_run():
+    p = _params(2, (128, 128), 4, "fp32", T_hat=0.9, rho0=0.5, kBT=1e-4)
+    with fsc.Lattice(p) as lat:
+        lat.init_uniform()
+        lat.step(20000)
+        st = lat.stats()
+    M0 = 0.5 * 128 * 128
+    drift = abs(st["mass"] - M0) / M0
+    print(f"fp32 relative mass drift after 20000 steps: {drift:.3e}")
+    assert drift <= 1e-6
+    assert np.abs(st["mom"]).max() / M0 <= 1e-6
+    assert st["bad"] == 0
+
+
+def test_same_seed_is_bitwise_deterministic():
+    p = _params(2, (64, 96), 8, "fp32", T_hat=0.75, rho0=1.0, kBT=1e-4, seed=9)
+    out = []
+    for _ in range(2):
+        with fsc.Lattice(p) as lat:
+            lat.init_uniform()
+            lat.step(300)
+            out.append(lat.get_populations())
+    assert np.array_equal(out[0], out[1])
+    p2 = _params(2, (64, 96), 8, "fp32", T_hat=0.75, rho0=1.0, kBT=1e-4, seed=10)
+    with fsc.Lattice(p2) as lat:
+        lat.init_uniform()
+        lat.step(300)
+        assert not np.array_equal(out[0], lat.get_populations())
+
+
+def test_rejects_bad_parameters():
+    with pytest.raises(fsc.FscError):
+        fsc.Lattice(_params(3, (8, 8, 8), 8, "fp32"))
+    with pytest.raises(fsc.FscError):
+        fsc.Lattice(fsc.make_params(D=2, nx=8, ny=8, rho0=-1.0))
+    with pytest.raises(fsc.FscError):
+        fsc.Lattice(fsc.make_params(D=2, nx=8, ny=8, lam=(1.0, 2.5, 1.0)))
+    with fsc.Lattice(_params(2, (8, 8), 4, "fp32")) as lat:
+        lat.init_uniform()
+        with pytest.raises(fsc.FscError):
+            lat.step(-1)
+
+
+# -------------------------------------------------------------- S(k) --------
+def _sk_case(shape, precision, seed):
+    D = len(shape)
+    Q = 9 if D == 2 else 19
+    f = I.smooth_density_populations(Q, shape, 0.7, 0.05, 5, seed)
+    p = _params(D, shape, 4, precision, rho0=0.7)
+    with fsc.Lattice(p) as lat:
+        lat.set_populations(f, 0)
+        lat.measure_sk()
+        lat.measure_sk()
+        ax = lat.read_sk(fsc.FSC_SK_AXIS)
+        rad = lat.read_sk(fsc.FSC_SK_RADIAL)
+        rho_gpu = lat.density()
+    ref = O.sk_sample(O.density(f))
+    return ax, rad, ref, rho_gpu, O.density(f)
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (48, 80), (24, 40), (16, 16, 16), (12, 10, 9)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_structure_factor_measurement_matches_oracle(shape, precision):
+    ax, rad, ref, rho_gpu, rho_ref = _sk_case(shape, precision, seed=4)
+    tol = 1e-10 if precision == "fp64" else 2e-4
+    assert np.abs(rho_gpu - rho_ref).max() <= (1e-13 if precision == "fp64" else 1e-6)
+    a_sum, a_sq, a_cnt = ax
+    r_sum, r_sq, r_cnt = ref["axis"]
+    D = len(shape)
+    assert np.array_equal(a_cnt, 2 * r_cnt[:, : a_cnt.shape[1]])
+    scale = max(r_sum.max(), 1e-300)
+    assert np.abs(a_sum[:, : r_sum.shape[1]] - 2 * r_sum).max() <= tol * 2 * scale
+    assert np.abs(a_sq[:, : r_sq.shape[1]] - 2 * r_sq).max() <= 2 * tol * 2 * r_sq.max() + 1e-300
+    if ref["radial"] is not None:
+        g_sum, g_sq, g_cnt = rad
+        o_sum, o_sq, o_cnt = ref["radial"]
+        assert np.array_equal(g_cnt, 2 * o_cnt)
+        assert np.abs(g_sum - 2 * o_sum).max() <= tol * 2 * o_sum.max()
+    else:
+        assert rad[0].size == 0
+
+
+# ----------------------------------------------------- graph and ensemble ----
+def test_graph_replay_equals_eager_steps():
+    p = _params(2, (64, 64), 4, "fp32", T_hat=0.9, rho0=0.5, kBT=1e-4, seed=3)
+    with fsc.Lattice(p) as a, fsc.Lattice(p) as b:
+        a.init_uniform()
+        b.init_uniform()
+        a.run(400, sk_every=10)
+        for _ in range(40):
+            b.step(10)
+            b.measure_sk()
+        assert a.t == b.t == 400
+        assert np.array_equal(a.get_populations(), b.get_populations())
+        sa, qa, ca = a.read_sk()
+        sb, qb, cb = b.read_sk()
+        assert np.array_equal(ca, cb)
+        assert np.allclose(sa, sb, rtol=1e-12, atol=0)
+        ra = a.read_sk(fsc.FSC_SK_RADIAL)
+        rb = b.read_sk(fsc.FSC_SK_RADIAL)
+        assert np.allclose(ra[0], rb[0], rtol=1e-12, atol=0)
+        # odd chunk and remainder handling
+        a.run(37, sk_every=7)
+        for _ in range(5):
+            b.step(7)
+            b.measure_sk()
+        b.step(2)
+        assert np.array_equal(a.get_populations(), b.get_populations())
+
+
+def test_ensemble_replicas_equal_single_lattices_and_oracle():
+    specs = [((64, 64), 0.9, 0.5), ((80, 96), 0.8, 2.0), ((128, 128), 0.7, 0.3), ((33, 47), 0.95, 0.8)]
+    plist = [_params(2, sh, 4, "fp32", T_hat=th, rho0=r0, kBT=1e-4, seed=5, replica=k)
+             for k, (sh, th, r0) in enumerate(specs)]
+    ens = fsc.Ensemble(plist)
+    ens.init_uniform()
+    ens.run(130, sk_every=0)
+    assert ens.t == 130
+    for k, (sh, th, r0) in enumerate(specs):
+        with fsc.Lattice(plist[k]) as lat:
+            lat.init_uniform()
+            lat.step(130)
+            single = lat.get_populations()
+            G = lat.G
+        got = ens.get_populations(k)
+        assert np.array_equal(got, single)
+        ref = O.step(O.uniform_state(2, sh, r0), 130, G=G, kind=4, kBT=1e-4, seed=5, replica=k)
+        assert_pop_close(got, ref, 2, r0, "fp32")
+    ens.close()
+
+
+# ------------------------------------------------ full-size sampled parity ---
+@pytest.mark.parametrize("case", ["deep_quench_4096", "metastable_256cube"])
+def test_full_size_one_step_matches_oracle(case):
+    c = I.DEEP_QUENCH if case == "deep_quench_4096" else I.METASTABLE_3D
+    D = c["D"]
+    shape = (c["ny"], c["nx"]) if D == 2 else (c["nz"], c["ny"], c["nx"])
+    Q = 9 if D == 2 else 19
+    f0 = I.random_populations(Q, shape, c["rho0"], 0.1, seed=21)
+    p = _params(D, shape, c["stencil"], c["precision"], T_hat=c["T_hat"], rho0=c["rho0"],
+                kBT=c["kBT"], seed=c["seed"])
+    with fsc.Lattice(p) as lat:
+        lat.set_populations(f0, 1234)
+        lat.step(1)
+        got = lat.get_populations()
+        G = lat.G
+    ref = O.step(f0, 1, G=G, kind=c["stencil"], kBT=c["kBT"], seed=c["seed"], t0=1234)
+    del f0
+    assert_pop_close(got, ref, D, c["rho0"], c["precision"])
+
+
+# ---------------------------------------------- statistics against theory ----
+@pytest.mark.parametrize("precision,T_hat,rho0,kBT", [("fp32", 0.9, 0.5, 1e-6),
+                                                      ("fp32", 0.8, 0.62, 1e-13),
+                                                      ("fp64", 0.9, 2.0, 1e-6)])
+def test_gpu_structure_factor_matches_exact_theory(precision, T_hat, rho0, kBT):
+    L = 64
+    p = _params(2, (L, L), 4, precision, T_hat=T_hat, rho0=rho0, kBT=kBT, seed=17)
+    nb = 40
+    with fsc.Lattice(p) as lat:
+        lat.init_uniform()
+        lat.step(8000)  # burn-in: slowest mode relaxes in ~10^3 steps
+        batches = []
+        for _ in range(nb):
+            lat.sk_reset()
+            lat.run(5000, sk_every=10)
+            s, _, c = lat.read_sk()
+            batches.append(s.sum(axis=0) / np.maximum(c.sum(axis=0), 1))
+        G = lat.G
+    B = np.array(batches)
+    z = []
+    for m in range(1, L // 2 + 1):
+        k = 2 * math.pi * m / L
+        th = T.sk_exact(k, rho0, G, kBT)
+        mean = B[:, m].mean()
+        err = B[:, m].std(ddof=1) / math.sqrt(nb)
+        z.append((mean - th) / err)
+        assert abs(mean / th - 1) < max(0.03, 4 * err / th)
+    z = np.array(z)
+    print("z-scores", np.round(z, 2))
+    assert np.all(np.abs(z) < 4.0)
+    assert np.mean(z ** 2) < 2.5

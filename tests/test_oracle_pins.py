@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-import theory as T
+from oracle import theory as T
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 from scipy import integrate
 
-import theory as T
+from oracle import theory as T
 
 
 def test_critical_point_is_1_1_1():
