@@ -163,6 +163,18 @@ int fsc_measure_sk(fsc_ctx *ctx);
 int fsc_sk_nbins(const fsc_ctx *ctx, int kind, int *nbins);
 int fsc_read_sk(fsc_ctx *ctx, int kind, double *sum, double *sumsq, int64_t *count, int nbins);
 
+/* Time series of S(k, t) and the domain length L(t) (unstable runs, where
+ * the structure factor evolves).  With capacity > 0, every S(k) sample also
+ * writes one row (step, L, S_1 .. S_{nb-1}) where S_b is that sample's mean of
+ * P(k) over radial shell b (row_len = 2 + nb, nb = radial bin count; 0 shells
+ * for non-cubic lattices) and
+ *     L = 2 pi sum_k P(k) / sum_k |k| P(k)      (k != 0, |k| exact per mode),
+ * the inverse first moment of the structure factor as a domain size.  Rows past
+ * `capacity` are counted but not stored.  Enabling clears the series. */
+int fsc_series_enable(fsc_ctx *ctx, int capacity);
+/* Copies min(rows, max_rows) rows into out (row-major, row_len doubles each). */
+int fsc_read_series(fsc_ctx *ctx, double *out, int max_rows, int *nrows, int *row_len);
+
 /* ----------------------------------------------------------------------- */
 /* Ensemble: many independent replicas (uneven sides, couplings, densities, */
 /* seeds) advanced together, one kernel launch per step over all replicas'  */
@@ -182,6 +194,37 @@ int fsc_ens_sk_nbins(const fsc_ens *ens, int replica, int kind, int *nbins);
 int fsc_ens_read_sk(fsc_ens *ens, int replica, int kind, double *sum, double *sumsq,
                     int64_t *count, int nbins);
 int fsc_ens_sk_reset(fsc_ens *ens);
+int fsc_ens_series_enable(fsc_ens *ens, int capacity);
+int fsc_ens_read_series(fsc_ens *ens, int replica, double *out, int max_rows, int *nrows,
+                        int *row_len);
+
+/* ----------------------------------------------------------------------- */
+/* Tiling of the fused step.                                                */
+/* ----------------------------------------------------------------------- */
+
+/* Times every compiled tile shape (cross-section tile, register prefetch
+ * depth) and marching length on the context's own buffers and keeps the
+ * fastest; the choice is cached per process and geometry.  The state is not
+ * changed (a trial launch only writes the buffer that holds no live data) and
+ * results do not depend on the tiling.  fsc_step / fsc_run tune automatically
+ * on first use when the lattice (or ensemble) has at least 2^20 nodes, unless
+ * the environment sets FSC_AUTOTUNE=0 (FSC_AUTOTUNE=1 tunes at any size). */
+int fsc_autotune(fsc_ctx *ctx);
+int fsc_ens_autotune(fsc_ens *ens);
+
+/* out[0..3] = tile x, tile y, prefetch depth, number of workgroups per step. */
+int fsc_get_tiling(const fsc_ctx *ctx, int *out4);
+int fsc_ens_get_tiling(const fsc_ens *ens, int *out4);
+
+/* ----------------------------------------------------------------------- */
+/* Diagnostics.                                                             */
+/* ----------------------------------------------------------------------- */
+
+/* Enqueues a plain device-to-device copy of `bytes` (a positive multiple of
+ * 16) on `stream` with 16-byte accesses: the practical HBM read+write ceiling
+ * that the step kernel's bandwidth is compared with, and the calibration of
+ * the memory-traffic counters.  Asynchronous. */
+int fsc_copy(const void *dev_src, void *dev_dst, int64_t bytes, void *stream);
 
 /* ----------------------------------------------------------------------- */
 /* Generator checks.                                                        */

@@ -266,3 +266,22 @@ def sk_sample(rho: np.ndarray):
                np.bincount(b, weights=v * v, minlength=n_rad),
                np.bincount(b, minlength=n_rad).astype(np.int64))
     return dict(axis=(a_sum, a_sq, a_cnt), radial=rad)
+
+
+def domain_length(rho: np.ndarray) -> float:
+    """L = 2 pi sum_k P(k) / sum_k |k| P(k) over k != 0 (|k| exact per mode):
+    the inverse first moment of the structure factor, used as the domain size
+    of a phase-separating field."""
+    rho = np.asarray(rho, dtype=np.float64)
+    P = np.abs(np.fft.fftn(rho - rho.mean())) ** 2 / rho.size
+    ks = np.meshgrid(*[2 * np.pi * np.fft.fftfreq(s) for s in rho.shape], indexing="ij")
+    kabs = np.sqrt(sum(k * k for k in ks))
+    mask = kabs > 0
+    return float(2 * np.pi * P[mask].sum() / (kabs[mask] * P[mask]).sum())
+
+
+def shell_means(rho: np.ndarray) -> np.ndarray:
+    """Mean of P(k) over each radial shell b = round(|m|) (equal sides only)."""
+    s = sk_sample(rho)["radial"]
+    tot, _, cnt = s
+    return np.where(cnt > 0, tot / np.maximum(cnt, 1), 0.0)

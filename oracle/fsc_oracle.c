@@ -276,34 +276,46 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 /* and uncorrelated in space and time; the generator is this build's        */
 /* choice and is stated exactly so that two independent implementations can */
 /* agree on it:                                                             */
-/*   key     = (seed low 32 bits, replica)                                  */
-/*   counter = (node, step low 32 bits, block, seed high 32 bits)           */
-/*   u(r)    = (floor(r / 2^9) + 1/2) / 2^23, in (0, 1)                     */
-/*   pair (u_a, u_b) -> sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b)        */
-/* Block b supplies the pairs (r0, r1) and (r2, r3); normals k = 0, 1, ...   */
-/* go to the non-conserved moments a = D+1, D+2, ... in basis order.        */
+/*   words w_0, w_1, ... : Philox4x32-10 outputs of blocks 0, 1, ..., with   */
+/*     key (seed low 32 bits, replica),                                     */
+/*     counter (node, step low 32 bits, block, seed high 32 bits);          */
+/*   pair k uses the radius uniform u_a = (floor(w_k / 2^9) + 1/2) / 2^23    */
+/*     and the angle uniform u_b = (h_k + 1/2) / 2^16 of a 16-bit field h_k: */
+/*     D2Q9 (3 pairs, block 0):  h_0 = high half of w_3, h_1 = low half of   */
+/*       w_3, h_2 = (low byte of w_0) * 256 + (low byte of w_1);             */
+/*     D3Q19 (8 pairs, blocks 0-2): h_k = the k-th 16-bit half of w_8..w_11, */
+/*       high half first;                                                   */
+/*   (z_2k, z_2k+1) = sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b);           */
+/* normal m goes to the m-th non-conserved moment (a = D+1+m).              */
 /* ------------------------------------------------------------------------ */
-static double uniform_from_u32(uint32_t r) {
-    return ((double)(r >> 9) + 0.5) / 8388608.0;
-}
-
 void orc_normals(int D, int64_t node, int64_t step, uint64_t seed, uint32_t replica, double *xi) {
     int Q = lattice_q(D);
     int nn = Q - D - 1;
+    int npairs = (nn + 1) / 2;
+    int nblocks = (D == 2) ? 1 : 3;
     uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), replica};
+    uint32_t w[12];
+    for (int blk = 0; blk < nblocks; ++blk) {
+        uint32_t ctr[4] = {(uint32_t)node, (uint32_t)step, (uint32_t)blk, (uint32_t)(seed >> 32)};
+        orc_philox4x32_10(ctr, key, w + 4 * blk);
+    }
     int k = 0;
-    for (uint32_t blk = 0; k < nn; ++blk) {
-        uint32_t ctr[4] = {(uint32_t)node, (uint32_t)step, blk, (uint32_t)(seed >> 32)};
-        uint32_t r[4];
-        orc_philox4x32_10(ctr, key, r);
-        for (int p = 0; p < 2 && k < nn; ++p) {
-            double ua = uniform_from_u32(r[2 * p]);
-            double ub = uniform_from_u32(r[2 * p + 1]);
-            double rad = sqrt(-2.0 * log(ua));
-            double ang = 2.0 * M_PI * ub;
-            xi[k++] = rad * cos(ang);
-            if (k < nn) xi[k++] = rad * sin(ang);
+    for (int p = 0; p < npairs; ++p) {
+        uint32_t h;
+        if (D == 2) {
+            if (p == 0) h = w[3] >> 16;
+            else if (p == 1) h = w[3] & 0xffffu;
+            else h = ((w[0] & 0xffu) << 8) | (w[1] & 0xffu);
+        } else {
+            uint32_t word = w[8 + p / 2];
+            h = (p % 2 == 0) ? (word >> 16) : (word & 0xffffu);
         }
+        double ua = ((double)(w[p] >> 9) + 0.5) / 8388608.0;
+        double ub = ((double)h + 0.5) / 65536.0;
+        double rad = sqrt(-2.0 * log(ua));
+        double ang = 2.0 * M_PI * ub;
+        xi[k++] = rad * cos(ang);
+        if (k < nn) xi[k++] = rad * sin(ang);
     }
 }
 

@@ -1,0 +1,142 @@
+"""FP64 reference of the learned coarse-grained surrogate (test infrastructure).
+
+The surrogate advances the block-averaged density of a phase-separating run
+by a fixed number of lattice steps.  It is not part of the paper; its
+definition (this build's) is:
+
+  x      = (rho - mean) / in_scale                          input normalisation
+  a_0    = SiLU(conv(x; W_0, b_0))                          1 -> C channels
+  a_l    = SiLU(conv(a_{l-1}; W_l, b_l)),  l = 1 .. L-2     C -> C
+  y      = conv(a_{L-2}; W_{L-1}, b_{L-1})                  C -> 1
+  yhat   = y - <y>_image                                    mean-free increment
+  rho'   = rho + out_scale * yhat                           conserves the mean
+
+conv is a 3x3 cross-correlation with circular padding (the lattice is
+periodic); SiLU(z) = z / (1 + exp(-z)).  Training loss: mean over pixels and
+batch of (yhat - (target - rho) / out_scale)^2.
+
+Parameters are one flat float vector, per layer: weights [C_out][C_in][3][3]
+then biases [C_out].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def layer_shapes(channels: int, layers: int):
+    shapes = []
+    for l in range(layers):
+        ci = 1 if l == 0 else channels
+        co = 1 if l == layers - 1 else channels
+        shapes.append((co, ci))
+    return shapes
+
+
+def n_params(channels: int, layers: int) -> int:
+    return sum(co * ci * 9 + co for co, ci in layer_shapes(channels, layers))
+
+
+def unpack(params: np.ndarray, channels: int, layers: int):
+    out = []
+    o = 0
+    for co, ci in layer_shapes(channels, layers):
+        W = params[o:o + co * ci * 9].reshape(co, ci, 3, 3)
+        o += co * ci * 9
+        b = params[o:o + co]
+        o += co
+        out.append((W, b))
+    return out
+
+
+def conv3x3(x: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """out[n, o, y, x] = b[o] + sum_{c, ky, kx} W[o, c, ky, kx] x[n, c, y+ky-1, x+kx-1] (periodic)."""
+    out = np.zeros((x.shape[0], W.shape[0]) + x.shape[2:]) + b[None, :, None, None]
+    for ky in range(3):
+        for kx in range(3):
+            xs = np.roll(x, shift=(1 - ky, 1 - kx), axis=(2, 3))
+            out += np.einsum("oc,ncyx->noyx", W[:, :, ky, kx], xs)
+    return out
+
+
+def conv3x3_input_grad(g: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """Adjoint of conv3x3 with respect to its input."""
+    out = np.zeros((g.shape[0], W.shape[1]) + g.shape[2:])
+    for ky in range(3):
+        for kx in range(3):
+            t = np.einsum("oc,noyx->ncyx", W[:, :, ky, kx], g)
+            out += np.roll(t, shift=(ky - 1, kx - 1), axis=(2, 3))
+    return out
+
+
+def conv3x3_weight_grad(g: np.ndarray, x: np.ndarray):
+    dW = np.zeros((g.shape[1], x.shape[1], 3, 3))
+    for ky in range(3):
+        for kx in range(3):
+            xs = np.roll(x, shift=(1 - ky, 1 - kx), axis=(2, 3))
+            dW[:, :, ky, kx] = np.einsum("noyx,ncyx->oc", g, xs)
+    return dW, g.sum(axis=(0, 2, 3))
+
+
+def silu(z):
+    return z / (1.0 + np.exp(-z))
+
+
+def dsilu(z):
+    s = 1.0 / (1.0 + np.exp(-z))
+    return s * (1.0 + z * (1.0 - s))
+
+
+def forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=False):
+    """rho: [B, H, W] -> prediction [B, H, W] (and the intermediates)."""
+    P = unpack(np.asarray(params, dtype=np.float64), channels, layers)
+    x = ((np.asarray(rho, dtype=np.float64) - mean) / in_scale)[:, None]
+    zs, acts = [], [x]
+    a = x
+    for l, (W, b) in enumerate(P):
+        z = conv3x3(a, W, b)
+        if l < layers - 1:
+            zs.append(z)
+            a = silu(z)
+            acts.append(a)
+        else:
+            y = z[:, 0]
+    yhat = y - y.mean(axis=(1, 2), keepdims=True)
+    pred = rho + out_scale * yhat
+    if keep:
+        return pred, dict(zs=zs, acts=acts, yhat=yhat, P=P)
+    return pred
+
+
+def loss_and_grad(params, rho, target, channels, layers, mean, in_scale, out_scale):
+    rho = np.asarray(rho, dtype=np.float64)
+    _, c = forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=True)
+    r = (np.asarray(target, dtype=np.float64) - rho) / out_scale
+    e = c["yhat"] - r
+    M = e.size
+    loss = float((e * e).mean())
+    g = 2.0 * e / M
+    g = g - g.mean(axis=(1, 2), keepdims=True)  # through the mean-free projection
+    grads = []
+    delta = g[:, None]
+    P = c["P"]
+    for l in range(layers - 1, -1, -1):
+        W, _ = P[l]
+        dW, db = conv3x3_weight_grad(delta, c["acts"][l])
+        grads.append((dW, db))
+        if l > 0:
+            delta = conv3x3_input_grad(delta, W) * dsilu(c["zs"][l - 1])
+    grads.reverse()
+    flat = np.concatenate([np.concatenate([dW.ravel(), db]) for dW, db in grads])
+    return loss, flat
+
+
+def init_params(channels: int, layers: int, seed: int) -> np.ndarray:
+    """He-style uniform initialisation (the library's own initialiser is
+    separate; tests pass parameters explicitly)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for co, ci in layer_shapes(channels, layers):
+        bound = np.sqrt(6.0 / (ci * 9))
+        out.append(rng.uniform(-bound, bound, size=co * ci * 9))
+        out.append(np.zeros(co))
+    return np.concatenate(out)

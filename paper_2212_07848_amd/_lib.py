@@ -28,11 +28,13 @@ EXPORTS = [
     "fsc_create", "fsc_create_external", "fsc_destroy", "fsc_last_error", "fsc_strerror",
     "fsc_get_params", "fsc_init_uniform", "fsc_set_populations", "fsc_get_populations",
     "fsc_step", "fsc_run", "fsc_get_step", "fsc_density", "fsc_stats", "fsc_sk_reset",
-    "fsc_measure_sk", "fsc_sk_nbins", "fsc_read_sk",
+    "fsc_measure_sk", "fsc_sk_nbins", "fsc_read_sk", "fsc_series_enable", "fsc_read_series",
     "fsc_ens_create", "fsc_ens_destroy", "fsc_ens_last_error", "fsc_ens_init_uniform",
     "fsc_ens_run", "fsc_ens_get_step", "fsc_ens_get_populations", "fsc_ens_set_populations",
     "fsc_ens_stats", "fsc_ens_sk_nbins", "fsc_ens_read_sk", "fsc_ens_sk_reset",
-    "fsc_philox", "fsc_normals",
+    "fsc_ens_series_enable", "fsc_ens_read_series",
+    "fsc_autotune", "fsc_ens_autotune", "fsc_get_tiling", "fsc_ens_get_tiling",
+    "fsc_copy", "fsc_philox", "fsc_normals",
 ]
 
 
@@ -93,6 +95,11 @@ def lib():
         "fsc_measure_sk": ([vp], C.c_int),
         "fsc_sk_nbins": ([vp, C.c_int, C.POINTER(C.c_int)], C.c_int),
         "fsc_read_sk": ([vp, C.c_int, dp, dp, i64p, C.c_int], C.c_int),
+        "fsc_series_enable": ([vp, C.c_int], C.c_int),
+        "fsc_read_series": ([vp, dp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "fsc_ens_series_enable": ([vp, C.c_int], C.c_int),
+        "fsc_ens_read_series": ([vp, C.c_int, dp, C.c_int, C.POINTER(C.c_int),
+                                 C.POINTER(C.c_int)], C.c_int),
         "fsc_ens_create": ([pp, C.c_int, vp, C.POINTER(vp)], C.c_int),
         "fsc_ens_destroy": ([vp], C.c_int),
         "fsc_ens_last_error": ([vp], C.c_char_p),
@@ -105,6 +112,11 @@ def lib():
         "fsc_ens_sk_nbins": ([vp, C.c_int, C.c_int, C.POINTER(C.c_int)], C.c_int),
         "fsc_ens_read_sk": ([vp, C.c_int, C.c_int, dp, dp, i64p, C.c_int], C.c_int),
         "fsc_ens_sk_reset": ([vp], C.c_int),
+        "fsc_autotune": ([vp], C.c_int),
+        "fsc_ens_autotune": ([vp], C.c_int),
+        "fsc_get_tiling": ([vp, C.POINTER(C.c_int)], C.c_int),
+        "fsc_ens_get_tiling": ([vp, C.POINTER(C.c_int)], C.c_int),
+        "fsc_copy": ([vp, vp, C.c_int64, vp], C.c_int),
         "fsc_philox": ([u32p, u32p, u32p, C.c_int64], C.c_int),
         "fsc_normals": ([C.c_int, C.c_int, C.c_uint64, C.c_uint32, i64p, i64p, C.c_int64, dp],
                         C.c_int),
@@ -188,6 +200,15 @@ class Lattice:
     def init_uniform(self):
         self._c(lib().fsc_init_uniform(self._h))
 
+    def autotune(self):
+        self._c(lib().fsc_autotune(self._h))
+
+    @property
+    def tiling(self):
+        out = (C.c_int * 4)()
+        self._c(lib().fsc_get_tiling(self._h, out))
+        return dict(tx=out[0], ty=out[1], pf=out[2], blocks=out[3])
+
     def set_populations(self, f: np.ndarray, step: int = 0):
         f = np.ascontiguousarray(f, dtype=np.float64)
         assert f.shape == (self.Q,) + self.shape
@@ -230,6 +251,14 @@ class Lattice:
     def measure_sk(self):
         self._c(lib().fsc_measure_sk(self._h))
 
+    def series_enable(self, capacity: int):
+        self._c(lib().fsc_series_enable(self._h, int(capacity)))
+
+    def read_series(self):
+        rc, rows = _read_series(lib().fsc_read_series, self._h)
+        self._c(rc)
+        return _series_dict(rows)
+
     def read_sk(self, kind=FSC_SK_AXIS):
         nb = C.c_int()
         self._c(lib().fsc_sk_nbins(self._h, kind, C.byref(nb)))
@@ -240,6 +269,21 @@ class Lattice:
         if kind == FSC_SK_AXIS:
             s, q, c = (v.reshape(self.D, -1) for v in (s, q, c))
         return s, q, c
+
+
+def _read_series(fn, *args):
+    n, ln = C.c_int(), C.c_int()
+    rc = fn(*args, None, 0, C.byref(n), C.byref(ln))
+    if rc != 0:
+        return rc, None
+    out = np.zeros((max(n.value, 0), ln.value))
+    if n.value:
+        rc = fn(*args, _dp(out), n.value, C.byref(n), C.byref(ln))
+    return rc, out
+
+
+def _series_dict(rows):
+    return dict(step=rows[:, 0].astype(np.int64), L=rows[:, 1], S=rows[:, 2:])
 
 
 class Ensemble:
@@ -275,6 +319,15 @@ class Ensemble:
     def init_uniform(self):
         self._c(lib().fsc_ens_init_uniform(self._h))
 
+    def autotune(self):
+        self._c(lib().fsc_ens_autotune(self._h))
+
+    @property
+    def tiling(self):
+        out = (C.c_int * 4)()
+        self._c(lib().fsc_ens_get_tiling(self._h, out))
+        return dict(tx=out[0], ty=out[1], pf=out[2], blocks=out[3])
+
     def run(self, n: int, sk_every: int = 0):
         self._c(lib().fsc_ens_run(self._h, int(n), int(sk_every)))
 
@@ -303,6 +356,14 @@ class Ensemble:
     def sk_reset(self):
         self._c(lib().fsc_ens_sk_reset(self._h))
 
+    def series_enable(self, capacity: int):
+        self._c(lib().fsc_ens_series_enable(self._h, int(capacity)))
+
+    def read_series(self, r: int):
+        rc, rows = _read_series(lib().fsc_ens_read_series, self._h, r)
+        self._c(rc)
+        return _series_dict(rows)
+
     def read_sk(self, r: int, kind=FSC_SK_AXIS):
         nb = C.c_int()
         self._c(lib().fsc_ens_sk_nbins(self._h, r, kind, C.byref(nb)))
@@ -314,6 +375,12 @@ class Ensemble:
             D = self.plist[r].D
             s, q, c = (v.reshape(D, -1) for v in (s, q, c))
         return s, q, c
+
+
+def device_copy(src_ptr: int, dst_ptr: int, nbytes: int, stream=None):
+    """Plain device copy (diagnostic; asynchronous on `stream`)."""
+    _check(lib().fsc_copy(C.c_void_p(src_ptr), C.c_void_p(dst_ptr), int(nbytes),
+                          _stream_handle(stream)))
 
 
 def philox(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:

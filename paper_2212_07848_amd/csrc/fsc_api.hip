@@ -3,7 +3,9 @@
 // per-node work is done by the kernels of fsc_step.hip / fsc_measure.hip.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <map>
 #include <string>
 #include <vector>
@@ -53,6 +55,10 @@ struct Rep {
     void *cbuf = nullptr, *ctmp = nullptr;
     void *tw[3] = {nullptr, nullptr, nullptr};
     double *d_stats = nullptr, *d_partials = nullptr;
+    // time series of samples: rows (step, L, per-shell mean S) -- see fsc_series_enable
+    double *d_mom = nullptr, *d_series = nullptr;
+    int *d_series_n = nullptr;
+    int series_cap = 0;
     Geometry geom() const { return Geometry{p.D, p.nx, p.ny, p.nz, N}; }
 };
 
@@ -69,7 +75,9 @@ struct fsc_ens {
     bool own_stream = false;
     int D = 2, stencil = 4, precision = 0;
     bool noise = false;
-    TileShape tile{128, 1};
+    TileShape tile{128, 1, 2};
+    int64_t target_blocks = 2048;  // marching length is chosen to give about this many blocks
+    int autotune = -1;             // -1: automatic for large lattices, 0: off, 1: done
     std::vector<RepDesc> desc;
     RepDesc *d_desc = nullptr;
     int *d_tile_begin = nullptr;
@@ -129,7 +137,9 @@ int resolve_params(const fsc_params &in, fsc_params &out, std::string &err) {
         out.T_hat = in.G != 0.0 ? std::exp(2.0) * CS2 / in.G : INFINITY;
     }
     const int64_t N = int64_t(in.nx) * in.ny * in.nz;
-    if (N * q_of(in.D) >= (int64_t(1) << 31)) return err = "lattice too large", FSC_E_INVAL;
+    // kernels address a population buffer with 32-bit byte offsets
+    const int64_t esz = in.precision == FSC_FP64 ? 8 : 4;
+    if (N * q_of(in.D) * esz >= (int64_t(1) << 32) - 1) return err = "lattice too large", FSC_E_INVAL;
     return FSC_OK;
 }
 
@@ -191,12 +201,16 @@ int init_rep(Rep &r, const fsc_params &p, void *ext_a, void *ext_b, fsc_ens *e) 
     }
     const size_t nsk = 2 * size_t(D) * r.n_axis + 2 * size_t(r.n_rad);
     if (hipMalloc(&r.d_sk, sizeof(double) * nsk) != hipSuccess ||
+        hipMalloc(&r.d_mom, sizeof(double) * 2) != hipSuccess ||
+        hipMalloc(&r.d_series_n, sizeof(int)) != hipSuccess ||
         hipMalloc(&r.d_stats, sizeof(double) * 8) != hipSuccess ||
         hipMalloc(&r.d_partials, sizeof(double) * stats_partials_len()) != hipSuccess) {
         (void)hipGetLastError();
         return fail(e, FSC_E_OOM, "accumulator allocation failed");
     }
     HIPCHK(e, hipMemsetAsync(r.d_sk, 0, sizeof(double) * nsk, e->stream));
+    HIPCHK(e, hipMemsetAsync(r.d_mom, 0, sizeof(double) * 2, e->stream));
+    HIPCHK(e, hipMemsetAsync(r.d_series_n, 0, sizeof(int), e->stream));
     return FSC_OK;
 }
 
@@ -219,8 +233,9 @@ int ensure_fft(Rep &r, fsc_ens *e) {
     return FSC_OK;
 }
 
-// enqueues one S(k) sample of replica r from buffer `par`
-int enqueue_measure(Rep &r, int par, fsc_ens *e) {
+// enqueues one S(k) sample of replica r from buffer `par`; the sampled state
+// is `step_off` steps past the device step counter
+int enqueue_measure(Rep &r, int par, fsc_ens *e, uint32_t step_off) {
     const Geometry g = r.geom();
     HIPCHK(e, launch_density_complex(g, r.p.precision, r.buf[par], r.cbuf, e->stream));
     void *a = r.cbuf, *b = r.ctmp;
@@ -246,7 +261,58 @@ int enqueue_measure(Rep &r, int par, fsc_ens *e) {
     t.rad_sq = r.n_rad ? r.d_sk + 2 * na + r.n_rad : nullptr;
     t.n_axis = r.n_axis;
     t.n_rad = r.n_rad;
+    const bool ser = r.series_cap > 0;
+    t.mom = ser ? r.d_mom : nullptr;
+    t.series = ser ? r.d_series : nullptr;
+    t.series_n = r.d_series_n;
+    t.series_cap = r.series_cap;
     HIPCHK(e, launch_bin(g, r.p.precision, a, t, e->stream));
+    if (ser)
+        HIPCHK(e, launch_series_finalize(r.d_mom, r.d_series, r.d_series_n, r.series_cap,
+                                         2 + r.n_rad, e->d_step, step_off, e->stream));
+    return FSC_OK;
+}
+
+int series_enable(fsc_ens *e, Rep &r, int cap) {
+    (void)hipStreamSynchronize(e->stream);
+    if (r.d_series) {
+        (void)hipFree(r.d_series);
+        r.d_series = nullptr;
+    }
+    r.series_cap = 0;
+    if (cap > 0) {
+        const size_t bytes = sizeof(double) * size_t(cap) * size_t(2 + r.n_rad);
+        if (hipMalloc(&r.d_series, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(e, FSC_E_OOM, "series allocation failed");
+        }
+        HIPCHK(e, hipMemsetAsync(r.d_series, 0, bytes, e->stream));
+        r.series_cap = cap;
+    }
+    HIPCHK(e, hipMemsetAsync(r.d_series_n, 0, sizeof(int), e->stream));
+    HIPCHK(e, hipMemsetAsync(r.d_mom, 0, sizeof(double) * 2, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    return FSC_OK;
+}
+
+int series_read(fsc_ens *e, Rep &r, double *out, int max_rows, int *nrows, int *row_len) {
+    const int len = 2 + r.n_rad;
+    if (row_len) *row_len = len;
+    int n = 0;
+    HIPCHK(e, hipMemcpyAsync(&n, r.d_series_n, sizeof(int), hipMemcpyDeviceToHost, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    n = std::min(n, r.series_cap);
+    if (nrows) *nrows = n;
+    if (!out || max_rows <= 0 || n == 0) return FSC_OK;
+    const int m = std::min(n, max_rows);
+    HIPCHK(e, hipMemcpyAsync(out, r.d_series, sizeof(double) * size_t(m) * len,
+                             hipMemcpyDeviceToHost, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    for (int row = 0; row < m; ++row)
+        for (int b = 0; b < r.n_rad; ++b)
+            out[size_t(row) * len + 2 + b] =
+                r.rad_modes[b] ? out[size_t(row) * len + 2 + b] / double(r.rad_modes[b]) : 0.0;
+    if (nrows) *nrows = m;
     return FSC_OK;
 }
 
@@ -264,8 +330,7 @@ void build_desc(fsc_ens *e) {
     }
     // marching length: enough blocks to fill 256 CUs several times over,
     // but long marches so that the 2R halo planes stay a small overhead
-    const int64_t target_blocks = 2048;
-    int H = int(std::min<int64_t>(256, std::max<int64_t>(16, work / target_blocks)));
+    int H = int(std::min<int64_t>(256, std::max<int64_t>(16, work / e->target_blocks)));
     int tile_begin = 0;
     for (auto &r : e->reps) {
         RepDesc d{};
@@ -347,26 +412,31 @@ void drop_graphs(fsc_ens *e) {
     e->graphs.clear();
 }
 
+StepLaunch make_launch(fsc_ens *e, int parity, uint32_t off) {
+    StepLaunch L;
+    L.reps = e->d_desc;
+    L.tile_begin = e->d_tile_begin;
+    L.nrep = int(e->reps.size());
+    L.total_tiles = e->total_tiles;
+    L.parity = parity;
+    L.step_base = e->d_step;
+    L.step_off = off;
+    L.D = e->D;
+    L.stencil = e->stencil;
+    L.precision = e->precision;
+    L.noise = e->noise;
+    L.tile = e->tile;
+    return L;
+}
+
 int enqueue_steps(fsc_ens *e, int parity, int64_t n, int64_t sk_every, int64_t *samples) {
     for (int64_t k = 0; k < n; ++k) {
-        StepLaunch L;
-        L.reps = e->d_desc;
-        L.tile_begin = e->d_tile_begin;
-        L.nrep = int(e->reps.size());
-        L.total_tiles = e->total_tiles;
-        L.parity = (parity + int(k & 1)) & 1;
-        L.step_base = e->d_step;
-        L.step_off = uint32_t(k);
-        L.D = e->D;
-        L.stencil = e->stencil;
-        L.precision = e->precision;
-        L.noise = e->noise;
-        L.tile = e->tile;
+        const StepLaunch L = make_launch(e, (parity + int(k & 1)) & 1, uint32_t(k));
         HIPCHK(e, launch_step(L, e->stream));
         if (sk_every > 0 && (k + 1) % sk_every == 0) {
             const int par = (parity + int((k + 1) & 1)) & 1;
             for (auto &r : e->reps) {
-                int rc = enqueue_measure(r, par, e);
+                int rc = enqueue_measure(r, par, e, uint32_t(k + 1));
                 if (rc) return rc;
             }
             if (samples) ++*samples;
@@ -374,6 +444,82 @@ int enqueue_steps(fsc_ens *e, int parity, int64_t n, int64_t sk_every, int64_t *
     }
     HIPCHK(e, launch_step_advance(e->d_step, uint64_t(n), e->stream));
     return FSC_OK;
+}
+
+// -------------------------------------------------------------------------
+// Autotuner: times every compiled tile shape and marching-length target on the
+// ensemble's own buffers and keeps the fastest.  A step launch only reads the
+// current state and writes the other buffer, which holds nothing needed, and
+// the step counter is not advanced, so tuning leaves the state untouched.
+// The per-node arithmetic does not depend on the tiling, so neither do results.
+// -------------------------------------------------------------------------
+struct TuneChoice {
+    TileShape tile;
+    int64_t target;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune_cache;
+
+std::string tune_key(const fsc_ens *e) {
+    std::string k = std::to_string(e->D) + "/" + std::to_string(e->stencil) + "/" +
+                    std::to_string(e->precision) + "/" + std::to_string(int(e->noise));
+    for (const auto &r : e->reps)
+        k += ":" + std::to_string(r.p.nx) + "x" + std::to_string(r.p.ny) + "x" + std::to_string(r.p.nz);
+    return k;
+}
+
+int ens_autotune(fsc_ens *e) {
+    const std::string key = tune_key(e);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            e->tile = it->second.tile;
+            e->target_blocks = it->second.target;
+            drop_graphs(e);
+            e->autotune = 1;
+            return upload_desc(e);
+        }
+    }
+    TileShape shapes[8];
+    const int nshape = tile_shapes(e->D, e->stencil, e->precision, shapes, 8);
+    const int64_t targets[3] = {1024, 2048, 4096};
+    hipEvent_t a, b;
+    HIPCHK(e, hipEventCreate(&a));
+    HIPCHK(e, hipEventCreate(&b));
+    float best = 1e30f;
+    TuneChoice choice{e->tile, e->target_blocks};
+    const int parity = int(e->step & 1);
+    for (int si = 0; si < nshape; ++si)
+        for (int64_t tg : targets) {
+            e->tile = shapes[si];
+            e->target_blocks = tg;
+            int rc = upload_desc(e);
+            if (rc) return rc;
+            const StepLaunch L = make_launch(e, parity, 0);
+            for (int k = 0; k < 2; ++k) HIPCHK(e, launch_step(L, e->stream));
+            HIPCHK(e, hipEventRecord(a, e->stream));
+            for (int k = 0; k < 8; ++k) HIPCHK(e, launch_step(L, e->stream));
+            HIPCHK(e, hipEventRecord(b, e->stream));
+            HIPCHK(e, hipEventSynchronize(b));
+            float ms = 0.f;
+            HIPCHK(e, hipEventElapsedTime(&ms, a, b));
+            if (ms < best) {
+                best = ms;
+                choice = TuneChoice{shapes[si], tg};
+            }
+        }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    e->tile = choice.tile;
+    e->target_blocks = choice.target;
+    drop_graphs(e);
+    e->autotune = 1;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[key] = choice;
+    }
+    return upload_desc(e);
 }
 
 int ens_run(fsc_ens *e, int64_t nsteps, int64_t sk_every) {
@@ -385,6 +531,16 @@ int ens_run(fsc_ens *e, int64_t nsteps, int64_t sk_every) {
             int rc = ensure_fft(r, e);
             if (rc) return rc;
         }
+    if (e->autotune < 0) {
+        int64_t nodes = 0;
+        for (const auto &r : e->reps) nodes += r.N;
+        if (e->autotune == -2 || nodes >= (int64_t(1) << 20)) {
+            int rc = ens_autotune(e);
+            if (rc) return rc;
+        } else {
+            e->autotune = 0;
+        }
+    }
     // whole chunks as graph replays
     int64_t chunk = sk_every > 0 ? sk_every : 64;
     if (chunk & 1) chunk *= 2;
@@ -457,9 +613,10 @@ int ens_create(const fsc_params *ps, int nrep, void *stream, void *ext_a, void *
     e->D = rp[0].D;
     e->stencil = rp[0].stencil;
     e->precision = rp[0].precision;
-    TileShape shapes[4];
-    tile_shapes(e->D, e->stencil, shapes, 4);
+    TileShape shapes[8];
+    tile_shapes(e->D, e->stencil, e->precision, shapes, 8);
     e->tile = shapes[0];
+    if (const char *env = std::getenv("FSC_AUTOTUNE")) e->autotune = std::atoi(env) ? -2 : 0;
     e->reps.resize(nrep);
     for (int k = 0; k < nrep; ++k) {
         e->noise = e->noise || rp[k].kBT > 0.0;
@@ -490,7 +647,8 @@ void ens_free(fsc_ens *e) {
             if (r.buf[0]) (void)hipFree(r.buf[0]);
             if (r.buf[1]) (void)hipFree(r.buf[1]);
         }
-        void *ptrs[] = {r.d_sk, r.cbuf, r.ctmp, r.tw[0], r.tw[1], r.tw[2], r.d_stats, r.d_partials};
+        void *ptrs[] = {r.d_sk,     r.cbuf,       r.ctmp,  r.tw[0],     r.tw[1],     r.tw[2],
+                        r.d_stats,  r.d_partials, r.d_mom, r.d_series, r.d_series_n};
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
     }
@@ -739,7 +897,7 @@ int fsc_measure_sk(fsc_ctx *ctx) {
     Rep &r = e->reps[0];
     int rc = ensure_fft(r, e);
     if (rc) return rc;
-    rc = enqueue_measure(r, int(e->step & 1), e);
+    rc = enqueue_measure(r, int(e->step & 1), e, 0);
     if (rc) return rc;
     r.nsamples += 1;
     return FSC_OK;
@@ -802,6 +960,54 @@ int fsc_ens_read_sk(fsc_ens *ens, int replica, int kind, double *sum, double *su
     return rc ? rc : ens_read_sk(ens, replica, kind, sum, sumsq, count, nbins);
 }
 int fsc_ens_sk_reset(fsc_ens *ens) { return ens ? ens_sk_reset(ens) : FSC_E_INVAL; }
+
+// ---- time series ----------------------------------------------------------
+int fsc_series_enable(fsc_ctx *ctx, int capacity) {
+    if (!ctx || capacity < 0) return FSC_E_INVAL;
+    drop_graphs(ctx->e);
+    return series_enable(ctx->e, ctx->e->reps[0], capacity);
+}
+int fsc_read_series(fsc_ctx *ctx, double *out, int max_rows, int *nrows, int *row_len) {
+    if (!ctx) return FSC_E_INVAL;
+    return series_read(ctx->e, ctx->e->reps[0], out, max_rows, nrows, row_len);
+}
+int fsc_ens_series_enable(fsc_ens *ens, int capacity) {
+    if (!ens || capacity < 0) return FSC_E_INVAL;
+    drop_graphs(ens);
+    for (auto &r : ens->reps) {
+        int rc = series_enable(ens, r, capacity);
+        if (rc) return rc;
+    }
+    return FSC_OK;
+}
+int fsc_ens_read_series(fsc_ens *ens, int replica, double *out, int max_rows, int *nrows,
+                        int *row_len) {
+    if (!ens) return FSC_E_INVAL;
+    int rc = rep_index(ens, replica);
+    return rc ? rc : series_read(ens, ens->reps[replica], out, max_rows, nrows, row_len);
+}
+
+// ---- tiling ---------------------------------------------------------------
+int fsc_autotune(fsc_ctx *ctx) { return ctx ? ens_autotune(ctx->e) : FSC_E_INVAL; }
+int fsc_ens_autotune(fsc_ens *ens) { return ens ? ens_autotune(ens) : FSC_E_INVAL; }
+static int get_tiling(const fsc_ens *e, int *out4) {
+    if (!out4) return FSC_E_INVAL;
+    out4[0] = e->tile.tx;
+    out4[1] = e->tile.ty;
+    out4[2] = e->tile.pf;
+    out4[3] = e->total_tiles;
+    return FSC_OK;
+}
+int fsc_get_tiling(const fsc_ctx *ctx, int *out4) { return ctx ? get_tiling(ctx->e, out4) : FSC_E_INVAL; }
+int fsc_ens_get_tiling(const fsc_ens *ens, int *out4) { return ens ? get_tiling(ens, out4) : FSC_E_INVAL; }
+
+// ---- diagnostics ----------------------------------------------------------
+int fsc_copy(const void *dev_src, void *dev_dst, int64_t bytes, void *stream) {
+    if (!dev_src || !dev_dst || bytes <= 0 || (bytes & 15)) return FSC_E_INVAL;
+    return launch_copy(dev_src, dev_dst, bytes, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? FSC_OK
+               : FSC_E_HIP;
+}
 
 // ---- generator checks ---------------------------------------------------
 int fsc_philox(const uint32_t *host_ctr, const uint32_t *host_key, uint32_t *host_out, int64_t n) {

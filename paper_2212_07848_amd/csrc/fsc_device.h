@@ -190,21 +190,33 @@ __host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
     return c;
 }
 
-// Uniform in (0,1): (floor(r / 2^9) + 1/2) 2^-23, i.e. the odd 24-bit integer
-// (r >> 8) | 1 times 2^-24 -- exact in float and double.
-template <typename real>
-__device__ inline real unit_open(uint32_t r) {
-    return real((r >> 8) | 1u) * real(5.9604644775390625e-08);
-}
-
-__device__ inline void box_muller(float ua, float ub, float &z0, float &z1) {
+// Noise normals of one node.  The paper fixes only that the thermal noise is
+// Gaussian and uncorrelated in space and time; the bit layout below is this
+// library's definition (the oracle implements the same one):
+//   words w_0, w_1, ... = Philox4x32-10 outputs of blocks 0, 1, ... with
+//     counter (node, step, block, seed >> 32), key (seed & 0xffffffff, replica);
+//   pair k takes a radius uniform u_a = (floor(w_k / 2^9) + 1/2) 2^-23 and an
+//     angle uniform u_b = (h_k + 1/2) 2^-16 from a 16-bit field h_k:
+//       D2Q9  (3 pairs, 1 block):  h_0 = w_3 >> 16, h_1 = w_3 & 0xffff,
+//                                  h_2 = (w_0 & 0xff) << 8 | (w_1 & 0xff)
+//       D3Q19 (8 pairs, 3 blocks): h_k = 16-bit half k of w_8 .. w_11
+//                                  (high half first)
+//   (z_2k, z_2k+1) = sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b); normal k goes
+//   to the k-th non-conserved moment.  Both uniforms are exact in float.
+__device__ __forceinline__ void box_muller(float ua, float ub, float &z0, float &z1) {
+#ifdef FSC_ACCURATE_BOX_MULLER
     const float rad = sqrtf(-2.0f * logf(ua));
     float s, c;
     sincospif(2.0f * ub, &s, &c);
+#else
+    // hardware log2, sqrt and sin/cos (argument in revolutions)
+    const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ua));
+    const float s = __builtin_amdgcn_sinf(ub), c = __builtin_amdgcn_cosf(ub);
+#endif
     z0 = rad * c;
     z1 = rad * s;
 }
-__device__ inline void box_muller(double ua, double ub, double &z0, double &z1) {
+__device__ __forceinline__ void box_muller(double ua, double ub, double &z0, double &z1) {
     const double rad = sqrt(-2.0 * log(ua));
     double s, c;
     sincospi(2.0 * ub, &s, &c);
@@ -212,25 +224,34 @@ __device__ inline void box_muller(double ua, double ub, double &z0, double &z1) 
     z1 = rad * s;
 }
 
-// The NN normals of node `node` at step `step`: pairs (r0,r1), (r2,r3) of
-// Philox blocks 0, 1, ... with counter (node, step, block, seed_hi).
-template <int NN, typename real>
-__device__ inline void node_normals(uint32_t node, uint32_t step, uint32_t seed_hi, uint32_t k0,
-                                    uint32_t k1, real (&z)[NN]) {
+template <class L, typename real>
+__device__ __forceinline__ void node_normals(uint32_t node, uint32_t step, uint32_t seed_hi,
+                                             uint32_t k0, uint32_t k1, real (&z)[L::NNORM]) {
+    constexpr int NN = L::NNORM;
+    constexpr int P = (NN + 1) / 2;
+    constexpr int NB = L::D == 2 ? 1 : 3;
+    uint32_t w[4 * NB];
 #pragma unroll
-    for (int blk = 0; blk < (NN + 3) / 4; ++blk) {
-        const U4 r = philox4x32_10(U4{node, step, uint32_t(blk), seed_hi}, k0, k1);
-        const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
+    for (int b = 0; b < NB; ++b) {
+        const U4 r = philox4x32_10(U4{node, step, uint32_t(b), seed_hi}, k0, k1);
+        w[4 * b] = r.x;
+        w[4 * b + 1] = r.y;
+        w[4 * b + 2] = r.z;
+        w[4 * b + 3] = r.w;
+    }
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int k = 4 * blk + 2 * p;
-            if (k < NN) {
-                real z0, z1;
-                box_muller(unit_open<real>(rr[2 * p]), unit_open<real>(rr[2 * p + 1]), z0, z1);
-                z[k] = z0;
-                if (k + 1 < NN) z[k + 1] = z1;
-            }
-        }
+    for (int k = 0; k < P; ++k) {
+        uint32_t h;
+        if (L::D == 2)
+            h = k == 0 ? (w[3] >> 16) : (k == 1 ? (w[3] & 0xffffu) : (((w[0] & 0xffu) << 8) | (w[1] & 0xffu)));
+        else
+            h = (k & 1) ? (w[8 + k / 2] & 0xffffu) : (w[8 + k / 2] >> 16);
+        const real ua = real((w[k] >> 8) | 1u) * real(5.9604644775390625e-08);     // (2m+1) 2^-24
+        const real ub = real(2u * h + 1u) * real(7.62939453125e-06);                  // (2h+1) 2^-17
+        real z0, z1;
+        box_muller(ua, ub, z0, z1);
+        z[2 * k] = z0;
+        if (2 * k + 1 < NN) z[2 * k + 1] = z1;
     }
 }
 

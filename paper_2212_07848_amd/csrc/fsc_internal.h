@@ -11,7 +11,7 @@ namespace fsc {
 // Tile shape of the fused step kernel: a TX x TY cross-section (TY = 1 in 2D)
 // marching along the slowest axis.
 struct TileShape {
-    int tx, ty;
+    int tx, ty, pf;  // cross-section tile and register prefetch depth (planes)
 };
 
 // Launch of one step over every replica of an ensemble.
@@ -31,7 +31,7 @@ struct StepLaunch {
 // Returns hipErrorInvalidValue when no instantiation matches.
 hipError_t launch_step(const StepLaunch &L, hipStream_t s);
 // Tile shapes compiled for a lattice/stencil; the first is the default.
-int tile_shapes(int D, int stencil, TileShape *out, int max);
+int tile_shapes(int D, int stencil, int precision, TileShape *out, int max);
 
 // Adds k to the device step counter (one thread).
 hipError_t launch_step_advance(uint64_t *step_base, uint64_t k, hipStream_t s);
@@ -72,9 +72,23 @@ struct BinTargets {
     double *axis_sum, *axis_sq;  // [D][n_axis]
     double *rad_sum, *rad_sq;    // [n_rad] or null
     int n_axis, n_rad;
+    // time series (null when disabled): per-sample sum P and sum |k| P, and
+    // rows [cap][2 + n_rad] = (step, L, per-shell sums of P) at row *series_n
+    double *mom;
+    double *series;
+    const int *series_n;
+    int series_cap;
 };
 hipError_t launch_bin(const Geometry &g, int precision, const void *spec, const BinTargets &t,
                       hipStream_t s);
+// Closes one sample of the time series: row *series_n gets (step, L) with
+// L = 2 pi sum P / sum |k| P, the moments are cleared and the row advances.
+hipError_t launch_series_finalize(double *mom, double *series, int *series_n, int cap,
+                                  int row_len, const uint64_t *step_base, uint32_t step_off,
+                                  hipStream_t s);
+
+// Plain copy of `bytes` (multiple of 16) bytes.
+hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
 
 // Device Philox / normals checks.
 hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n,

@@ -372,11 +372,16 @@ template <typename real>
 __global__ void __launch_bounds__(256) k_bin(Geometry g, const cplx<real> *__restrict__ spec,
                                              BinTargets t, double invN) {
     extern __shared__ double wnd[];  // [2][W]
+    __shared__ double red[2][4];
     const int row = blockIdx.x;
     const int y = row % g.ny, z = row / g.ny;
     const int my = signed_mode(y, g.ny), mz = signed_mode(z, g.nz);
     const int64_t base2 = int64_t(my) * my + int64_t(mz) * mz;
     const bool rad = t.n_rad > 0;
+    const bool ser = t.mom != nullptr;
+    const int srow = ser ? t.series_n[0] : 0;
+    const bool ser_row = ser && t.series != nullptr && srow < t.series_cap;
+    const double ky = 2.0 * M_PI * my / g.ny, kz = 2.0 * M_PI * mz / g.nz;
     int blo = 0, W = 0;
     if (rad) {
         const int half = g.nx / 2;
@@ -385,6 +390,7 @@ __global__ void __launch_bounds__(256) k_bin(Geometry g, const cplx<real> *__res
         for (int k = threadIdx.x; k < 2 * W; k += 256) wnd[k] = 0.0;
         __syncthreads();
     }
+    double sP = 0.0, skP = 0.0;
     for (int x = threadIdx.x; x < g.nx; x += 256) {
         const int mx = signed_mode(x, g.nx);
         const int64_t m2 = base2 + int64_t(mx) * mx;
@@ -403,13 +409,33 @@ __global__ void __launch_bounds__(256) k_bin(Geometry g, const cplx<real> *__res
             atomicAdd(&wnd[b], P);
             atomicAdd(&wnd[W + b], P * P);
         }
+        if (ser) {
+            const double kx = 2.0 * M_PI * mx / g.nx;
+            sP += P;
+            skP += sqrt(kx * kx + ky * ky + kz * kz) * P;
+        }
+    }
+    if (ser) {
+        sP = wave_sum(sP);
+        skP = wave_sum(skP);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        if (lane == 0) {
+            red[0][wv] = sP;
+            red[1][wv] = skP;
+        }
+    }
+    if (rad || ser) __syncthreads();
+    if (ser && threadIdx.x == 0) {
+        unsafeAtomicAdd(&t.mom[0], red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+        unsafeAtomicAdd(&t.mom[1], red[1][0] + red[1][1] + red[1][2] + red[1][3]);
     }
     if (rad) {
-        __syncthreads();
+        double *srow_bins = ser_row ? t.series + size_t(srow) * (2 + t.n_rad) + 2 : nullptr;
         for (int k = threadIdx.x; k < W; k += 256) {
             if (wnd[k] != 0.0 || wnd[W + k] != 0.0) {
                 unsafeAtomicAdd(&t.rad_sum[blo + k], wnd[k]);
                 unsafeAtomicAdd(&t.rad_sq[blo + k], wnd[W + k]);
+                if (srow_bins) unsafeAtomicAdd(&srow_bins[blo + k], wnd[k]);
             }
         }
     }
@@ -427,6 +453,61 @@ hipError_t launch_bin(const Geometry &g, int precision, const void *spec, const 
     else
         hipLaunchKernelGGL(k_bin<double>, dim3(unsigned(rows)), dim3(256), shm, s, g,
                            static_cast<const cplx<double> *>(spec), t, invN);
+    return hipGetLastError();
+}
+
+__global__ void k_series_finalize(double *mom, double *series, int *series_n, int cap,
+                                  int row_len, const uint64_t *step_base, uint32_t step_off) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int row = series_n[0];
+    if (series != nullptr && row < cap) {
+        series[size_t(row) * row_len] = double(step_base[0] + step_off);
+        series[size_t(row) * row_len + 1] = mom[1] > 0.0 ? 2.0 * M_PI * mom[0] / mom[1] : 0.0;
+    }
+    mom[0] = 0.0;
+    mom[1] = 0.0;
+    series_n[0] = row + 1;
+}
+
+hipError_t launch_series_finalize(double *mom, double *series, int *series_n, int cap,
+                                  int row_len, const uint64_t *step_base, uint32_t step_off,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(k_series_finalize, dim3(1), dim3(64), 0, s, mom, series, series_n, cap,
+                       row_len, step_base, step_off);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Plain device copy (16-byte lanes, grid-stride): the practical HBM
+// read+write ceiling and the calibration for the memory-traffic counters.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_copy(const uint4 *__restrict__ src,
+                                              uint4 *__restrict__ dst, int64_t n16) {
+    // each block moves 4 consecutive 4 KiB pieces per iteration: four
+    // independent 16-byte loads per lane are in flight before the stores
+    const int64_t stride = int64_t(gridDim.x) * 1024;
+    for (int64_t base = int64_t(blockIdx.x) * 1024; base < n16; base += stride) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = base + u * 256 + threadIdx.x;
+            if (k < n16) v[u] = src[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = base + u * 256 + threadIdx.x;
+            if (k < n16) dst[k] = v[u];
+        }
+    }
+}
+
+hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t s) {
+    if (bytes <= 0 || (bytes & 15)) return hipErrorInvalidValue;
+    const int64_t n16 = bytes / 16;
+    const int64_t want = (n16 + 1023) / 1024;
+    const unsigned blocks = unsigned(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, static_cast<const uint4 *>(src),
+                       static_cast<uint4 *>(dst), n16);
     return hipGetLastError();
 }
 
@@ -453,14 +534,15 @@ hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out
     return hipGetLastError();
 }
 
-template <int NN, typename real>
+template <class L, typename real>
 __global__ void k_normals(uint64_t seed, uint32_t replica, const int64_t *node,
                           const int64_t *step, int64_t n, double *out) {
+    constexpr int NN = L::NNORM;
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
     real z[NN];
-    node_normals<NN, real>(uint32_t(node[k]), uint32_t(step[k]), uint32_t(seed >> 32),
-                           uint32_t(seed), replica, z);
+    node_normals<L, real>(uint32_t(node[k]), uint32_t(step[k]), uint32_t(seed >> 32),
+                          uint32_t(seed), replica, z);
     for (int q = 0; q < NN; ++q) out[k * NN + q] = double(z[q]);
 }
 
@@ -472,17 +554,17 @@ hipError_t launch_normals(int D, int precision, uint64_t seed, uint32_t replica,
     if (nb == 0) return hipSuccess;
     if (D == 2) {
         if (precision == 0)
-            hipLaunchKernelGGL((k_normals<D2Q9::NNORM, float>), dim3(unsigned(nb)), dim3(256), 0,
+            hipLaunchKernelGGL((k_normals<D2Q9, float>), dim3(unsigned(nb)), dim3(256), 0,
                                s, seed, replica, node, step, n, out);
         else
-            hipLaunchKernelGGL((k_normals<D2Q9::NNORM, double>), dim3(unsigned(nb)), dim3(256), 0,
+            hipLaunchKernelGGL((k_normals<D2Q9, double>), dim3(unsigned(nb)), dim3(256), 0,
                                s, seed, replica, node, step, n, out);
     } else {
         if (precision == 0)
-            hipLaunchKernelGGL((k_normals<D3Q19::NNORM, float>), dim3(unsigned(nb)), dim3(256), 0,
+            hipLaunchKernelGGL((k_normals<D3Q19, float>), dim3(unsigned(nb)), dim3(256), 0,
                                s, seed, replica, node, step, n, out);
         else
-            hipLaunchKernelGGL((k_normals<D3Q19::NNORM, double>), dim3(unsigned(nb)), dim3(256),
+            hipLaunchKernelGGL((k_normals<D3Q19, double>), dim3(unsigned(nb)), dim3(256),
                                0, s, seed, replica, node, step, n, out);
     }
     return hipGetLastError();

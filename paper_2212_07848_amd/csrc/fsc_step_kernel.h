@@ -1,48 +1,242 @@
-// fsc_step_kernel.h -- the fused time step of the fluctuating Shan-Chen lattice
-// Boltzmann equation (Eq. 12 of Lulli et al., arXiv:2212.07848) on gfx950.
+// fsc_step_kernel.h -- the fused time step of the fluctuating Shan-Chen
+// lattice Boltzmann equation (Eq. 12 of Lulli et al., arXiv:2212.07848) on
+// gfx950.
 //
 // One launch advances every replica of an ensemble by one step.  A workgroup
 // owns a TX x TY cross-section tile (TY = 1 in 2D) and marches along the
 // slowest axis (y in 2D, z in 3D) over H planes:
 //
-//   for each plane s of the march:
-//     pull-load f_i(x - c_i) of plane s + R (R = stencil radius) for the tile
-//       and its R-wide cross-section ring, form n, and write
-//       dpsi = psi(n) - psi(n0) = psi0 expm1(dn / (n0 n)) into an LDS ring
-//       buffer of 2R + 2 planes;
+//   for each plane s of the march (upwards in even chunks, downwards in odd):
+//     wait for the pulled populations f_i(x - c_i) of plane s + R (R = stencil
+//       radius, ahead in march direction; loads issued PF planes earlier), form
+//       n and write
+//       dpsi = psi(n) - psi(n0) = psi0 expm1(dn / (n0 n)) for the tile and its
+//       R-wide cross-section ring into an LDS ring buffer of 2R + 2 planes;
+//     issue the loads of plane s + R + PF (software prefetch);
 //     barrier;
-//     for plane s (populations kept in registers since they were loaded):
+//     for plane s (populations held in a register ring since they arrived):
 //       Shan-Chen force of Eq. (1) from the LDS dpsi stencil, summed as
 //         antisymmetric pairs so that a uniform field gives exactly zero;
-//       velocity u = (j + F/2)/n, moment-space collision with Guo forcing
-//         and Philox/Box-Muller noise on the non-conserved moments;
+//       u = (j + F/2)/n, moment-space collision with Guo forcing and
+//         Philox/Box-Muller noise on the non-conserved moments;
 //       back-transform and store f*_i(x) (pull streaming: the next step reads
 //         f*_i(x - c_i)).
 //
 // Populations are stored as deviations df_i = f_i - w_i n0 (float or double),
 // SoA [i][slow][..][x], so that small thermal fluctuations keep their
-// precision and every load/store is a coalesced 64-lane access.  Densities and
-// the pseudopotential never touch HBM: the halo is recomputed from pulled
-// populations (extra reads hit L2), so the algorithmic traffic is one read
-// and one write per population per node.
+// precision and every access is a coalesced wave-wide transaction.  Densities
+// and the pseudopotential never touch HBM: the halo is recomputed from pulled
+// populations (the extra reads hit L2), so the algorithmic traffic is one
+// read and one write per population per node.  Loads and stores use a
+// wave-uniform 64-bit base (SGPR pair) plus a per-lane 32-bit byte offset that
+// is constant along the march, so the addressing costs no vector ALU work.
 #pragma once
 
 #include "fsc_internal.h"
 
 namespace fsc {
 
+// Raw buffer accesses: a buffer resource (base, byte size) in SGPRs, a
+// wave-uniform byte offset in an SGPR and a per-lane byte offset in a VGPR.
+// Out-of-range lanes read 0 and drop writes.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int BUF_DWORD3 = 0x00020000;  // raw 32-bit buffer (gfx9 family)
 
-template <class L, class ST, typename real, bool NOISE, int TX, int TY>
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint64_t bytes) {
+    const int n = bytes >= 0xffffffffull ? int(0xffffffff) : int(uint32_t(bytes));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, n, BUF_DWORD3);
+}
+template <typename T>
+__device__ __forceinline__ T bload(rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float bload<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, double v) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float fexpm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double fexpm1(double x) { return expm1(x); }
+
+// ---------------------------------------------------------------------------
+// D2Q9 collision, written out on the weight-orthogonal basis
+//   1, cx, cy, 3c^2-2, cx^2-cy^2, cxcy, (3c^2-4)cx, (3c^2-4)cy, 9c^4-15c^2+2
+// (norms b = 1, 1/3, 1/3, 4, 4/9, 1/9, 2/3, 2/3, 16).  The equilibrium and
+// Guo-source moments of the second-order rows are rho u.A.u and 2 u.A.F; the
+// kinetic rows have none.  In: pulled deviations f (overwritten by the
+// post-collision deviations), force F, noise normals z (6).
+// ---------------------------------------------------------------------------
+template <typename real, bool NOISE>
+__device__ __forceinline__ void collide_d2q9(real (&f)[9], real rho0, const real F[3],
+                                             const real (&lam)[9], const real (&amp)[9],
+                                             const real (&z)[6]) {
+    const real s13 = f[1] + f[3], d13 = f[1] - f[3];
+    const real s24 = f[2] + f[4], d24 = f[2] - f[4];
+    const real s57 = f[5] + f[7], d57 = f[5] - f[7];
+    const real s68 = f[6] + f[8], d68 = f[6] - f[8];
+    const real Ax = s13 + s24, Dg = s57 + s68;
+    const real dn = f[0] + Ax + Dg;
+    const real u1 = d57 - d68, u2 = d57 + d68;
+    const real jx = d13 + u1, jy = d24 + u2;
+    const real m3 = real(4) * Dg + Ax - real(2) * f[0];
+    const real m4 = s13 - s24;
+    const real m5 = s57 - s68;
+    const real m6 = real(2) * u1 - d13;
+    const real m7 = real(2) * u2 - d24;
+    const real m8 = real(8) * Dg - real(4) * Ax + real(2) * f[0];
+
+    const real rho = rho0 + dn;
+    const real ir = fast_rcp(rho);
+    const real ux = (jx + real(0.5) * F[0]) * ir;
+    const real uy = (jy + real(0.5) * F[1]) * ir;
+    const real uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
+    const real uFx = ux * F[0], uFy = uy * F[1];
+
+    real sr = real(0);
+    if constexpr (NOISE) sr = fsqrt(rho);
+    auto relax = [&](int a, real m, real meq, real src, real zz) {
+        real o = m + lam[a] * (meq - m) + (real(1) - real(0.5) * lam[a]) * src;
+        if constexpr (NOISE) o += amp[a] * sr * zz;
+        return o;
+    };
+    // post-collision moments, each divided by its norm b_a
+    const real n0 = dn;
+    const real n1 = (jx + F[0]) * real(3);
+    const real n2 = (jy + F[1]) * real(3);
+    const real n3 = relax(3, m3, real(3) * rho * (uxx + uyy), real(6) * (uFx + uFy), z[0]) * real(0.25);
+    const real n4 = relax(4, m4, rho * (uxx - uyy), real(2) * (uFx - uFy), z[1]) * real(2.25);
+    const real n5 = relax(5, m5, rho * uxy, ux * F[1] + uy * F[0], z[2]) * real(9);
+    real g6 = (real(1) - lam[6]) * m6, g7 = (real(1) - lam[7]) * m7, g8 = (real(1) - lam[8]) * m8;
+    if constexpr (NOISE) {
+        g6 += amp[6] * sr * z[3];
+        g7 += amp[7] * sr * z[4];
+        g8 += amp[8] * sr * z[5];
+    }
+    const real n6 = g6 * real(1.5), n7 = g7 * real(1.5), n8 = g8 * real(0.0625);
+
+    // back-transform f_i = w_i sum_a M_ai n_a
+    const real w0 = real(4.0 / 9.0), w1 = real(1.0 / 9.0), w5 = real(1.0 / 36.0);
+    f[0] = w0 * (n0 - real(2) * n3 + real(2) * n8);
+    const real ba = n0 + n3 - real(4) * n8;
+    const real ap = ba + n4, am = ba - n4;
+    const real px = n1 - n6, py = n2 - n7;
+    f[1] = w1 * (ap + px);
+    f[3] = w1 * (ap - px);
+    f[2] = w1 * (am + py);
+    f[4] = w1 * (am - py);
+    const real bd = n0 + real(4) * n3 + real(8) * n8;
+    const real bp = bd + n5, bm = bd - n5;
+    const real X = n1 + real(2) * n6, Y = n2 + real(2) * n7;
+    const real XpY = X + Y, XmY = X - Y;
+    f[5] = w5 * (bp + XpY);
+    f[7] = w5 * (bp - XpY);
+    f[6] = w5 * (bm - XmY);
+    f[8] = w5 * (bm + XmY);
+}
+
+// ---------------------------------------------------------------------------
+// Generic collision on the constexpr basis of a lattice (used for D3Q19).
+// ---------------------------------------------------------------------------
+template <class L, typename real, bool NOISE>
+__device__ __forceinline__ void collide_generic(real (&f)[L::Q], real rho0, const real F[3],
+                                                const real (&lam)[L::Q], const real (&amp)[L::Q],
+                                                const real (&z)[L::NNORM]) {
+    constexpr int D = L::D, Q = L::Q;
+    real dn = real(0);
+    real j[3] = {real(0), real(0), real(0)};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        dn += f[i];
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            if (L::c(i, q) == 1) j[q] += f[i];
+            if (L::c(i, q) == -1) j[q] -= f[i];
+        }
+    }
+    const real rho = rho0 + dn;
+    const real ir = fast_rcp(rho);
+    real u[3] = {real(0), real(0), real(0)};
+#pragma unroll
+    for (int q = 0; q < D; ++q) u[q] = (j[q] + real(0.5) * F[q]) * ir;
+    real sr = real(0);
+    if constexpr (NOISE) sr = fsqrt(rho);
+
+    real ms[Q];
+    ms[0] = dn;
+#pragma unroll
+    for (int q = 0; q < D; ++q) ms[1 + q] = j[q] + F[q];
+#pragma unroll
+    for (int a = D + 1; a < Q; ++a) {
+        real m = real(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int c = L::M(a, i);
+            if (c == 1) m += f[i];
+            else if (c == -1) m -= f[i];
+            else if (c != 0) m += real(c) * f[i];
+        }
+        real out;
+        if (L::cls(a) == 3) {
+            out = (real(1) - lam[a]) * m;
+        } else {
+            real uAu = real(0), uAF = real(0);
+#pragma unroll
+            for (int p = 0; p < D; ++p)
+#pragma unroll
+                for (int q = 0; q < D; ++q) {
+                    const double A = L::A(a, p, q);
+                    if (A != 0.0) {
+                        uAu += real(A) * u[p] * u[q];
+                        uAF += real(A) * u[p] * F[q];
+                    }
+                }
+            out = m + lam[a] * (rho * uAu - m) + (real(1) - real(0.5) * lam[a]) * (real(2) * uAF);
+        }
+        if constexpr (NOISE) out += amp[a] * sr * z[a - D - 1];
+        ms[a] = out;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        real v = real(0);
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            if (L::M(a, i) != 0) v += real(back_coef<L>(i, a)) * ms[a];
+        }
+        f[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The step kernel.
+// ---------------------------------------------------------------------------
+template <class L, class ST, typename real, bool NOISE, int TX, int TY, int PF = 2>
 __global__ void __launch_bounds__(TX *TY)
     k_step(const RepDesc *__restrict__ reps, const int *__restrict__ tile_begin, int nrep,
            int parity, const uint64_t *__restrict__ step_base, uint32_t step_off) {
     constexpr int D = L::D, Q = L::Q, R = ST::R;
     constexpr int S = 2 * R + 2;                  // LDS planes (one barrier per plane)
+    constexpr int NSLOT = R + 1 + PF;             // register ring of pulled planes
     constexpr int EXTX = TX + 2 * R;
     constexpr int RY = (D == 3) ? R : 0;
     constexpr int EXTY = (D == 3) ? TY + 2 * R : 1;
     constexpr int NN = L::NNORM;
     constexpr int NT = TX * TY;
+    constexpr int MAXRING = (D == 2) ? 2 * R : (TX + 2 * R) * (TY + 2 * R) - TX * TY;
+    static_assert(MAXRING <= NT, "one ring node per thread at most");
+    constexpr uint32_t ES = sizeof(real);
     __shared__ real lds[S][EXTY][EXTX];
 
     // ---- which replica / tile -------------------------------------------
@@ -55,7 +249,6 @@ __global__ void __launch_bounds__(TX *TY)
     }
     const RepDesc &d = reps[lo];
     const int nx = d.nx, ny = d.ny, ns = d.ns, plane = d.plane;
-    const int64_t N = d.N;
     const int t = lb - d.tile_begin;
     const int tix = t % d.tiles_x;
     const int t2 = t / d.tiles_x;
@@ -68,126 +261,152 @@ __global__ void __launch_bounds__(TX *TY)
     const int TYe = (D == 3) ? min(TY, ny - y0) : 1;
 
     const int tid = threadIdx.x;
-    const int tx = tid % TX, ty = tid / TX;
-    const bool active = tx < TXe && ty < TYe;
-    const int x = active ? x0 + tx : 0;
-    const int y = (D == 3 && active) ? y0 + ty : 0;
+    const bool active = (tid % TX) < TXe && (tid / TX) < TYe;
+    // Lanes past a ragged edge work on the last valid node of the tile: they
+    // load, compute and store exactly what that node's own lane does (the
+    // duplicate stores carry identical bytes), so the loads, the collision and
+    // the stores need no branch; only their LDS writes are skipped.
+    const int tx = min(tid % TX, TXe - 1), ty = min(tid / TX, TYe - 1);
 
-    const real *src = static_cast<const real *>(d.buf[parity]);
-    real *dst = static_cast<real *>(d.buf[parity ^ 1]);
+    const uint64_t buf_bytes = uint64_t(Q) * uint64_t(d.N) * sizeof(real);
+    const rsrc_t src = make_rsrc(d.buf[parity], buf_bytes);
+    const rsrc_t dst = make_rsrc(d.buf[parity ^ 1], buf_bytes);
+    const uint32_t pop_bytes = uint32_t(d.N) * ES;  // < 2^31 (checked on the host)
 
     const real rho0 = real(d.rho0);
     const real psi0 = real(d.psi0);
     const real G = real(d.G);
     const real inv_rho0 = real(1.0 / d.rho0);
+    real lam[Q], amp[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        lam[a] = real(d.lam[a]);
+        amp[a] = real(d.amp[a]);
+    }
 
-    // cross-section pull offsets of the main node, by (c_x, c_y)
-    const int xm = x == 0 ? nx - 1 : x - 1;
-    const int xp = x + 1 == nx ? 0 : x + 1;
-    const int ym = y == 0 ? ny - 1 : y - 1;
-    const int yp = y + 1 == ny ? 0 : y + 1;
-    auto cross_off = [&](int cxv, int cyv, int xx, int xxm, int xxp, int yy, int yym, int yyp) {
-        const int xs = cxv == 1 ? xxm : (cxv == -1 ? xxp : xx);
-        if (D == 2) return xs;
-        const int ys = cyv == 1 ? yym : (cyv == -1 ? yyp : yy);
-        return xs + nx * ys;
+    // ---- per-lane pull offsets (bytes, within a plane), by (c_x, c_y) ------
+    auto make_offsets = [&](int xx, int yy, uint32_t (&xo)[3][3]) {
+        const int xm = xx == 0 ? nx - 1 : xx - 1, xp = xx + 1 == nx ? 0 : xx + 1;
+        const int ym = yy == 0 ? ny - 1 : yy - 1, yp = yy + 1 == ny ? 0 : yy + 1;
+        const int xs[3] = {xp, xx, xm};  // index c + 1 -> x - c
+        const int ys[3] = {yp, yy, ym};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                xo[a][b] = uint32_t(D == 3 ? xs[b] + nx * ys[a] : xs[b]) * ES;
     };
-    auto plane_off = [&](int p, int cs) { return wrap_any(p - cs, ns) * plane; };
-    // marching-axis velocity component and cross-section components
+    // main node
+    const int x = x0 + tx;
+    const int y = D == 3 ? y0 + ty : 0;
+    uint32_t xo_m[3][3];
+    make_offsets(x, y, xo_m);
+    // ring node (extended cross-section, outside the tile), at most one per thread
+    const int ringW = TXe + 2 * R;
+    const int nring = (D == 2) ? 2 * R : ringW * (TYe + 2 * R) - TXe * TYe;
+    const bool has_ring = tid < nring;
+    int rex = 0, rey = 0;
+    if (has_ring) {
+        const int k = tid;
+        if (D == 2) {
+            rex = k < R ? k : TXe + k;
+        } else {
+            const int band = ringW * R;
+            if (k < band) {
+                rey = k / ringW;
+                rex = k % ringW;
+            } else if (k < 2 * band) {
+                const int kk = k - band;
+                rey = TYe + R + kk / ringW;
+                rex = kk % ringW;
+            } else {
+                const int kk = k - 2 * band;
+                rey = R + kk / (2 * R);
+                const int c = kk % (2 * R);
+                rex = c < R ? c : TXe + c;
+            }
+        }
+    }
+    uint32_t xo_r[3][3];
+    make_offsets(has_ring ? wrap_any(x0 - R + rex, nx) : 0,
+                 (D == 3 && has_ring) ? wrap_any(y0 - RY + rey, ny) : 0, xo_r);
+
+    const uint32_t pbytes = uint32_t(plane) * ES;
     auto cm = [](int i) { return L::c(i, D - 1); };
     auto c0 = [](int i) { return L::c(i, 0); };
     auto c1 = [](int i) { return D == 3 ? L::c(i, 1) : 0; };
-
     auto slot = [](int p) { return (p + S) % S; };
 
-    // pseudopotential deviation from a density deviation
-    auto dpsi_of = [&](real dn) {
-        if constexpr (sizeof(real) == 4) return psi0 * expm1f(dn * inv_rho0 / (rho0 + dn));
-        else return psi0 * expm1(dn * inv_rho0 / (rho0 + dn));
+    // loads of plane p (pulled) for the lane offsets xo
+    auto load_plane = [&](int p, const uint32_t (&xo)[3][3], real (&out)[Q]) {
+        const uint32_t pb[3] = {uint32_t(wrap_any(p + 1, ns)) * pbytes,
+                                uint32_t(wrap_any(p, ns)) * pbytes,
+                                uint32_t(wrap_any(p - 1, ns)) * pbytes};
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            out[i] = bload<real>(src, xo[c1(i) + 1][c0(i) + 1], uint32_t(i) * pop_bytes + pb[cm(i) + 1]);
     };
-
-    // ring node k of the extended cross-section -> (ex, ey)
-    const int ringW = TXe + 2 * R;
-    const int nring = (D == 2) ? 2 * R : ringW * (TYe + 2 * R) - TXe * TYe;
-    auto ring_pos = [&](int k, int &ex, int &ey) {
-        if (D == 2) {
-            ey = 0;
-            ex = k < R ? k : TXe + k;
-            return;
-        }
-        const int band = ringW * R;
-        if (k < band) {
-            ey = k / ringW;
-            ex = k % ringW;
-        } else if (k < 2 * band) {
-            const int kk = k - band;
-            ey = TYe + R + kk / ringW;
-            ex = kk % ringW;
-        } else {
-            const int kk = k - 2 * band;
-            ey = R + kk / (2 * R);
-            const int c = kk % (2 * R);
-            ex = c < R ? c : TXe + c;
-        }
+    auto dpsi_of = [&](const real (&fv)[Q]) {
+        real dn = real(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dn += fv[i];
+        return psi0 * fexpm1(dn * inv_rho0 * fast_rcp(rho0 + dn));
     };
-
-    // computes plane p: main-node populations into fmain (if active) and the
-    // dpsi of the whole extended cross-section into LDS
-    auto do_plane = [&](int p, real (&fmain)[Q]) {
-        const int po[3] = {plane_off(p, -1), plane_off(p, 0), plane_off(p, 1)};
+    auto put_psi = [&](int p, const real (&fm)[Q], const real (&fr)[Q]) {
         const int sl = slot(p);
-        if (active) {
-            real dn = real(0);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const real *pi = src + int64_t(i) * N;
-                fmain[i] = pi[po[cm(i) + 1] + cross_off(c0(i), c1(i), x, xm, xp, y, ym, yp)];
-                dn += fmain[i];
-            }
-            lds[sl][ty + RY][tx + R] = dpsi_of(dn);
-        }
-        for (int k = tid; k < nring; k += NT) {
-            int ex, ey;
-            ring_pos(k, ex, ey);
-            const int xr = wrap_any(x0 - R + ex, nx);
-            const int yr = (D == 3) ? wrap_any(y0 - RY + ey, ny) : 0;
-            const int xrm = xr == 0 ? nx - 1 : xr - 1;
-            const int xrp = xr + 1 == nx ? 0 : xr + 1;
-            const int yrm = yr == 0 ? ny - 1 : yr - 1;
-            const int yrp = yr + 1 == ny ? 0 : yr + 1;
-            real dn = real(0);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const real *pi = src + int64_t(i) * N;
-                dn += pi[po[cm(i) + 1] + cross_off(c0(i), c1(i), xr, xrm, xrp, yr, yrm, yrp)];
-            }
-            lds[sl][ey][ex] = dpsi_of(dn);
-        }
+        if (active) lds[sl][ty + RY][tx + R] = dpsi_of(fm);
+        if (has_ring) lds[sl][rey][rex] = dpsi_of(fr);
     };
 
     const uint64_t step = step_base[0] + step_off;
     const uint32_t step32 = uint32_t(step);
 
-    real fr[R + 1][Q];
+    // ---- march order ---------------------------------------------------------
+    // Odd chunks march downwards, so two neighbouring chunks reach their shared
+    // boundary planes at the same time (both at the start or both at the end of
+    // their march) and the halo planes one of them re-reads are still in L2.
+    const int dir = (chunk & 1) ? -1 : 1;
+    const int len = s_end - s_begin;
+    const int first = dir > 0 ? s_begin : s_end - 1;
+
+    // ---- prologue: planes first - dir R .. first + dir (R - 1) ---------------
+    real F[NSLOT][Q];
+    real RG[Q];
 #pragma unroll
     for (int k = -R; k < R; ++k) {
-        real tmp[Q];
-        do_plane(s_begin + k, tmp);
+        real tm[Q];
+        load_plane(first + dir * k, xo_m, tm);
+        if (has_ring) load_plane(first + dir * k, xo_r, RG);
+        put_psi(first + dir * k, tm, RG);
         if (k >= 0) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) fr[k][i] = tmp[i];
+            for (int i = 0; i < Q; ++i) F[k][i] = tm[i];
         }
     }
+    // prefetch: ring plane first + dir R, main planes first + dir (R + q), q < PF
+    if (has_ring) load_plane(first + dir * R, xo_r, RG);
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+        if (q < len) load_plane(first + dir * (R + q), xo_m, F[R + q]);
 
-    for (int s = s_begin; s < s_end; ++s) {
-        do_plane(s + R, fr[R]);
-        __syncthreads();
+    const uint32_t lane_store = uint32_t(D == 3 ? x + nx * y : x) * ES;
 
-        if (active) {
+    for (int m0 = 0; m0 < len; m0 += NSLOT) {
+#pragma unroll
+        for (int j = 0; j < NSLOT; ++j) {
+            const int m = m0 + j;
+            if (m >= len) break;
+            const int s = first + dir * m;
+            // plane s + dir R has arrived: its dpsi goes to LDS
+            put_psi(s + dir * R, F[(j + R) % NSLOT], RG);
+            // prefetch: ring plane s + dir (R + 1), main plane s + dir (R + PF)
+            if (has_ring && m + 1 < len) load_plane(s + dir * (R + 1), xo_r, RG);
+            if (m + PF < len) load_plane(s + dir * (R + PF), xo_m, F[(j + R + PF) % NSLOT]);
+            __syncthreads();
+
             int sl[2 * R + 1];
 #pragma unroll
             for (int k = -R; k <= R; ++k) sl[k + R] = slot(s + k);
-
             // ---- Shan-Chen force, Eq. (1), as antisymmetric pairs ----------
             real g[3] = {real(0), real(0), real(0)};
 #pragma unroll
@@ -195,9 +414,8 @@ __global__ void __launch_bounds__(TX *TY)
                 const int ex = ST::e(a, 0);
                 const int ey = D == 3 ? ST::e(a, 1) : 0;
                 const int es = ST::e(a, D - 1);
-                const real vp = lds[sl[R + es]][ty + RY + ey][tx + R + ex];
-                const real vm = lds[sl[R - es]][ty + RY - ey][tx + R - ex];
-                const real diff = vp - vm;
+                const real diff = lds[sl[R + es]][ty + RY + ey][tx + R + ex] -
+                                  lds[sl[R - es]][ty + RY - ey][tx + R - ex];
 #pragma unroll
                 for (int q = 0; q < D; ++q) {
                     const int eq = ST::e(a, q);
@@ -205,110 +423,33 @@ __global__ void __launch_bounds__(TX *TY)
                 }
             }
             const real pre = G * (psi0 + lds[sl[R]][ty + RY][tx + R]);
-            real F[3];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) F[q] = pre * g[q];
-
-            // ---- moments of the pulled populations -------------------------
-            const real(&f)[Q] = fr[0];
-            real dn = real(0);
-            real j[3] = {real(0), real(0), real(0)};
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                dn += f[i];
-#pragma unroll
-                for (int q = 0; q < D; ++q) {
-                    if (L::c(i, q) == 1) j[q] += f[i];
-                    if (L::c(i, q) == -1) j[q] -= f[i];
-                }
-            }
-            const real rho = rho0 + dn;
-            const real inv_rho = real(1) / rho;
-            real u[3] = {real(0), real(0), real(0)};
-#pragma unroll
-            for (int q = 0; q < D; ++q) u[q] = (j[q] + real(0.5) * F[q]) * inv_rho;
+            const real Fv[3] = {pre * g[0], pre * g[1], pre * g[2]};
 
             real z[NN];
-            real srho = real(0);
             if constexpr (NOISE) {
                 const uint32_t node = uint32_t(x + nx * (y + (D == 3 ? ny * s : s)));
-                node_normals<NN, real>(node, step32, d.seed_hi, d.key0, d.key1, z);
-                srho = sqrt(rho);
+                node_normals<L, real>(node, step32, d.seed_hi, d.key0, d.key1, z);
+            } else {
+#pragma unroll
+                for (int k = 0; k < NN; ++k) z[k] = real(0);
             }
+            real(&fv)[Q] = F[j % NSLOT];
+            if constexpr (D == 2) collide_d2q9<real, NOISE>(fv, rho0, Fv, lam, amp, z);
+            else collide_generic<L, real, NOISE>(fv, rho0, Fv, lam, amp, z);
 
-            // ---- collision in moment space ---------------------------------
-            real ms[Q];
-            ms[0] = dn;
+            const uint32_t so = uint32_t(s) * pbytes + lane_store;
 #pragma unroll
-            for (int q = 0; q < D; ++q) ms[1 + q] = j[q] + F[q];
-#pragma unroll
-            for (int a = D + 1; a < Q; ++a) {
-                real m = real(0);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    const int c = L::M(a, i);
-                    if (c == 1) m += f[i];
-                    else if (c == -1) m -= f[i];
-                    else if (c != 0) m += real(c) * f[i];
-                }
-                const real lam = real(d.lam[a]);
-                real out;
-                if (L::cls(a) == 3) {
-                    out = (real(1) - lam) * m;
-                } else {
-                    real uAu = real(0), uAF = real(0);
-#pragma unroll
-                    for (int p = 0; p < D; ++p)
-#pragma unroll
-                        for (int q = 0; q < D; ++q) {
-                            const double A = L::A(a, p, q);
-                            if (A != 0.0) {
-                                uAu += real(A) * u[p] * u[q];
-                                uAF += real(A) * u[p] * F[q];
-                            }
-                        }
-                    const real meq = rho * uAu;
-                    out = m - lam * (m - meq) + (real(1) - real(0.5) * lam) * (real(2) * uAF);
-                }
-                if constexpr (NOISE) out += real(d.amp[a]) * srho * z[a - D - 1];
-                ms[a] = out;
-            }
-
-            // ---- back-transform and store ----------------------------------
-            const int sp = s * plane + (D == 3 ? x + nx * y : x);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                real v = real(0);
-#pragma unroll
-                for (int a = 0; a < Q; ++a) {
-                    const int c = L::M(a, i);
-                    if (c != 0) v += real(back_coef<L>(i, a)) * ms[a];
-                }
-                dst[int64_t(i) * N + sp] = v;
-            }
+            for (int i = 0; i < Q; ++i) bstore(dst, so, uint32_t(i) * pop_bytes, fv[i]);
         }
-
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-#pragma unroll
-            for (int i = 0; i < Q; ++i) fr[k][i] = fr[k + 1][i];
     }
 }
 
-template <class L, class ST, typename real, bool NOISE, int TX, int TY>
+template <class L, class ST, typename real, bool NOISE, int TX, int TY, int PF>
 inline hipError_t launch_one(const StepLaunch &P, hipStream_t s) {
-    hipLaunchKernelGGL((k_step<L, ST, real, NOISE, TX, TY>), dim3(P.total_tiles), dim3(TX * TY),
-                       0, s, P.reps, P.tile_begin, P.nrep, P.parity, P.step_base, P.step_off);
+    hipLaunchKernelGGL((k_step<L, ST, real, NOISE, TX, TY, PF>), dim3(P.total_tiles),
+                       dim3(TX * TY), 0, s, P.reps, P.tile_begin, P.nrep, P.parity, P.step_base,
+                       P.step_off);
     return hipGetLastError();
-}
-
-template <class L, class ST, int TX, int TY>
-inline hipError_t launch_prec(const StepLaunch &P, hipStream_t s) {
-    if (P.precision == 0)
-        return P.noise ? launch_one<L, ST, float, true, TX, TY>(P, s)
-                       : launch_one<L, ST, float, false, TX, TY>(P, s);
-    return P.noise ? launch_one<L, ST, double, true, TX, TY>(P, s)
-                   : launch_one<L, ST, double, false, TX, TY>(P, s);
 }
 
 }  // namespace fsc

@@ -283,6 +283,22 @@ def test_ensemble_replicas_equal_single_lattices_and_oracle():
     ens.close()
 
 
+def test_autotune_leaves_state_and_results_unchanged():
+    p = _params(2, (200, 300), 8, "fp32", T_hat=0.75, rho0=1.0, kBT=1e-4, seed=4)
+    with fsc.Lattice(p) as a, fsc.Lattice(p) as b:
+        a.init_uniform()
+        b.init_uniform()
+        a.step(40)
+        b.step(17)
+        before = b.get_populations()
+        b.autotune()
+        assert np.array_equal(before, b.get_populations())
+        b.step(23)
+        assert np.array_equal(a.get_populations(), b.get_populations())
+        t = b.tiling
+        assert t["blocks"] > 0 and t["tx"] in (64, 128, 256)
+
+
 # ------------------------------------------------ full-size sampled parity ---
 @pytest.mark.parametrize("case", ["deep_quench_4096", "metastable_256cube"])
 def test_full_size_one_step_matches_oracle(case):
@@ -334,3 +350,38 @@ def test_gpu_structure_factor_matches_exact_theory(precision, T_hat, rho0, kBT):
     print("z-scores", np.round(z, 2))
     assert np.all(np.abs(z) < 4.0)
     assert np.mean(z ** 2) < 2.5
+
+
+# --------------------------------------------------- S(k, t) and L(t) --------
+@pytest.mark.parametrize("shape,precision", [((64, 64), "fp64"), ((64, 64), "fp32"),
+                                             ((16, 16, 16), "fp32")])
+def test_series_row_matches_oracle(shape, precision):
+    D = len(shape)
+    Q = 9 if D == 2 else 19
+    f = I.smooth_density_populations(Q, shape, 1.0, 0.2, 6, seed=8)
+    p = _params(D, shape, 4, precision, rho0=1.0)
+    with fsc.Lattice(p) as lat:
+        lat.series_enable(8)
+        lat.set_populations(f, 77)
+        lat.measure_sk()
+        ser = lat.read_series()
+    rho = O.density(f)
+    assert list(ser["step"]) == [77]
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    assert ser["L"][0] == pytest.approx(O.domain_length(rho), rel=tol)
+    ref = O.shell_means(rho)
+    assert np.allclose(ser["S"][0], ref, rtol=tol, atol=tol * ref.max())
+
+
+def test_series_through_graph_replay_records_every_sample():
+    p = _params(2, (128, 128), 8, "fp32", T_hat=0.7, rho0=1.0, kBT=1e-4, seed=2)
+    with fsc.Lattice(p) as lat:
+        lat.init_uniform()
+        lat.series_enable(64)
+        lat.run(1000, sk_every=50)
+        ser = lat.read_series()
+    assert list(ser["step"]) == list(range(50, 1001, 50))
+    L = ser["L"]
+    assert np.all(np.isfinite(L)) and np.all(L > 0)
+    # spinodal decomposition: the domains coarsen once the unstable modes saturate
+    assert L[-1] > L[4]

@@ -320,3 +320,18 @@ def test_oracle_sk_matches_exact_linear_theory(T_hat, n0, G):
     z = np.array(z)
     assert np.all(np.abs(z) < 4.0), z
     assert np.mean(z ** 2) < 2.5, z
+
+
+def test_domain_length_of_single_modes():
+    # a field made of one wave vector k0 (and its conjugate) has L = 2 pi/|k0|
+    for shape, m in [((32, 32), (3, 0)), ((32, 32), (2, 5)), ((16, 16, 16), (1, 2, 2))]:
+        grids = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+        k = [2 * np.pi * mm / s for mm, s in zip(m, shape)]
+        rho = 1.0 + 0.1 * np.cos(sum(kk * g for kk, g in zip(k, grids)))
+        assert O.domain_length(rho) == pytest.approx(2 * np.pi / np.sqrt(sum(kk * kk for kk in k)),
+                                                     rel=1e-12)
+    # two equal-power modes: the harmonic mean of their lengths
+    g = np.arange(64)
+    rho = np.cos(2 * np.pi * 2 * g / 64)[None, :] + np.cos(2 * np.pi * 8 * g / 64)[:, None]
+    k1, k2 = 2 * np.pi * 2 / 64, 2 * np.pi * 8 / 64
+    assert O.domain_length(rho) == pytest.approx(2 * np.pi * 2 / (k1 + k2), rel=1e-12)

@@ -1,0 +1,62 @@
+"""Pins of the FP64 surrogate reference (oracle/surrogate.py)."""
+import numpy as np
+import pytest
+
+from oracle import surrogate as S
+
+
+def test_conv3x3_is_the_periodic_cross_correlation():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(2, 3, 5, 6))
+    W = rng.normal(size=(4, 3, 3, 3))
+    b = rng.normal(size=4)
+    out = S.conv3x3(x, W, b)
+    for n in range(2):
+        for o in range(4):
+            for y in range(5):
+                for xx in range(6):
+                    v = b[o]
+                    for c in range(3):
+                        for ky in range(3):
+                            for kx in range(3):
+                                v += W[o, c, ky, kx] * x[n, c, (y + ky - 1) % 5, (xx + kx - 1) % 6]
+                    assert out[n, o, y, xx] == pytest.approx(v, abs=1e-12)
+
+
+def test_conv_adjoint_identity():
+    # <conv(x) - b, g> = <x, conv^T(g)>
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=(2, 3, 7, 5))
+    g = rng.normal(size=(2, 4, 7, 5))
+    W = rng.normal(size=(4, 3, 3, 3))
+    lhs = (S.conv3x3(x, W, np.zeros(4)) * g).sum()
+    rhs = (x * S.conv3x3_input_grad(g, W)).sum()
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(2)
+    C, L = 3, 4
+    p = S.init_params(C, L, seed=3) + 0.05 * rng.normal(size=S.n_params(C, L))
+    rho = 1.0 + 0.3 * rng.normal(size=(2, 6, 6))
+    tgt = rho + 0.05 * rng.normal(size=rho.shape)
+    kw = dict(channels=C, layers=L, mean=1.0, in_scale=0.3, out_scale=0.05)
+    loss, g = S.loss_and_grad(p, rho, tgt, **kw)
+    h = 1e-6
+    idx = rng.choice(p.size, size=40, replace=False)
+    for i in idx:
+        e = np.zeros_like(p)
+        e[i] = h
+        lp, _ = S.loss_and_grad(p + e, rho, tgt, **kw)
+        lm, _ = S.loss_and_grad(p - e, rho, tgt, **kw)
+        assert g[i] == pytest.approx((lp - lm) / (2 * h), rel=1e-5, abs=1e-9)
+
+
+def test_prediction_conserves_the_image_mean():
+    rng = np.random.default_rng(4)
+    C, L = 4, 5
+    p = S.init_params(C, L, seed=5)
+    rho = 1.0 + 0.3 * rng.normal(size=(3, 8, 8))
+    pred = S.forward(p, rho, C, L, 1.0, 0.3, 0.1)
+    assert np.allclose(pred.mean(axis=(1, 2)), rho.mean(axis=(1, 2)), atol=1e-14)
+    assert S.n_params(32, 5) == 288 + 32 + 3 * (9216 + 32) + 288 + 1
