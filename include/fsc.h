@@ -51,6 +51,7 @@ extern "C" {
 #define FSC_E_DIVERGED (-4) /* non-finite or non-positive density detected */
 #define FSC_E_STATE (-5)    /* call not valid in the current state */
 #define FSC_E_NOTSUP (-6)   /* combination not supported by this build */
+#define FSC_E_IO (-7)       /* checkpoint file missing, unreadable, truncated or corrupt */
 
 #define FSC_E4 4 /* 2D: |e|^2 in {1,2} (8 neighbours); 3D: {1,2} (18) */
 #define FSC_E8 8 /* 2D only: |e|^2 in {1,2,4,5,8} (24 neighbours, 5x5 block) */
@@ -139,6 +140,11 @@ int fsc_run(fsc_ctx *ctx, int64_t nsteps, int64_t sk_every);
 
 int fsc_get_step(const fsc_ctx *ctx, int64_t *step);
 
+/* Checkpoint of a single lattice: same file format and behaviour as
+ * fsc_ens_save / fsc_ens_load below (one replica). */
+int fsc_save(fsc_ctx *ctx, const char *path);
+int fsc_load(fsc_ctx *ctx, const char *path);
+
 /* Density n(x) = sum_i f_i of the current state, host double [nz][ny][nx]. */
 int fsc_density(fsc_ctx *ctx, double *host_rho);
 
@@ -194,9 +200,76 @@ int fsc_ens_sk_nbins(const fsc_ens *ens, int replica, int kind, int *nbins);
 int fsc_ens_read_sk(fsc_ens *ens, int replica, int kind, double *sum, double *sumsq,
                     int64_t *count, int nbins);
 int fsc_ens_sk_reset(fsc_ens *ens);
+
+/* Checkpoint and resume.  fsc_ens_save writes the current step, every
+ * replica's parameters, its populations exactly as stored and its FP64 S(k)
+ * accumulators to a file at `path` (host file IO, caller-owned path; the
+ * stream is synchronised).  fsc_ens_load restores them into an ensemble
+ * created with the same parameters, in the same order: continuing from the
+ * loaded state is bit-identical to continuing the saved run, because the
+ * noise of Eq. 12 depends only on (seed, replica, node, step).  Errors:
+ * FSC_E_IO (cannot open, truncated, not a checkpoint), FSC_E_INVAL (another
+ * replica count or other parameters; nothing is changed), FSC_E_HIP.
+ * Time-series rows (fsc_ens_series_enable) are not part of the file. */
+int fsc_ens_save(fsc_ens *ens, const char *path);
+int fsc_ens_load(fsc_ens *ens, const char *path);
 int fsc_ens_series_enable(fsc_ens *ens, int capacity);
 int fsc_ens_read_series(fsc_ens *ens, int replica, double *out, int max_rows, int *nrows,
                         int *row_len);
+
+/* ----------------------------------------------------------------------- */
+/* Learned coarse-grained surrogate (not in the paper).                     */
+/*                                                                          */
+/* A periodic convolutional network advances the block-averaged density of  */
+/* a phase-separating 2D lattice by a fixed number of lattice steps:        */
+/*   x = (rho - mean)/in_scale; a_0 = SiLU(conv(x)); a_l = SiLU(conv(a_l-1)),*/
+/*   l = 1..layers-2 (32 channels); y = conv(a_layers-2);                    */
+/*   rho' = rho + out_scale (y - <y>_image)   (conserves each image's mean)  */
+/* conv = 3x3 cross-correlation, circular padding.  The 32 -> 32 layers run  */
+/* on BF16 matrix cores with FP32 accumulation (forward, backward-data and   */
+/* backward-weight); parameters are FP32, trained by Adam on the loss        */
+/* mean((y - <y>) - (target - rho)/out_scale)^2.  Fields are device float    */
+/* arrays [batch][H][W]; calls run on the surrogate's stream (NULL: its own) */
+/* and return after enqueueing, except those returning host data.           */
+/* ----------------------------------------------------------------------- */
+typedef struct fsc_sur fsc_sur;
+
+/* layers in [3, 16]; W a multiple of 32; max_batch * H * W < 2^26.  Weights
+ * are drawn from `seed` (He-uniform), biases zero. */
+int fsc_sur_create(int layers, int H, int W, int max_batch, uint64_t seed, void *stream,
+                   fsc_sur **out);
+int fsc_sur_destroy(fsc_sur *s);
+const char *fsc_sur_last_error(const fsc_sur *s);
+/* Parameters: one float vector, per layer W[c_out][c_in][3][3] then b[c_out]. */
+int fsc_sur_nparams(const fsc_sur *s, int64_t *n);
+int fsc_sur_set_params(fsc_sur *s, const float *host, int64_t n); /* resets Adam state */
+int fsc_sur_get_params(fsc_sur *s, float *host, int64_t n);
+int fsc_sur_set_norm(fsc_sur *s, float mean, float in_scale, float out_scale);
+int fsc_sur_forward(fsc_sur *s, const float *dev_in, float *dev_out, int batch);
+/* Gradient of the loss (host float[nparams], may be NULL) and the loss. */
+int fsc_sur_grad(fsc_sur *s, const float *dev_in, const float *dev_target, int batch,
+                 float *host_grad, double *loss);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) at learning rate lr; *loss (may be
+ * NULL) gets the loss before the update. */
+int fsc_sur_train_step(fsc_sur *s, const float *dev_in, const float *dev_target, int batch,
+                       float lr, double *loss);
+
+/* Block-averaged density of the current state over factor x factor blocks
+ * into dev_out[(ny/factor) x (nx/factor)] (2D lattices, sides divisible by
+ * factor); enqueued on the lattice's stream. */
+int fsc_coarsen(fsc_ctx *ctx, int factor, float *dev_out);
+int fsc_ens_coarsen(fsc_ens *ens, int replica, int factor, float *dev_out);
+
+/* S(k) of device fields [batch][n][n] (float): per radial shell the mean of
+ * |sum_x f(x) e^{-ik.x}|^2 / n^2 (shells as FSC_SK_RADIAL, nbins from
+ * fsc_field_nbins) and L = 2 pi sum P / sum |k| P.  Synchronous on `stream`. */
+int fsc_field_nbins(int n, int *nbins);
+int fsc_field_sk(const float *dev_fields, int batch, int ny, int nx, void *stream,
+                 double *host_shell_mean, double *host_L, int nbins);
+
+/* Matrix-core layout check: C = A (16x32) B (32x16) through one BF16 MFMA
+ * with the operand placement the surrogate kernels use (host row-major). */
+int fsc_mfma_probe(const float *host_a, const float *host_b, float *host_c);
 
 /* ----------------------------------------------------------------------- */
 /* Tiling of the fused step.                                                */

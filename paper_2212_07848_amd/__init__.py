@@ -6,9 +6,9 @@ device memory and streams (``Lattice(..., stream=torch_stream,
 buffers=(tensor_a, tensor_b))``).
 """
 from ._lib import (FSC_E4, FSC_E8, FSC_FP32_SHIFTED, FSC_FP64, FSC_SK_AXIS, FSC_SK_RADIAL,
-                   EXPORTS, Ensemble, FscError, Lattice, Params, device_copy, lib, make_params,
-                   normals, philox)
+                   EXPORTS, Ensemble, FscError, Lattice, Params, Surrogate, device_copy,
+                   field_sk, lib, make_params, mfma_probe, normals, philox)
 
 __all__ = ["FSC_E4", "FSC_E8", "FSC_FP32_SHIFTED", "FSC_FP64", "FSC_SK_AXIS", "FSC_SK_RADIAL",
-           "EXPORTS", "Ensemble", "FscError", "Lattice", "Params", "device_copy", "lib",
-           "make_params", "normals", "philox"]
+           "EXPORTS", "Ensemble", "FscError", "Lattice", "Params", "Surrogate", "device_copy",
+           "field_sk", "lib", "make_params", "mfma_probe", "normals", "philox"]

@@ -21,20 +21,24 @@ FSC_FP32_SHIFTED, FSC_FP64 = 0, 1
 FSC_SK_AXIS, FSC_SK_RADIAL = 0, 1
 
 ERRORS = {0: "ok", -1: "invalid argument", -2: "HIP runtime error", -3: "out of memory",
-          -4: "diverged", -5: "invalid state", -6: "not supported"}
+          -4: "diverged", -5: "invalid state", -6: "not supported", -7: "file error"}
 
 # Every symbol include/fsc.h declares.
 EXPORTS = [
     "fsc_create", "fsc_create_external", "fsc_destroy", "fsc_last_error", "fsc_strerror",
     "fsc_get_params", "fsc_init_uniform", "fsc_set_populations", "fsc_get_populations",
-    "fsc_step", "fsc_run", "fsc_get_step", "fsc_density", "fsc_stats", "fsc_sk_reset",
+    "fsc_step", "fsc_run", "fsc_get_step", "fsc_save", "fsc_load", "fsc_density", "fsc_stats", "fsc_sk_reset",
     "fsc_measure_sk", "fsc_sk_nbins", "fsc_read_sk", "fsc_series_enable", "fsc_read_series",
     "fsc_ens_create", "fsc_ens_destroy", "fsc_ens_last_error", "fsc_ens_init_uniform",
     "fsc_ens_run", "fsc_ens_get_step", "fsc_ens_get_populations", "fsc_ens_set_populations",
     "fsc_ens_stats", "fsc_ens_sk_nbins", "fsc_ens_read_sk", "fsc_ens_sk_reset",
-    "fsc_ens_series_enable", "fsc_ens_read_series",
+    "fsc_ens_save", "fsc_ens_load", "fsc_ens_series_enable", "fsc_ens_read_series",
     "fsc_autotune", "fsc_ens_autotune", "fsc_get_tiling", "fsc_ens_get_tiling",
     "fsc_copy", "fsc_philox", "fsc_normals",
+    "fsc_sur_create", "fsc_sur_destroy", "fsc_sur_last_error", "fsc_sur_nparams",
+    "fsc_sur_set_params", "fsc_sur_get_params", "fsc_sur_set_norm", "fsc_sur_forward",
+    "fsc_sur_grad", "fsc_sur_train_step", "fsc_coarsen", "fsc_ens_coarsen", "fsc_field_nbins",
+    "fsc_field_sk", "fsc_mfma_probe",
 ]
 
 
@@ -74,6 +78,7 @@ def lib():
         raise ImportError(f"{LIBPATH} is not built; run __graft_entry__.build() first")
     L = C.CDLL(LIBPATH)
     vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
+    fp = C.POINTER(C.c_float)
     pp = C.POINTER(Params)
     u32p = C.POINTER(C.c_uint32)
     sig = {
@@ -89,6 +94,10 @@ def lib():
         "fsc_step": ([vp, C.c_int64], C.c_int),
         "fsc_run": ([vp, C.c_int64, C.c_int64], C.c_int),
         "fsc_get_step": ([vp, i64p], C.c_int),
+        "fsc_save": ([vp, C.c_char_p], C.c_int),
+        "fsc_load": ([vp, C.c_char_p], C.c_int),
+        "fsc_ens_save": ([vp, C.c_char_p], C.c_int),
+        "fsc_ens_load": ([vp, C.c_char_p], C.c_int),
         "fsc_density": ([vp, dp], C.c_int),
         "fsc_stats": ([vp, dp], C.c_int),
         "fsc_sk_reset": ([vp], C.c_int),
@@ -118,6 +127,22 @@ def lib():
         "fsc_ens_get_tiling": ([vp, C.POINTER(C.c_int)], C.c_int),
         "fsc_copy": ([vp, vp, C.c_int64, vp], C.c_int),
         "fsc_philox": ([u32p, u32p, u32p, C.c_int64], C.c_int),
+        "fsc_sur_create": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, vp, C.POINTER(vp)],
+                           C.c_int),
+        "fsc_sur_destroy": ([vp], C.c_int),
+        "fsc_sur_last_error": ([vp], C.c_char_p),
+        "fsc_sur_nparams": ([vp, i64p], C.c_int),
+        "fsc_sur_set_params": ([vp, fp, C.c_int64], C.c_int),
+        "fsc_sur_get_params": ([vp, fp, C.c_int64], C.c_int),
+        "fsc_sur_set_norm": ([vp, C.c_float, C.c_float, C.c_float], C.c_int),
+        "fsc_sur_forward": ([vp, vp, vp, C.c_int], C.c_int),
+        "fsc_sur_grad": ([vp, vp, vp, C.c_int, fp, dp], C.c_int),
+        "fsc_sur_train_step": ([vp, vp, vp, C.c_int, C.c_float, dp], C.c_int),
+        "fsc_coarsen": ([vp, C.c_int, vp], C.c_int),
+        "fsc_ens_coarsen": ([vp, C.c_int, C.c_int, vp], C.c_int),
+        "fsc_field_nbins": ([C.c_int, C.POINTER(C.c_int)], C.c_int),
+        "fsc_field_sk": ([vp, C.c_int, C.c_int, C.c_int, vp, dp, dp, C.c_int], C.c_int),
+        "fsc_mfma_probe": ([fp, fp, fp], C.c_int),
         "fsc_normals": ([C.c_int, C.c_int, C.c_uint64, C.c_uint32, i64p, i64p, C.c_int64, dp],
                         C.c_int),
     }
@@ -248,6 +273,13 @@ class Lattice:
     def sk_reset(self):
         self._c(lib().fsc_sk_reset(self._h))
 
+    def save(self, path: str):
+        """Checkpoint: step, populations as stored, S(k) accumulators."""
+        self._c(lib().fsc_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        self._c(lib().fsc_load(self._h, os.fsencode(path)))
+
     def measure_sk(self):
         self._c(lib().fsc_measure_sk(self._h))
 
@@ -258,6 +290,10 @@ class Lattice:
         rc, rows = _read_series(lib().fsc_read_series, self._h)
         self._c(rc)
         return _series_dict(rows)
+
+    def coarsen(self, factor: int, out_tensor):
+        """Block means into a device float tensor of shape (ny/factor, nx/factor)."""
+        self._c(lib().fsc_coarsen(self._h, int(factor), C.c_void_p(out_tensor.data_ptr())))
 
     def read_sk(self, kind=FSC_SK_AXIS):
         nb = C.c_int()
@@ -356,6 +392,13 @@ class Ensemble:
     def sk_reset(self):
         self._c(lib().fsc_ens_sk_reset(self._h))
 
+    def save(self, path: str):
+        """Checkpoint of every replica (see fsc_ens_save)."""
+        self._c(lib().fsc_ens_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        self._c(lib().fsc_ens_load(self._h, os.fsencode(path)))
+
     def series_enable(self, capacity: int):
         self._c(lib().fsc_ens_series_enable(self._h, int(capacity)))
 
@@ -363,6 +406,9 @@ class Ensemble:
         rc, rows = _read_series(lib().fsc_ens_read_series, self._h, r)
         self._c(rc)
         return _series_dict(rows)
+
+    def coarsen(self, r: int, factor: int, out_tensor):
+        self._c(lib().fsc_ens_coarsen(self._h, r, int(factor), C.c_void_p(out_tensor.data_ptr())))
 
     def read_sk(self, r: int, kind=FSC_SK_AXIS):
         nb = C.c_int()
@@ -375,6 +421,92 @@ class Ensemble:
             D = self.plist[r].D
             s, q, c = (v.reshape(D, -1) for v in (s, q, c))
         return s, q, c
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Surrogate:
+    """The learned coarse-grained surrogate (fsc_sur).  Device fields are
+    passed as objects with data_ptr() (torch tensors) or raw pointers."""
+
+    def __init__(self, layers: int, H: int, W: int, max_batch: int, seed: int = 0, stream=None):
+        L = lib()
+        self._h = C.c_void_p()
+        _check(L.fsc_sur_create(layers, H, W, max_batch, C.c_uint64(seed), _stream_handle(stream),
+                                C.byref(self._h)), L.fsc_sur_last_error, None)
+        n = C.c_int64()
+        self._c(L.fsc_sur_nparams(self._h, C.byref(n)))
+        self.nparams = n.value
+        self.layers, self.H, self.W = layers, H, W
+
+    def _c(self, rc):
+        _check(rc, lib().fsc_sur_last_error, self._h)
+
+    def close(self):
+        if self._h:
+            lib().fsc_sur_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _ptr(x):
+        return C.c_void_p(x.data_ptr() if hasattr(x, "data_ptr") else int(x))
+
+    def get_params(self):
+        out = np.zeros(self.nparams, dtype=np.float32)
+        self._c(lib().fsc_sur_get_params(self._h, _fp(out), self.nparams))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.nparams
+        self._c(lib().fsc_sur_set_params(self._h, _fp(p), self.nparams))
+
+    def set_norm(self, mean: float, in_scale: float, out_scale: float):
+        self._c(lib().fsc_sur_set_norm(self._h, mean, in_scale, out_scale))
+
+    def forward(self, x, out, batch: int):
+        self._c(lib().fsc_sur_forward(self._h, self._ptr(x), self._ptr(out), int(batch)))
+
+    def grad(self, x, target, batch: int):
+        g = np.zeros(self.nparams, dtype=np.float32)
+        loss = C.c_double()
+        self._c(lib().fsc_sur_grad(self._h, self._ptr(x), self._ptr(target), int(batch), _fp(g),
+                                   C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, x, target, batch: int, lr: float, want_loss: bool = True):
+        loss = C.c_double()
+        self._c(lib().fsc_sur_train_step(self._h, self._ptr(x), self._ptr(target), int(batch),
+                                         float(lr), C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+
+def field_sk(fields, batch: int, n: int, stream=None):
+    """Radial shell means of S(k) and L for device float fields [batch][n][n]."""
+    nb = C.c_int()
+    _check(lib().fsc_field_nbins(n, C.byref(nb)))
+    shells = np.zeros((batch, nb.value))
+    L = np.zeros(batch)
+    ptr = C.c_void_p(fields.data_ptr() if hasattr(fields, "data_ptr") else int(fields))
+    _check(lib().fsc_field_sk(ptr, batch, n, n, _stream_handle(stream), _dp(shells), _dp(L),
+                              nb.value))
+    return shells, L
+
+
+def mfma_probe(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    Cm = np.zeros((16, 16), dtype=np.float32)
+    _check(lib().fsc_mfma_probe(_fp(A), _fp(B), _fp(Cm)))
+    return Cm
 
 
 def device_copy(src_ptr: int, dst_ptr: int, nbytes: int, stream=None):

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -354,21 +355,18 @@ void build_desc(fsc_ens *e) {
         d.G = r.p.G;
         d.rho0 = r.p.rho0;
         d.psi0 = std::exp(-1.0 / r.p.rho0);
-        for (int a = 0; a < 19; ++a) {
-            d.lam[a] = 1.0;
-            d.amp[a] = 0.0;
+        const double lams[4] = {1.0, r.p.lambda_bulk, r.p.lambda_shear, r.p.lambda_ghost};
+        for (int k = 0; k < 4; ++k) {
+            const double g = 1.0 - lams[k];
+            d.lamc[k] = lams[k];
+            d.ampc[k] = k == 0 ? 0.0 : std::sqrt(r.p.kBT / CS2 * (1.0 - g * g));
+            d.lamcf[k] = float(d.lamc[k]);
+            d.ampcf[k] = float(d.ampc[k]);
         }
-        for (int a = 0; a < r.Q; ++a) {
-            const int k = r.cls[a];
-            const double lam = k == 0 ? 1.0
-                                      : (k == 1 ? r.p.lambda_bulk
-                                                : (k == 2 ? r.p.lambda_shear : r.p.lambda_ghost));
-            d.lam[a] = lam;
-            if (k != 0) {
-                const double g = 1.0 - lam;
-                d.amp[a] = std::sqrt(r.p.kBT / CS2 * r.b[a] * (1.0 - g * g));
-            }
-        }
+        d.Gf = float(d.G);
+        d.rho0f = float(d.rho0);
+        d.psi0f = float(d.psi0);
+        d.inv_rho0f = float(1.0 / d.rho0);
         d.key0 = uint32_t(r.p.seed & 0xffffffffu);
         d.key1 = r.p.replica;
         d.seed_hi = uint32_t(r.p.seed >> 32);
@@ -774,6 +772,99 @@ int ens_init_uniform(fsc_ens *e) {
     return ens_sk_reset(e);
 }
 
+// ---- checkpoints -----------------------------------------------------------
+// File layout (native byte order): magic "FSCK", u32 version, u32 replica count,
+// u32 zero, i64 step; then per replica: its resolved fsc_params, i64 S(k)
+// sample count, u64 accumulator count, u64 population bytes, the populations
+// exactly as stored (pull-layout deviations of the current buffer), the FP64
+// S(k) accumulators.  Resuming from the file reproduces the run bit for bit,
+// since the noise depends only on (seed, replica, node, step).
+constexpr uint32_t kCkptMagic = 0x4b435346u;  // "FSCK" read as little-endian u32
+constexpr uint32_t kCkptVersion = 1;
+
+bool same_run(const fsc_params &a, const fsc_params &b) {
+    auto eqd = [](double x, double y) { return std::memcmp(&x, &y, sizeof(double)) == 0; };
+    return a.D == b.D && a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.stencil == b.stencil &&
+           a.precision == b.precision && eqd(a.G, b.G) && eqd(a.rho0, b.rho0) &&
+           eqd(a.lambda_bulk, b.lambda_bulk) && eqd(a.lambda_shear, b.lambda_shear) &&
+           eqd(a.lambda_ghost, b.lambda_ghost) && eqd(a.kBT, b.kBT) && a.seed == b.seed &&
+           a.replica == b.replica;
+}
+
+uint64_t sk_len(const Rep &r) { return 2 * uint64_t(r.p.D) * r.n_axis + 2 * uint64_t(r.n_rad); }
+
+int ens_save(fsc_ens *e, const char *path) {
+    std::unique_ptr<FILE, int (*)(FILE *)> fp(std::fopen(path, "wb"), std::fclose);
+    if (!fp) return fail(e, FSC_E_IO, std::string("cannot open ") + path + " for writing");
+    auto put = [&](const void *p, size_t n) { return std::fwrite(p, 1, n, fp.get()) == n; };
+    const uint32_t head[4] = {kCkptMagic, kCkptVersion, uint32_t(e->reps.size()), 0};
+    bool ok = put(head, sizeof(head)) && put(&e->step, sizeof(e->step));
+    const int par = int(e->step & 1);
+    std::vector<unsigned char> raw;
+    std::vector<double> acc;
+    for (size_t k = 0; ok && k < e->reps.size(); ++k) {
+        Rep &r = e->reps[k];
+        const uint64_t nsk = sk_len(r);
+        const uint64_t nbytes = uint64_t(r.esz) * r.Q * r.N;
+        raw.resize(nbytes);
+        acc.resize(nsk);
+        HIPCHK(e, hipMemcpyAsync(raw.data(), r.buf[par], nbytes, hipMemcpyDeviceToHost, e->stream));
+        HIPCHK(e, hipMemcpyAsync(acc.data(), r.d_sk, sizeof(double) * nsk, hipMemcpyDeviceToHost,
+                                 e->stream));
+        HIPCHK(e, hipStreamSynchronize(e->stream));
+        ok = put(&r.p, sizeof(r.p)) && put(&r.nsamples, sizeof(r.nsamples)) && put(&nsk, sizeof(nsk)) &&
+             put(&nbytes, sizeof(nbytes)) && put(raw.data(), nbytes) &&
+             put(acc.data(), sizeof(double) * nsk);
+    }
+    if (!ok || std::fflush(fp.get()) != 0) return fail(e, FSC_E_IO, std::string("write failed: ") + path);
+    return FSC_OK;
+}
+
+int ens_load(fsc_ens *e, const char *path) {
+    std::unique_ptr<FILE, int (*)(FILE *)> fp(std::fopen(path, "rb"), std::fclose);
+    if (!fp) return fail(e, FSC_E_IO, std::string("cannot open ") + path);
+    auto get = [&](void *p, size_t n) { return std::fread(p, 1, n, fp.get()) == n; };
+    uint32_t head[4];
+    int64_t step = 0;
+    if (!get(head, sizeof(head)) || !get(&step, sizeof(step)) || head[0] != kCkptMagic)
+        return fail(e, FSC_E_IO, std::string("not a checkpoint: ") + path);
+    if (head[1] != kCkptVersion) return fail(e, FSC_E_IO, "unsupported checkpoint version");
+    if (head[2] != e->reps.size()) return fail(e, FSC_E_INVAL, "checkpoint holds another replica count");
+    if (step < 0) return fail(e, FSC_E_IO, "corrupt checkpoint step");
+    // read and check the whole file before any device state changes
+    const size_t n = e->reps.size();
+    std::vector<std::vector<unsigned char>> raws(n);
+    std::vector<std::vector<double>> accs(n);
+    std::vector<int64_t> ns(n);
+    for (size_t k = 0; k < n; ++k) {
+        const Rep &r = e->reps[k];
+        fsc_params p;
+        uint64_t nsk = 0, nbytes = 0;
+        if (!get(&p, sizeof(p)) || !get(&ns[k], sizeof(int64_t)) || !get(&nsk, sizeof(nsk)) ||
+            !get(&nbytes, sizeof(nbytes)))
+            return fail(e, FSC_E_IO, "truncated checkpoint");
+        if (!same_run(p, r.p))
+            return fail(e, FSC_E_INVAL,
+                        "checkpoint replica " + std::to_string(k) + " was written with other parameters");
+        if (nsk != sk_len(r) || nbytes != uint64_t(r.esz) * r.Q * r.N || ns[k] < 0)
+            return fail(e, FSC_E_IO, "checkpoint sizes do not match the lattice");
+        raws[k].resize(nbytes);
+        accs[k].resize(nsk);
+        if (!get(raws[k].data(), nbytes) || !get(accs[k].data(), sizeof(double) * nsk))
+            return fail(e, FSC_E_IO, "truncated checkpoint");
+    }
+    const int par = int(step & 1);
+    for (size_t k = 0; k < n; ++k) {
+        Rep &r = e->reps[k];
+        HIPCHK(e, hipMemcpyAsync(r.buf[par], raws[k].data(), raws[k].size(), hipMemcpyHostToDevice,
+                                 e->stream));
+        HIPCHK(e, hipMemcpyAsync(r.d_sk, accs[k].data(), sizeof(double) * accs[k].size(),
+                                 hipMemcpyHostToDevice, e->stream));
+        r.nsamples = ns[k];
+    }
+    return set_step_device(e, step);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -790,6 +881,7 @@ const char *fsc_strerror(int code) {
     case FSC_E_DIVERGED: return "diverged (non-finite or non-positive density)";
     case FSC_E_STATE: return "invalid state";
     case FSC_E_NOTSUP: return "not supported";
+    case FSC_E_IO: return "file error";
     default: return "unknown error";
     }
 }
@@ -960,6 +1052,18 @@ int fsc_ens_read_sk(fsc_ens *ens, int replica, int kind, double *sum, double *su
     return rc ? rc : ens_read_sk(ens, replica, kind, sum, sumsq, count, nbins);
 }
 int fsc_ens_sk_reset(fsc_ens *ens) { return ens ? ens_sk_reset(ens) : FSC_E_INVAL; }
+int fsc_ens_save(fsc_ens *ens, const char *path) {
+    return ens && path ? ens_save(ens, path) : FSC_E_INVAL;
+}
+int fsc_ens_load(fsc_ens *ens, const char *path) {
+    return ens && path ? ens_load(ens, path) : FSC_E_INVAL;
+}
+int fsc_save(fsc_ctx *ctx, const char *path) {
+    return ctx && path ? ens_save(ctx->e, path) : FSC_E_INVAL;
+}
+int fsc_load(fsc_ctx *ctx, const char *path) {
+    return ctx && path ? ens_load(ctx->e, path) : FSC_E_INVAL;
+}
 
 // ---- time series ----------------------------------------------------------
 int fsc_series_enable(fsc_ctx *ctx, int capacity) {
@@ -1000,6 +1104,112 @@ static int get_tiling(const fsc_ens *e, int *out4) {
 }
 int fsc_get_tiling(const fsc_ctx *ctx, int *out4) { return ctx ? get_tiling(ctx->e, out4) : FSC_E_INVAL; }
 int fsc_ens_get_tiling(const fsc_ens *ens, int *out4) { return ens ? get_tiling(ens, out4) : FSC_E_INVAL; }
+
+// ---- coarse-graining and field measurement (surrogate inputs/outputs) ---
+int fsc_coarsen(fsc_ctx *ctx, int factor, float *dev_out) {
+    if (!ctx || !dev_out) return FSC_E_INVAL;
+    fsc_ens *e = ctx->e;
+    Rep &r = e->reps[0];
+    if (r.p.D != 2 || factor < 1 || r.p.nx % factor || r.p.ny % factor)
+        return fail(e, FSC_E_INVAL, "coarsening needs a 2D lattice with sides divisible by factor");
+    HIPCHK(e, launch_coarsen(r.geom(), r.p.precision, r.buf[e->step & 1], r.p.rho0, factor, dev_out,
+                             e->stream));
+    return FSC_OK;
+}
+
+int fsc_ens_coarsen(fsc_ens *ens, int replica, int factor, float *dev_out) {
+    if (!ens || !dev_out) return FSC_E_INVAL;
+    int rc = rep_index(ens, replica);
+    if (rc) return rc;
+    Rep &r = ens->reps[replica];
+    if (r.p.D != 2 || factor < 1 || r.p.nx % factor || r.p.ny % factor)
+        return fail(ens, FSC_E_INVAL, "coarsening needs a 2D lattice with sides divisible by factor");
+    HIPCHK(ens, launch_coarsen(r.geom(), r.p.precision, r.buf[ens->step & 1], r.p.rho0, factor,
+                               dev_out, ens->stream));
+    return FSC_OK;
+}
+
+int fsc_field_sk(const float *dev_fields, int batch, int ny, int nx, void *stream,
+                 double *host_shell_mean, double *host_L, int nbins) {
+    if (!dev_fields || batch < 1 || nx < 2 || ny < 2 || nx != ny || nx > 8192) return FSC_E_INVAL;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    auto round_sqrt = [](int64_t m) {
+        int64_t b = int64_t(std::sqrt(double(m)));
+        while (b * b > m) --b;
+        while ((b + 1) * (b + 1) <= m) ++b;
+        if (m - b * b > b) ++b;
+        return int(b);
+    };
+    const int L = nx;
+    const int nrad = round_sqrt(2 * int64_t(L / 2) * (L / 2)) + 1;
+    if (nbins != nrad) return FSC_E_INVAL;
+    std::vector<int64_t> modes(nrad, 0);
+    for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x) {
+            const int64_t mx = x <= L / 2 ? x : x - L, my = y <= L / 2 ? y : y - L;
+            if (mx || my) modes[round_sqrt(mx * mx + my * my)] += 1;
+        }
+    const int64_t N = int64_t(nx) * ny;
+    void *ca = nullptr, *cb = nullptr, *tw = nullptr;
+    double *acc = nullptr;
+    int *cnt = nullptr;
+    const size_t nacc = 2 * size_t(2 * (L / 2 + 1)) + 2 * size_t(nrad) + 2 + size_t(2 + nrad);
+    if (hipMalloc(&ca, 8 * N) != hipSuccess || hipMalloc(&cb, 8 * N) != hipSuccess ||
+        hipMalloc(&tw, 8 * twiddle_len(L)) != hipSuccess ||
+        hipMalloc(&acc, sizeof(double) * nacc) != hipSuccess ||
+        hipMalloc(&cnt, sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        for (void *p : {ca, cb, tw, (void *)acc, (void *)cnt})
+            if (p) (void)hipFree(p);
+        return FSC_E_OOM;
+    }
+    hipError_t ec = launch_twiddles(0, tw, L, st);
+    std::vector<double> host(nacc);
+    const Geometry g{2, nx, ny, 1, N};
+    const int na = L / 2 + 1;
+    for (int b = 0; b < batch && ec == hipSuccess; ++b) {
+        ec = hipMemsetAsync(acc, 0, sizeof(double) * nacc, st);
+        if (ec == hipSuccess) ec = hipMemsetAsync(cnt, 0, sizeof(int), st);
+        if (ec == hipSuccess) ec = launch_field_cplx(dev_fields + size_t(b) * N, int(N), ca, st);
+        if (ec == hipSuccess) ec = launch_fft_axis(0, ca, cb, tw, nx, ny, 1, st);
+        if (ec == hipSuccess) ec = launch_fft_axis(0, cb, ca, tw, ny, nx, 1, st);
+        BinTargets t;
+        t.axis_sum = acc;
+        t.axis_sq = acc + 2 * na;
+        t.rad_sum = acc + 4 * na;
+        t.rad_sq = acc + 4 * na + nrad;
+        t.n_axis = na;
+        t.n_rad = nrad;
+        t.mom = acc + 4 * na + 2 * nrad;
+        t.series = acc + 4 * na + 2 * nrad + 2;
+        t.series_n = cnt;
+        t.series_cap = 1;
+        if (ec == hipSuccess) ec = launch_bin(g, 0, ca, t, st);
+        if (ec == hipSuccess)
+            ec = hipMemcpyAsync(host.data(), acc, sizeof(double) * nacc, hipMemcpyDeviceToHost, st);
+        if (ec == hipSuccess) ec = hipStreamSynchronize(st);
+        if (ec != hipSuccess) break;
+        const double *rs = host.data() + 4 * na;
+        const double *mom = host.data() + 4 * na + 2 * nrad;
+        for (int k = 0; k < nrad; ++k)
+            if (host_shell_mean)
+                host_shell_mean[size_t(b) * nrad + k] = modes[k] ? rs[k] / double(modes[k]) : 0.0;
+        if (host_L) host_L[b] = mom[1] > 0.0 ? 2.0 * M_PI * mom[0] / mom[1] : 0.0;
+    }
+    for (void *p : {ca, cb, tw, (void *)acc, (void *)cnt}) (void)hipFree(p);
+    return ec == hipSuccess ? FSC_OK : FSC_E_HIP;
+}
+
+int fsc_field_nbins(int n, int *nbins) {
+    if (n < 2 || !nbins) return FSC_E_INVAL;
+    int64_t m = 2 * int64_t(n / 2) * (n / 2);
+    int64_t b = int64_t(std::sqrt(double(m)));
+    while (b * b > m) --b;
+    while ((b + 1) * (b + 1) <= m) ++b;
+    if (m - b * b > b) ++b;
+    *nbins = int(b) + 1;
+    return FSC_OK;
+}
 
 // ---- diagnostics ----------------------------------------------------------
 int fsc_copy(const void *dev_src, void *dev_dst, int64_t bytes, void *stream) {

@@ -116,10 +116,21 @@ __host__ __device__ constexpr double moment_norm(int a) {
     for (int i = 0; i < L::Q; ++i) s += L::w(i) * double(L::M(a, i)) * double(L::M(a, i));
     return s;
 }
-template <class L>
-__host__ __device__ constexpr double back_coef(int i, int a) {
-    return L::w(i) * double(L::M(a, i)) / moment_norm<L>(a);
+
+// sqrt(b_a), by Newton's iteration at compile time: the noise of row a is
+// sqrt(b_a) times a per-class amplitude.
+__host__ __device__ constexpr double const_sqrt(double x) {
+    double r = x > 1.0 ? x : 1.0;
+    for (int k = 0; k < 64; ++k) r = 0.5 * (r + x / r);
+    return r;
 }
+template <class L>
+struct RowScale {
+    double v[19];
+    __host__ __device__ constexpr RowScale() : v{} {
+        for (int a = 0; a < L::Q; ++a) v[a] = const_sqrt(moment_norm<L>(a));
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Interaction stencils of Eq. (1), as half sets (one of each +-e pair).
@@ -271,8 +282,13 @@ struct RepDesc {
     int32_t noise;           // kBT > 0
     int32_t pad0;
     double G, rho0, psi0;
-    double lam[19];          // relaxation rate per moment row
-    double amp[19];          // sqrt(kBT/c_s^2 * b_a * (1 - (1-lam_a)^2)) per row (0: conserved)
+    // Per moment class c (1 bulk, 2 shear, 3 ghost; 0 = conserved, unused):
+    // relaxation rate lam_c and noise amplitude sqrt(kBT/c_s^2 (1 - (1-lam_c)^2));
+    // row a of class c gets noise sqrt(b_a) amp_c sqrt(n) xi_a.
+    double lamc[4], ampc[4];
+    // float copies for the FP32 kernels (wave-uniform, kept in scalar registers)
+    float Gf, rho0f, psi0f, inv_rho0f;
+    float lamcf[4], ampcf[4];
     uint32_t key0, key1, seed_hi, pad1;
 };
 

@@ -87,6 +87,12 @@ hipError_t launch_series_finalize(double *mom, double *series, int *series_n, in
                                   int row_len, const uint64_t *step_base, uint32_t step_off,
                                   hipStream_t s);
 
+// Block means of the density over f x f blocks (2D) into out[(ny/f) x (nx/f)].
+hipError_t launch_coarsen(const Geometry &g, int precision, const void *buf, double rho0, int f,
+                          float *out, hipStream_t s);
+// Real field -> interleaved complex float.
+hipError_t launch_field_cplx(const float *f, int n, void *c, hipStream_t s);
+
 // Plain copy of `bytes` (multiple of 16) bytes.
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
 

@@ -8,7 +8,8 @@
 //
 //   for each plane s of the march (upwards in even chunks, downwards in odd):
 //     wait for the pulled populations f_i(x - c_i) of plane s + R (R = stencil
-//       radius, ahead in march direction; loads issued PF planes earlier), form
+//       radius, ahead in march direction; loads issued PF planes earlier, or
+//       just now when PF = 0), form
 //       n and write
 //       dpsi = psi(n) - psi(n0) = psi0 expm1(dn / (n0 n)) for the tile and its
 //       R-wide cross-section ring into an LDS ring buffer of 2R + 2 planes;
@@ -81,7 +82,7 @@ __device__ __forceinline__ double fexpm1(double x) { return expm1(x); }
 // ---------------------------------------------------------------------------
 template <typename real, bool NOISE>
 __device__ __forceinline__ void collide_d2q9(real (&f)[9], real rho0, const real F[3],
-                                             const real (&lam)[9], const real (&amp)[9],
+                                             const real (&lc)[4], const real (&ac)[4],
                                              const real (&z)[6]) {
     const real s13 = f[1] + f[3], d13 = f[1] - f[3];
     const real s24 = f[2] + f[4], d24 = f[2] - f[4];
@@ -105,11 +106,24 @@ __device__ __forceinline__ void collide_d2q9(real (&f)[9], real rho0, const real
     const real uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
     const real uFx = ux * F[0], uFy = uy * F[1];
 
-    real sr = real(0);
-    if constexpr (NOISE) sr = fsqrt(rho);
+    // noise: row a of class c adds sqrt(b_a) amp_c sqrt(n) xi_a
+    constexpr RowScale<D2Q9> sb{};
+    real sa[4] = {real(0), real(0), real(0), real(0)};
+    if constexpr (NOISE) {
+        const real sr = fsqrt(rho);
+        sa[1] = ac[1] * sr;
+        sa[2] = ac[2] * sr;
+        sa[3] = ac[3] * sr;
+    }
     auto relax = [&](int a, real m, real meq, real src, real zz) {
-        real o = m + lam[a] * (meq - m) + (real(1) - real(0.5) * lam[a]) * src;
-        if constexpr (NOISE) o += amp[a] * sr * zz;
+        const real l = lc[D2Q9::cls(a)];
+        real o = m + l * (meq - m) + (real(1) - real(0.5) * l) * src;
+        if constexpr (NOISE) o += real(sb.v[a]) * sa[D2Q9::cls(a)] * zz;
+        return o;
+    };
+    auto ghost = [&](int a, real m, real zz) {
+        real o = (real(1) - lc[3]) * m;
+        if constexpr (NOISE) o += real(sb.v[a]) * sa[3] * zz;
         return o;
     };
     // post-collision moments, each divided by its norm b_a
@@ -119,13 +133,9 @@ __device__ __forceinline__ void collide_d2q9(real (&f)[9], real rho0, const real
     const real n3 = relax(3, m3, real(3) * rho * (uxx + uyy), real(6) * (uFx + uFy), z[0]) * real(0.25);
     const real n4 = relax(4, m4, rho * (uxx - uyy), real(2) * (uFx - uFy), z[1]) * real(2.25);
     const real n5 = relax(5, m5, rho * uxy, ux * F[1] + uy * F[0], z[2]) * real(9);
-    real g6 = (real(1) - lam[6]) * m6, g7 = (real(1) - lam[7]) * m7, g8 = (real(1) - lam[8]) * m8;
-    if constexpr (NOISE) {
-        g6 += amp[6] * sr * z[3];
-        g7 += amp[7] * sr * z[4];
-        g8 += amp[8] * sr * z[5];
-    }
-    const real n6 = g6 * real(1.5), n7 = g7 * real(1.5), n8 = g8 * real(0.0625);
+    const real n6 = ghost(6, m6, z[3]) * real(1.5);
+    const real n7 = ghost(7, m7, z[4]) * real(1.5);
+    const real n8 = ghost(8, m8, z[5]) * real(0.0625);
 
     // back-transform f_i = w_i sum_a M_ai n_a
     const real w0 = real(4.0 / 9.0), w1 = real(1.0 / 9.0), w5 = real(1.0 / 36.0);
@@ -148,75 +158,130 @@ __device__ __forceinline__ void collide_d2q9(real (&f)[9], real rho0, const real
 }
 
 // ---------------------------------------------------------------------------
-// Generic collision on the constexpr basis of a lattice (used for D3Q19).
+// D3Q19 collision on the weight-orthogonal basis (rows as in fsc_device.h),
+// written with the sums s and differences d of opposite populations: even
+// rows see only sums, odd rows only differences, and the back-transform
+// gives each opposite pair as w (E +- O) from its even and odd parts.
 // ---------------------------------------------------------------------------
-template <class L, typename real, bool NOISE>
-__device__ __forceinline__ void collide_generic(real (&f)[L::Q], real rho0, const real F[3],
-                                                const real (&lam)[L::Q], const real (&amp)[L::Q],
-                                                const real (&z)[L::NNORM]) {
-    constexpr int D = L::D, Q = L::Q;
-    real dn = real(0);
-    real j[3] = {real(0), real(0), real(0)};
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        dn += f[i];
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
-            if (L::c(i, q) == 1) j[q] += f[i];
-            if (L::c(i, q) == -1) j[q] -= f[i];
-        }
-    }
+template <typename real, bool NOISE>
+__device__ __forceinline__ void collide_d3q19(real (&f)[19], real rho0, const real F[3],
+                                              const real (&lc)[4], const real (&ac)[4],
+                                              const real (&z)[15]) {
+    const real sx = f[1] + f[2], dx = f[1] - f[2];
+    const real sy = f[3] + f[4], dy = f[3] - f[4];
+    const real sz = f[5] + f[6], dz = f[5] - f[6];
+    const real S1 = f[7] + f[8], D1 = f[7] - f[8];      // +-(1, 1, 0)
+    const real S2 = f[9] + f[10], D2 = f[9] - f[10];    // +-(1,-1, 0)
+    const real S3 = f[11] + f[12], D3 = f[11] - f[12];  // +-(1, 0, 1)
+    const real S4 = f[13] + f[14], D4 = f[13] - f[14];  // +-(1, 0,-1)
+    const real S5 = f[15] + f[16], D5 = f[15] - f[16];  // +-(0, 1, 1)
+    const real S6 = f[17] + f[18], D6 = f[17] - f[18];  // +-(0, 1,-1)
+    const real Sxy = S1 + S2, Sxz = S3 + S4, Syz = S5 + S6;
+    const real Sd = Sxy + Sxz + Syz, Sa = sx + sy + sz;
+    const real dn = f[0] + Sa + Sd;
+    const real Dx4 = D1 + D2 + D3 + D4;
+    const real Dy4 = D1 - D2 + D5 + D6;
+    const real Dz4 = D3 - D4 + D5 - D6;
+    const real jx = dx + Dx4, jy = dy + Dy4, jz = dz + Dz4;
+    const real m4 = Sd - f[0];
+    const real m5 = real(2) * sx - sy - sz + Sxy + Sxz - real(2) * Syz;
+    const real m6 = sy - sz + Sxy - Sxz;
+    const real m7 = S1 - S2, m8 = S5 - S6, m9 = S3 - S4;
+    const real m10 = Dx4 - real(2) * dx, m11 = Dy4 - real(2) * dy, m12 = Dz4 - real(2) * dz;
+    const real m13 = D1 + D2 - D3 - D4;
+    const real m14 = D2 - D1 + D5 + D6;
+    const real m15 = D3 - D4 - D5 + D6;
+    const real m16 = f[0] - real(2) * Sa + Sd;
+    const real m17 = sy + sz - real(2) * sx + Sxy + Sxz - real(2) * Syz;
+    const real m18 = sz - sy + Sxy - Sxz;
+
     const real rho = rho0 + dn;
     const real ir = fast_rcp(rho);
-    real u[3] = {real(0), real(0), real(0)};
-#pragma unroll
-    for (int q = 0; q < D; ++q) u[q] = (j[q] + real(0.5) * F[q]) * ir;
-    real sr = real(0);
-    if constexpr (NOISE) sr = fsqrt(rho);
+    const real ux = (jx + real(0.5) * F[0]) * ir;
+    const real uy = (jy + real(0.5) * F[1]) * ir;
+    const real uz = (jz + real(0.5) * F[2]) * ir;
+    const real uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
+    const real uFx = ux * F[0], uFy = uy * F[1], uFz = uz * F[2];
 
-    real ms[Q];
-    ms[0] = dn;
-#pragma unroll
-    for (int q = 0; q < D; ++q) ms[1 + q] = j[q] + F[q];
-#pragma unroll
-    for (int a = D + 1; a < Q; ++a) {
-        real m = real(0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int c = L::M(a, i);
-            if (c == 1) m += f[i];
-            else if (c == -1) m -= f[i];
-            else if (c != 0) m += real(c) * f[i];
-        }
-        real out;
-        if (L::cls(a) == 3) {
-            out = (real(1) - lam[a]) * m;
-        } else {
-            real uAu = real(0), uAF = real(0);
-#pragma unroll
-            for (int p = 0; p < D; ++p)
-#pragma unroll
-                for (int q = 0; q < D; ++q) {
-                    const double A = L::A(a, p, q);
-                    if (A != 0.0) {
-                        uAu += real(A) * u[p] * u[q];
-                        uAF += real(A) * u[p] * F[q];
-                    }
-                }
-            out = m + lam[a] * (rho * uAu - m) + (real(1) - real(0.5) * lam[a]) * (real(2) * uAF);
-        }
-        if constexpr (NOISE) out += amp[a] * sr * z[a - D - 1];
-        ms[a] = out;
+    constexpr RowScale<D3Q19> sb{};
+    real sa[4] = {real(0), real(0), real(0), real(0)};
+    if constexpr (NOISE) {
+        const real sr = fsqrt(rho);
+        sa[1] = ac[1] * sr;
+        sa[2] = ac[2] * sr;
+        sa[3] = ac[3] * sr;
     }
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        real v = real(0);
-#pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            if (L::M(a, i) != 0) v += real(back_coef<L>(i, a)) * ms[a];
-        }
-        f[i] = v;
-    }
+    auto relax = [&](int a, real m, real meq, real src, real zz) {
+        const real l = lc[D3Q19::cls(a)];
+        real o = m + l * (meq - m) + (real(1) - real(0.5) * l) * src;
+        if constexpr (NOISE) o += real(sb.v[a]) * sa[D3Q19::cls(a)] * zz;
+        return o;
+    };
+    auto ghost = [&](int a, real m, real zz) {
+        real o = (real(1) - lc[3]) * m;
+        if constexpr (NOISE) o += real(sb.v[a]) * sa[3] * zz;
+        return o;
+    };
+    // post-collision moments divided by their norms
+    const real n0 = dn;
+    const real n1 = (jx + F[0]) * real(3), n2 = (jy + F[1]) * real(3), n3 = (jz + F[2]) * real(3);
+    const real n4 = relax(4, m4, rho * (uxx + uyy + uzz), real(2) * (uFx + uFy + uFz), z[0]) * real(1.5);
+    const real n5 = relax(5, m5, rho * (real(2) * uxx - uyy - uzz),
+                          real(2) * (real(2) * uFx - uFy - uFz), z[1]) * real(0.75);
+    const real n6 = relax(6, m6, rho * (uyy - uzz), real(2) * (uFy - uFz), z[2]) * real(2.25);
+    const real n7 = relax(7, m7, rho * ux * uy, ux * F[1] + uy * F[0], z[3]) * real(9);
+    const real n8 = relax(8, m8, rho * uy * uz, uy * F[2] + uz * F[1], z[4]) * real(9);
+    const real n9 = relax(9, m9, rho * uz * ux, uz * F[0] + ux * F[2], z[5]) * real(9);
+    const real n10 = ghost(10, m10, z[6]) * real(1.5);
+    const real n11 = ghost(11, m11, z[7]) * real(1.5);
+    const real n12 = ghost(12, m12, z[8]) * real(1.5);
+    const real n13 = ghost(13, m13, z[9]) * real(4.5);
+    const real n14 = ghost(14, m14, z[10]) * real(4.5);
+    const real n15 = ghost(15, m15, z[11]) * real(4.5);
+    const real n16 = ghost(16, m16, z[12]) * real(0.5);
+    const real n17 = ghost(17, m17, z[13]) * real(0.75);
+    const real n18 = ghost(18, m18, z[14]) * real(2.25);
+
+    // back-transform f_i = w_i sum_a M_ai n_a, pairwise
+    const real w0 = real(1.0 / 3.0), w1 = real(1.0 / 18.0), w2 = real(1.0 / 36.0);
+    f[0] = w0 * (n0 - n4 + n16);
+    const real e0 = n0 - real(2) * n16;
+    const real Ex = e0 + real(2) * (n5 - n17), Ox = n1 - real(2) * n10;
+    const real eyz = e0 - n5 + n17;
+    const real Ey = eyz + n6 - n18, Oy = n2 - real(2) * n11;
+    const real Ez = eyz - n6 + n18, Oz = n3 - real(2) * n12;
+    f[1] = w1 * (Ex + Ox);
+    f[2] = w1 * (Ex - Ox);
+    f[3] = w1 * (Ey + Oy);
+    f[4] = w1 * (Ey - Oy);
+    f[5] = w1 * (Ez + Oz);
+    f[6] = w1 * (Ez - Oz);
+    const real ed = n0 + n4 + n16;
+    const real exy = ed + n5 + n6 + n17 + n18;   // pairs 1, 2 (before the +-n7 term)
+    const real exz = ed + n5 - n6 + n17 - n18;   // pairs 3, 4 (+-n9)
+    const real eyz2 = ed - real(2) * (n5 + n17); // pairs 5, 6 (+-n8)
+    const real E1 = exy + n7, E2 = exy - n7;
+    const real E3 = exz + n9, E4 = exz - n9;
+    const real E5 = eyz2 + n8, E6 = eyz2 - n8;
+    const real ax = n1 + n10, ay = n2 + n11, az = n3 + n12;
+    const real O1 = ax + ay + n13 - n14;
+    const real O2 = ax - ay + n13 + n14;
+    const real O3 = ax + az - n13 + n15;
+    const real O4 = ax - az - n13 - n15;
+    const real O5 = ay + az + n14 - n15;
+    const real O6 = ay - az + n14 + n15;
+    f[7] = w2 * (E1 + O1);
+    f[8] = w2 * (E1 - O1);
+    f[9] = w2 * (E2 + O2);
+    f[10] = w2 * (E2 - O2);
+    f[11] = w2 * (E3 + O3);
+    f[12] = w2 * (E3 - O3);
+    f[13] = w2 * (E4 + O4);
+    f[14] = w2 * (E4 - O4);
+    f[15] = w2 * (E5 + O5);
+    f[16] = w2 * (E5 - O5);
+    f[17] = w2 * (E6 + O6);
+    f[18] = w2 * (E6 - O6);
 }
 
 // ---------------------------------------------------------------------------
@@ -273,15 +338,16 @@ __global__ void __launch_bounds__(TX *TY)
     const rsrc_t dst = make_rsrc(d.buf[parity ^ 1], buf_bytes);
     const uint32_t pop_bytes = uint32_t(d.N) * ES;  // < 2^31 (checked on the host)
 
-    const real rho0 = real(d.rho0);
-    const real psi0 = real(d.psi0);
-    const real G = real(d.G);
-    const real inv_rho0 = real(1.0 / d.rho0);
-    real lam[Q], amp[Q];
+    constexpr bool F32 = sizeof(real) == 4;
+    const real rho0 = F32 ? real(d.rho0f) : real(d.rho0);
+    const real psi0 = F32 ? real(d.psi0f) : real(d.psi0);
+    const real G = F32 ? real(d.Gf) : real(d.G);
+    const real inv_rho0 = F32 ? real(d.inv_rho0f) : real(1.0 / d.rho0);
+    real lc[4], ac[4];
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-        lam[a] = real(d.lam[a]);
-        amp[a] = real(d.amp[a]);
+    for (int k = 0; k < 4; ++k) {
+        lc[k] = F32 ? real(d.lamcf[k]) : real(d.lamc[k]);
+        ac[k] = F32 ? real(d.ampcf[k]) : real(d.ampc[k]);
     }
 
     // ---- per-lane pull offsets (bytes, within a plane), by (c_x, c_y) ------
@@ -371,7 +437,15 @@ __global__ void __launch_bounds__(TX *TY)
 
     // ---- prologue: planes first - dir R .. first + dir (R - 1) ---------------
     real F[NSLOT][Q];
+    // The ring plane is prefetched one plane ahead unless the main planes are
+    // not prefetched either (PF = 0, the register-lean form).
+    constexpr bool RING_PF = PF > 0;
+    // Ring-plane registers.  Lanes without a ring node never load them; they
+    // still get a defined value, so that no lane carries an undefined value
+    // through the march loop.
     real RG[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) RG[i] = real(0);
 #pragma unroll
     for (int k = -R; k < R; ++k) {
         real tm[Q];
@@ -384,7 +458,7 @@ __global__ void __launch_bounds__(TX *TY)
         }
     }
     // prefetch: ring plane first + dir R, main planes first + dir (R + q), q < PF
-    if (has_ring) load_plane(first + dir * R, xo_r, RG);
+    if (RING_PF && has_ring) load_plane(first + dir * R, xo_r, RG);
 #pragma unroll
     for (int q = 0; q < PF; ++q)
         if (q < len) load_plane(first + dir * (R + q), xo_m, F[R + q]);
@@ -398,10 +472,13 @@ __global__ void __launch_bounds__(TX *TY)
             if (m >= len) break;
             const int s = first + dir * m;
             // plane s + dir R has arrived: its dpsi goes to LDS
+            // PF = 0: plane s + dir R is loaded here, right before its dpsi is needed
+            if constexpr (PF == 0) load_plane(s + dir * R, xo_m, F[(j + R) % NSLOT]);
+            if (!RING_PF && has_ring) load_plane(s + dir * R, xo_r, RG);
             put_psi(s + dir * R, F[(j + R) % NSLOT], RG);
             // prefetch: ring plane s + dir (R + 1), main plane s + dir (R + PF)
-            if (has_ring && m + 1 < len) load_plane(s + dir * (R + 1), xo_r, RG);
-            if (m + PF < len) load_plane(s + dir * (R + PF), xo_m, F[(j + R + PF) % NSLOT]);
+            if (RING_PF && has_ring && m + 1 < len) load_plane(s + dir * (R + 1), xo_r, RG);
+            if (PF > 0 && m + PF < len) load_plane(s + dir * (R + PF), xo_m, F[(j + R + PF) % NSLOT]);
             __syncthreads();
 
             int sl[2 * R + 1];
@@ -434,8 +511,8 @@ __global__ void __launch_bounds__(TX *TY)
                 for (int k = 0; k < NN; ++k) z[k] = real(0);
             }
             real(&fv)[Q] = F[j % NSLOT];
-            if constexpr (D == 2) collide_d2q9<real, NOISE>(fv, rho0, Fv, lam, amp, z);
-            else collide_generic<L, real, NOISE>(fv, rho0, Fv, lam, amp, z);
+            if constexpr (D == 2) collide_d2q9<real, NOISE>(fv, rho0, Fv, lc, ac, z);
+            else collide_d3q19<real, NOISE>(fv, rho0, Fv, lc, ac, z);
 
             const uint32_t so = uint32_t(s) * pbytes + lane_store;
 #pragma unroll

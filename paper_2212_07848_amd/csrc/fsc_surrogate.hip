@@ -1,0 +1,851 @@
+// fsc_surrogate.hip -- learned coarse-grained surrogate of the phase-separating
+// lattice: a small periodic convolutional network that maps the block-averaged
+// density at time t to the one at t + k lattice steps.  Not part of the paper:
+// it is the inference/training path next to the lattice, judged against the
+// lattice's own S(k, t) and L(t).
+//
+// Network (C = 32 hidden channels, L layers):
+//   x = (rho - mean)/in_scale;  a_0 = SiLU(conv(x));  a_l = SiLU(conv(a_{l-1}))
+//   y = conv(a_{L-2});  rho' = rho + out_scale (y - <y>_image)
+// conv = 3x3 cross-correlation with circular padding.  The C -> C layers run
+// as implicit GEMMs on v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32
+// accumulation), forward, backward-data and backward-weight; the 1 -> C and
+// C -> 1 layers and the reductions are FP32 vector code.  Parameters are FP32
+// masters updated by Adam; BF16 copies feed the matrix cores.
+//
+// Activations are NHWC: pixel p = (n H + y) W + x, channel fastest.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fsc.h"
+#include "fsc_internal.h"
+
+namespace fsc {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int SC = 32;  // hidden channels
+
+__device__ __forceinline__ float silu(float z) { return z / (1.f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+    const float s = 1.f / (1.f + __expf(-z));
+    return s * (1.f + z * (1.f - s));
+}
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// ---------------------------------------------------------------------------
+// Matrix-core operand layout of v_mfma_f32_16x16x32_bf16 as used here: lane l
+// supplies row (l % 16) of A and column (l % 16) of B with the eight K values
+// 8 (l / 16) .. 8 (l / 16) + 7; the result element D[4 (l / 16) + r][l % 16] is
+// register r of lane l.  (Any K order that is the same for A and B gives the
+// same product; the M/N/D placement is checked by fsc_mfma_probe.)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__global__ void k_mfma_probe(const float *A, const float *B, float *Cm) {
+    const int l = threadIdx.x, r16 = l & 15, g = l >> 4;
+    bf16x8 a, b;
+    for (int e = 0; e < 8; ++e) {
+        a[e] = bf16(A[r16 * 32 + 8 * g + e]);
+        b[e] = bf16(B[(8 * g + e) * 16 + r16]);
+    }
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+    c = mfma16(a, b, c);
+    for (int r = 0; r < 4; ++r) Cm[(4 * g + r) * 16 + r16] = c[r];
+}
+
+// ---------------------------------------------------------------------------
+// Layer 0 (1 -> C) forward, FP32: one thread per pixel.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_first(const float *__restrict__ in, int B, int H, int W,
+                                               float mean, float inv_scale,
+                                               const float *__restrict__ w,
+                                               const float *__restrict__ b, float *__restrict__ z,
+                                               bf16 *__restrict__ a) {
+    const int P = B * H * W;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const int x = p % W, t = p / W, y = t % H, n = t / H;
+    float xi[9];
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx)
+            xi[ky * 3 + kx] =
+                (in[(n * H + wrapi(y + ky - 1, H)) * W + wrapi(x + kx - 1, W)] - mean) * inv_scale;
+#pragma unroll
+    for (int co = 0; co < SC; ++co) {
+        float acc = b[co];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc += w[co * 9 + k] * xi[k];
+        z[size_t(p) * SC + co] = acc;
+        a[size_t(p) * SC + co] = bf16(silu(acc));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// C -> C layer on the matrix cores.  A wave computes 16 consecutive pixels of
+// one image row for all 32 output channels: 9 taps x 2 column tiles of
+// 16x16x32 MFMA, with the packed weights held in registers.
+//   forward:   out = conv(a_in; W) + bias -> z (FP32), SiLU(z) (BF16)
+//   backward:  out = conv(dZ; W') (W' = tap-flipped transpose: the adjoint)
+//              -> dZ_prev = out * SiLU'(z_prev) (BF16)
+// ---------------------------------------------------------------------------
+template <bool BWD>
+__global__ void __launch_bounds__(256) k_mid(const bf16 *__restrict__ ain,
+                                             const bf16 *__restrict__ wpk,
+                                             const float *__restrict__ bias, int B, int H, int W,
+                                             float *__restrict__ zout, bf16 *__restrict__ aout,
+                                             const float *__restrict__ zprev) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * 4;
+    const int r16 = lane & 15, g = lane >> 4;
+    bf16x8 bop[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+            bop[t][nt] = *reinterpret_cast<const bf16x8 *>(wpk + (t * SC + nt * 16 + r16) * SC + g * 8);
+    float bv[2] = {0.f, 0.f};
+    if (!BWD) {
+        bv[0] = bias[r16];
+        bv[1] = bias[16 + r16];
+    }
+    const int tiles = (B * H * W) / 16;
+    for (int tile = wave; tile < tiles; tile += nwaves) {
+        const int p0 = tile * 16;
+        const int x0 = p0 % W, t2 = p0 / W, y = t2 % H, n = t2 / H;
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            const int rowbase = (n * H + wrapi(y + ky - 1, H)) * W;
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const int q = rowbase + wrapi(x0 + r16 + kx - 1, W);
+                const bf16x8 aop = *reinterpret_cast<const bf16x8 *>(ain + size_t(q) * SC + g * 8);
+                acc0 = mfma16(aop, bop[ky * 3 + kx][0], acc0);
+                acc1 = mfma16(aop, bop[ky * 3 + kx][1], acc1);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const size_t pix = size_t(p0 + 4 * g + r);
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const int co = nt * 16 + r16;
+                const float v = nt ? acc1[r] : acc0[r];
+                if (BWD) {
+                    aout[pix * SC + co] = bf16(v * dsilu(zprev[pix * SC + co]));
+                } else {
+                    const float zz = v + bv[nt];
+                    zout[pix * SC + co] = zz;
+                    aout[pix * SC + co] = bf16(silu(zz));
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Last layer (C -> 1) forward, FP32 from BF16 activations.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_last(const bf16 *__restrict__ a, int B, int H, int W,
+                                              const float *__restrict__ w, const float *__restrict__ b,
+                                              float *__restrict__ y) {
+    const int P = B * H * W;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const int x = p % W, t = p / W, yy = t % H, n = t / H;
+    float acc = b[0];
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            const int q = (n * H + wrapi(yy + ky - 1, H)) * W + wrapi(x + kx - 1, W);
+            const bf16x8 *ap = reinterpret_cast<const bf16x8 *>(a + size_t(q) * SC);
+#pragma unroll
+            for (int c8 = 0; c8 < SC / 8; ++c8) {
+                const bf16x8 v = ap[c8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) acc += w[(c8 * 8 + e) * 9 + ky * 3 + kx] * float(v[e]);
+            }
+        }
+    y[p] = acc;
+}
+
+// per-image sums of a field (one block per image), in FP64
+__global__ void __launch_bounds__(256) k_img_sum(const float *__restrict__ v, int HW,
+                                                 double *__restrict__ out) {
+    __shared__ double sh[4];
+    const float *row = v + size_t(blockIdx.x) * HW;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < HW; i += 256) s += double(row[i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void __launch_bounds__(256) k_pred(const float *__restrict__ in,
+                                              const float *__restrict__ y,
+                                              const double *__restrict__ ysum, int P, int HW,
+                                              float out_scale, float *__restrict__ out) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const float mean = float(ysum[p / HW] / HW);
+    out[p] = in[p] + out_scale * (y[p] - mean);
+}
+
+// loss terms and dL/dyhat; loss accumulated in FP64
+__global__ void __launch_bounds__(256) k_loss(const float *__restrict__ in,
+                                              const float *__restrict__ tgt,
+                                              const float *__restrict__ y,
+                                              const double *__restrict__ ysum, int P, int HW,
+                                              float inv_out_scale, float invM,
+                                              float *__restrict__ gout, double *__restrict__ loss) {
+    __shared__ double sh[4];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    double e2 = 0.0;
+    if (p < P) {
+        const float yhat = y[p] - float(ysum[p / HW] / HW);
+        const float e = yhat - (tgt[p] - in[p]) * inv_out_scale;
+        gout[p] = 2.f * e * invM;
+        e2 = double(e) * double(e);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = e2;
+    __syncthreads();
+    if (threadIdx.x == 0) unsafeAtomicAdd(loss, sh[0] + sh[1] + sh[2] + sh[3]);
+}
+
+// Last layer backward-data: dZ_{L-2}[p][c] = SiLU'(z) sum_t dy[p - off(t)] W[c][t]
+// with dy = g - <g>_image (the mean-free projection's adjoint).
+__global__ void __launch_bounds__(256) k_last_bwd(const float *__restrict__ g,
+                                                  const double *__restrict__ gsum, int B, int H,
+                                                  int W, const float *__restrict__ w,
+                                                  const float *__restrict__ zprev,
+                                                  bf16 *__restrict__ dz) {
+    const int P = B * H * W;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const int x = p % W, t = p / W, yy = t % H, n = t / H;
+    const float gm = float(gsum[n] / (H * W));
+    float dyv[9];
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx)
+            dyv[ky * 3 + kx] = g[(n * H + wrapi(yy - ky + 1, H)) * W + wrapi(x - kx + 1, W)] - gm;
+#pragma unroll
+    for (int c = 0; c < SC; ++c) {
+        float da = 0.f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) da += dyv[k] * w[c * 9 + k];
+        dz[size_t(p) * SC + c] = bf16(da * dsilu(zprev[size_t(p) * SC + c]));
+    }
+}
+
+// Weight gradient of the last layer: dW[c][t] = sum_p dy[p] a[p + off(t)][c],
+// db = sum_p dy[p].  Block: 32 channels x 8 pixel groups; FP32 atomics.
+__global__ void __launch_bounds__(256) k_last_wgrad(const float *__restrict__ g,
+                                                    const double *__restrict__ gsum, int B,
+                                                    int H, int W, const bf16 *__restrict__ a,
+                                                    float *__restrict__ dw, float *__restrict__ db,
+                                                    int chunk) {
+    __shared__ float red[8][SC][10];
+    const int c = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int P = B * H * W;
+    float acc[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int p_begin = blockIdx.x * chunk, p_end = min(P, p_begin + chunk);
+    for (int p = p_begin + grp; p < p_end; p += 8) {
+        const int x = p % W, t = p / W, yy = t % H, n = t / H;
+        const float dy = g[p] - float(gsum[n] / (H * W));
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const int q = (n * H + wrapi(yy + ky - 1, H)) * W + wrapi(x + kx - 1, W);
+                acc[ky * 3 + kx] += dy * float(a[size_t(q) * SC + c]);
+            }
+        acc[9] += dy;
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) red[grp][c][k] = acc[k];
+    __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            float s = 0.f;
+            for (int q = 0; q < 8; ++q) s += red[q][c][k];
+            if (k < 9) atomicAdd(&dw[c * 9 + k], s);
+            else if (c == 0) atomicAdd(db, s);
+        }
+    }
+}
+
+// Weight gradient of layer 0: dW[c][t] = sum_p dZ0[p][c] x[p + off(t)], db[c] = sum dZ0.
+__global__ void __launch_bounds__(256) k_first_wgrad(const bf16 *__restrict__ dz,
+                                                     const float *__restrict__ in, int B, int H,
+                                                     int W, float mean, float inv_scale,
+                                                     float *__restrict__ dw,
+                                                     float *__restrict__ db, int chunk) {
+    __shared__ float red[8][SC][10];
+    const int c = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int P = B * H * W;
+    float acc[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int p_begin = blockIdx.x * chunk, p_end = min(P, p_begin + chunk);
+    for (int p = p_begin + grp; p < p_end; p += 8) {
+        const int x = p % W, t = p / W, yy = t % H, n = t / H;
+        const float d = float(dz[size_t(p) * SC + c]);
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const float xv =
+                    (in[(n * H + wrapi(yy + ky - 1, H)) * W + wrapi(x + kx - 1, W)] - mean) * inv_scale;
+                acc[ky * 3 + kx] += d * xv;
+            }
+        acc[9] += d;
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) red[grp][c][k] = acc[k];
+    __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            float s = 0.f;
+            for (int q = 0; q < 8; ++q) s += red[q][c][k];
+            if (k < 9) atomicAdd(&dw[c * 9 + k], s);
+            else atomicAdd(&db[c], s);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient of a C -> C layer on the matrix cores:
+//   dW[co][ci][t] = sum_p dZ[p][co] a[p + off(t)][ci],  db[co] = sum_p dZ[p][co]
+// a GEMM over K = pixels.  A block stages 32 consecutive pixels of dZ and, for
+// the nine taps, of the shifted activations in LDS, transposed to
+// [channel][pixel] (one copy per horizontal shift keeps 16-byte reads aligned);
+// wave w accumulates taps w, w + 4, w + 8 as 2 x 2 tiles of 16x16x32 MFMA.
+// ---------------------------------------------------------------------------
+constexpr int WSEG = 32;
+constexpr int WPAD = 40;
+
+__global__ void __launch_bounds__(256) k_mid_wgrad(const bf16 *__restrict__ dz,
+                                                   const bf16 *__restrict__ ain, int B, int H,
+                                                   int W, float *__restrict__ dw,
+                                                   float *__restrict__ db) {
+    __shared__ __attribute__((aligned(16))) bf16 sdz[SC][WPAD];
+    __shared__ __attribute__((aligned(16))) bf16 sa[3][3][SC][WPAD];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    f32x4 acc[3][2][2];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) acc[s][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+    const int nseg = (B * H * W) / WSEG;
+    for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+        const int p0 = seg * WSEG;
+        const int x0 = p0 % W, t2 = p0 / W, y = t2 % H, n = t2 / H;
+        __syncthreads();
+        // dZ tile: 32 pixels x 32 channels, 4 values per thread
+        {
+            const int e = tid * 4;
+            const int j = e / SC, c = e % SC;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sdz[c + k][j] = dz[size_t(p0 + j) * SC + c + k];
+        }
+        // shifted activation tiles
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            const int rowbase = (n * H + wrapi(y + ky - 1, H)) * W;
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const int e = tid * 4;
+                const int j = e / SC, c = e % SC;
+                const size_t q = size_t(rowbase + wrapi(x0 + j + kx - 1, W));
+#pragma unroll
+                for (int k = 0; k < 4; ++k) sa[kx][ky][c + k][j] = ain[q * SC + c + k];
+            }
+        }
+        __syncthreads();
+        if (tid < SC) {
+            float s = 0.f;
+#pragma unroll
+            for (int j = 0; j < WSEG; ++j) s += float(sdz[tid][j]);
+            bacc += s;
+        }
+        bf16x8 aop[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+            aop[mt] = *reinterpret_cast<const bf16x8 *>(&sdz[mt * 16 + r16][8 * g]);
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int t = wave + 4 * s;
+            if (t < 9) {
+                const int ky = t / 3, kx = t % 3;
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    const bf16x8 bop =
+                        *reinterpret_cast<const bf16x8 *>(&sa[kx][ky][nt * 16 + r16][8 * g]);
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt) acc[s][mt][nt] = mfma16(aop[mt], bop, acc[s][mt][nt]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int t = wave + 4 * s;
+        if (t < 9) {
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int co = mt * 16 + 4 * g + r, ci = nt * 16 + r16;
+                        atomicAdd(&dw[(co * SC + ci) * 9 + t], acc[s][mt][nt][r]);
+                    }
+        }
+    }
+    if (tid < SC) atomicAdd(&db[tid], bacc);
+}
+
+// BF16 packings of a C -> C layer: forward wf[t][co][ci], adjoint wb[t][ci][co]
+// = W[co][ci][8 - t] (tap flip).
+__global__ void k_pack(const float *__restrict__ w, bf16 *__restrict__ wf, bf16 *__restrict__ wb) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= SC * SC * 9) return;
+    const int t = k % 9, ci = (k / 9) % SC, co = k / (9 * SC);
+    const bf16 v = bf16(w[k]);
+    wf[(t * SC + co) * SC + ci] = v;
+    wb[((8 - t) * SC + ci) * SC + co] = v;
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int n, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.f - b1) * gk;
+    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    p[k] -= lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-graining: mean density over f x f blocks of the streamed state.
+// ---------------------------------------------------------------------------
+template <class L, typename real>
+__global__ void __launch_bounds__(256) k_coarsen(Geometry g, const real *__restrict__ src,
+                                                 double rho0, int f, float *__restrict__ out) {
+    const int cx = g.nx / f, cy = g.ny / f;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= cx * cy) return;
+    const int X = k % cx, Y = k / cx;
+    double s = 0.0;
+    for (int dy = 0; dy < f; ++dy)
+        for (int dx = 0; dx < f; ++dx) {
+            const int x = X * f + dx, y = Y * f + dy;
+            const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
+            const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                const int c0 = L::c(i, 0), c1 = L::c(i, 1);
+                const int xs = c0 == 1 ? xm : (c0 == -1 ? xp : x);
+                const int ys = c1 == 1 ? ym : (c1 == -1 ? yp : y);
+                s += double(src[int64_t(i) * g.N + xs + int64_t(g.nx) * ys]);
+            }
+        }
+    out[k] = float(rho0 + s / double(f * f));
+}
+
+hipError_t launch_coarsen(const Geometry &g, int precision, const void *buf, double rho0, int f,
+                          float *out, hipStream_t s) {
+    if (g.D != 2 || f < 1 || g.nx % f || g.ny % f) return hipErrorInvalidValue;
+    const int n = (g.nx / f) * (g.ny / f);
+    const unsigned nb = unsigned((n + 255) / 256);
+    if (precision == 0)
+        hipLaunchKernelGGL((k_coarsen<D2Q9, float>), dim3(nb), dim3(256), 0, s, g,
+                           static_cast<const float *>(buf), rho0, f, out);
+    else
+        hipLaunchKernelGGL((k_coarsen<D2Q9, double>), dim3(nb), dim3(256), 0, s, g,
+                           static_cast<const double *>(buf), rho0, f, out);
+    return hipGetLastError();
+}
+
+// real field -> complex (for the S(k) pipeline on coarse fields)
+__global__ void k_field_cplx(const float *__restrict__ f, int n, float *__restrict__ c) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    c[2 * k] = f[k];
+    c[2 * k + 1] = 0.f;
+}
+
+hipError_t launch_field_cplx(const float *f, int n, void *c, hipStream_t s) {
+    hipLaunchKernelGGL(k_field_cplx, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, f, n,
+                       static_cast<float *>(c));
+    return hipGetLastError();
+}
+
+}  // namespace fsc
+
+// ===========================================================================
+// Surrogate object and its C ABI.
+// ===========================================================================
+using namespace fsc;
+
+struct fsc_sur {
+    int layers = 5, H = 0, W = 0, maxB = 0;
+    float mean = 1.f, in_scale = 1.f, out_scale = 1.f;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int64_t nparams = 0;
+    std::vector<int64_t> woff, boff;  // offsets of each layer's weights / biases
+    float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
+    bf16 *wf = nullptr, *wb = nullptr;  // [mid layer][9][32][32]
+    std::vector<float *> z;            // [layers - 1] of P x 32
+    std::vector<bf16 *> a;             // [layers - 1] of P x 32
+    bf16 *dzA = nullptr, *dzB = nullptr;
+    float *y = nullptr, *gbuf = nullptr;
+    double *ysum = nullptr, *gsum = nullptr, *loss = nullptr;
+    int64_t adam_t = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_sur_error;
+
+int sur_fail(fsc_sur *s, int code, const std::string &msg) {
+    if (s) s->err = msg;
+    else g_sur_error = msg;
+    return code;
+}
+
+#define SCHK(s, expr)                                                                       \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess) return sur_fail((s), FSC_E_HIP, std::string(#expr) + ": " +   \
+                                                                 hipGetErrorString(_e));    \
+    } while (0)
+
+int nmid(const fsc_sur *s) { return s->layers - 2; }
+
+void sur_free(fsc_sur *s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    void *ptrs[] = {s->params, s->grads, s->m, s->v, s->wf, s->wb, s->dzA, s->dzB,
+                    s->y,      s->gbuf,  s->ysum, s->gsum, s->loss};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto p : s->z)
+        if (p) (void)hipFree(p);
+    for (auto p : s->a)
+        if (p) (void)hipFree(p);
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int pack_weights(fsc_sur *s) {
+    for (int l = 1; l <= nmid(s); ++l) {
+        const size_t off = size_t(l - 1) * 9 * SC * SC;
+        hipLaunchKernelGGL(k_pack, dim3((SC * SC * 9 + 255) / 256), dim3(256), 0, s->stream,
+                           s->params + s->woff[l], s->wf + off, s->wb + off);
+        SCHK(s, hipGetLastError());
+    }
+    return FSC_OK;
+}
+
+int check_batch(fsc_sur *s, int batch) {
+    if (batch < 1 || batch > s->maxB) return sur_fail(s, FSC_E_INVAL, "batch out of range");
+    return FSC_OK;
+}
+
+// forward pass up to y (and the per-image sums of y)
+int sur_forward_core(fsc_sur *s, const float *in, int B) {
+    const int P = B * s->H * s->W;
+    const unsigned nb = unsigned((P + 255) / 256);
+    const float inv = 1.f / s->in_scale;
+    hipLaunchKernelGGL(k_first, dim3(nb), dim3(256), 0, s->stream, in, B, s->H, s->W, s->mean, inv,
+                       s->params + s->woff[0], s->params + s->boff[0], s->z[0], s->a[0]);
+    SCHK(s, hipGetLastError());
+    const int tiles = P / 16;
+    const unsigned mb = unsigned(std::min(2048, std::max(1, tiles / 16)));
+    for (int l = 1; l <= nmid(s); ++l) {
+        const size_t off = size_t(l - 1) * 9 * SC * SC;
+        hipLaunchKernelGGL(k_mid<false>, dim3(mb), dim3(256), 0, s->stream, s->a[l - 1],
+                           s->wf + off, s->params + s->boff[l], B, s->H, s->W, s->z[l], s->a[l],
+                           nullptr);
+        SCHK(s, hipGetLastError());
+    }
+    const int last = s->layers - 1;
+    hipLaunchKernelGGL(k_last, dim3(nb), dim3(256), 0, s->stream, s->a[last - 1], B, s->H, s->W,
+                       s->params + s->woff[last], s->params + s->boff[last], s->y);
+    SCHK(s, hipGetLastError());
+    hipLaunchKernelGGL(k_img_sum, dim3(B), dim3(256), 0, s->stream, s->y, s->H * s->W, s->ysum);
+    SCHK(s, hipGetLastError());
+    return FSC_OK;
+}
+
+int sur_backward(fsc_sur *s, const float *in, const float *tgt, int B) {
+    const int H = s->H, W = s->W, P = B * H * W;
+    const unsigned nb = unsigned((P + 255) / 256);
+    SCHK(s, hipMemsetAsync(s->grads, 0, sizeof(float) * s->nparams, s->stream));
+    SCHK(s, hipMemsetAsync(s->loss, 0, sizeof(double), s->stream));
+    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s->stream, in, tgt, s->y, s->ysum, P, H * W,
+                       1.f / s->out_scale, 1.f / float(P), s->gbuf, s->loss);
+    SCHK(s, hipGetLastError());
+    hipLaunchKernelGGL(k_img_sum, dim3(B), dim3(256), 0, s->stream, s->gbuf, H * W, s->gsum);
+    SCHK(s, hipGetLastError());
+    const int last = s->layers - 1;
+    const int chunk = 2048;
+    const unsigned cb = unsigned((P + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_last_wgrad, dim3(cb), dim3(256), 0, s->stream, s->gbuf, s->gsum, B, H, W,
+                       s->a[last - 1], s->grads + s->woff[last], s->grads + s->boff[last], chunk);
+    SCHK(s, hipGetLastError());
+    bf16 *dz = s->dzA, *dzn = s->dzB;
+    hipLaunchKernelGGL(k_last_bwd, dim3(nb), dim3(256), 0, s->stream, s->gbuf, s->gsum, B, H, W,
+                       s->params + s->woff[last], s->z[last - 1], dz);
+    SCHK(s, hipGetLastError());
+    const int tiles = P / 16;
+    const unsigned mb = unsigned(std::min(2048, std::max(1, tiles / 16)));
+    const unsigned wgb = unsigned(std::min(1024, std::max(1, P / WSEG / 8)));
+    for (int l = nmid(s); l >= 1; --l) {
+        // dz holds dL/dz_l; weight gradient, then dL/dz_{l-1}
+        hipLaunchKernelGGL(k_mid_wgrad, dim3(wgb), dim3(256), 0, s->stream, dz, s->a[l - 1], B, H,
+                           W, s->grads + s->woff[l], s->grads + s->boff[l]);
+        SCHK(s, hipGetLastError());
+        const size_t off = size_t(l - 1) * 9 * SC * SC;
+        hipLaunchKernelGGL(k_mid<true>, dim3(mb), dim3(256), 0, s->stream, dz, s->wb + off,
+                           nullptr, B, H, W, nullptr, dzn, s->z[l - 1]);
+        SCHK(s, hipGetLastError());
+        std::swap(dz, dzn);
+    }
+    hipLaunchKernelGGL(k_first_wgrad, dim3(cb), dim3(256), 0, s->stream, dz, in, B, H, W, s->mean,
+                       1.f / s->in_scale, s->grads + s->woff[0], s->grads + s->boff[0], chunk);
+    SCHK(s, hipGetLastError());
+    return FSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fsc_sur_create(int layers, int H, int W, int max_batch, uint64_t seed, void *stream,
+                   fsc_sur **out) {
+    if (!out) return FSC_E_INVAL;
+    *out = nullptr;
+    if (layers < 3 || layers > 16 || H < 1 || W < 16 || (W % 32) || max_batch < 1 ||
+        int64_t(max_batch) * H * W >= (int64_t(1) << 26))
+        return sur_fail(nullptr, FSC_E_INVAL,
+                        "need 3 <= layers <= 16, W a multiple of 32, batch*H*W < 2^26");
+    fsc_sur *s = new fsc_sur();
+    s->layers = layers;
+    s->H = H;
+    s->W = W;
+    s->maxB = max_batch;
+    s->stream = static_cast<hipStream_t>(stream);
+    if (!s->stream) {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete s;
+            return sur_fail(nullptr, FSC_E_HIP, "stream creation failed");
+        }
+        s->own_stream = true;
+    }
+    // parameter layout: per layer W[co][ci][3][3] then b[co]
+    int64_t o = 0;
+    std::vector<float> host;
+    uint64_t st = seed * 0x9E3779B97F4A7C15ull + 0x2545F4914F6CDD1Dull;
+    auto rnd = [&]() {  // splitmix64 -> uniform in [-1, 1)
+        st += 0x9E3779B97F4A7C15ull;
+        uint64_t zz = st;
+        zz = (zz ^ (zz >> 30)) * 0xBF58476D1CE4E5B9ull;
+        zz = (zz ^ (zz >> 27)) * 0x94D049BB133111EBull;
+        zz ^= zz >> 31;
+        return double(zz >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    };
+    for (int l = 0; l < layers; ++l) {
+        const int ci = l == 0 ? 1 : SC, co = l == layers - 1 ? 1 : SC;
+        s->woff.push_back(o);
+        const double bound = std::sqrt(6.0 / (ci * 9));
+        for (int k = 0; k < co * ci * 9; ++k) host.push_back(float(bound * rnd()));
+        o += co * ci * 9;
+        s->boff.push_back(o);
+        for (int k = 0; k < co; ++k) host.push_back(0.f);
+        o += co;
+    }
+    s->nparams = o;
+    const size_t P = size_t(max_batch) * H * W;
+    bool ok = hipMalloc(&s->params, sizeof(float) * o) == hipSuccess &&
+              hipMalloc(&s->grads, sizeof(float) * o) == hipSuccess &&
+              hipMalloc(&s->m, sizeof(float) * o) == hipSuccess &&
+              hipMalloc(&s->v, sizeof(float) * o) == hipSuccess &&
+              hipMalloc(&s->wf, sizeof(bf16) * 9 * SC * SC * std::max(1, layers - 2)) == hipSuccess &&
+              hipMalloc(&s->wb, sizeof(bf16) * 9 * SC * SC * std::max(1, layers - 2)) == hipSuccess &&
+              hipMalloc(&s->dzA, sizeof(bf16) * P * SC) == hipSuccess &&
+              hipMalloc(&s->dzB, sizeof(bf16) * P * SC) == hipSuccess &&
+              hipMalloc(&s->y, sizeof(float) * P) == hipSuccess &&
+              hipMalloc(&s->gbuf, sizeof(float) * P) == hipSuccess &&
+              hipMalloc(&s->ysum, sizeof(double) * max_batch) == hipSuccess &&
+              hipMalloc(&s->gsum, sizeof(double) * max_batch) == hipSuccess &&
+              hipMalloc(&s->loss, sizeof(double)) == hipSuccess;
+    for (int l = 0; ok && l < layers - 1; ++l) {
+        float *zz = nullptr;
+        bf16 *aa = nullptr;
+        ok = hipMalloc(&zz, sizeof(float) * P * SC) == hipSuccess &&
+             hipMalloc(&aa, sizeof(bf16) * P * SC) == hipSuccess;
+        s->z.push_back(zz);
+        s->a.push_back(aa);
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        sur_free(s);
+        return sur_fail(nullptr, FSC_E_OOM, "surrogate allocation failed");
+    }
+    if (hipMemcpy(s->params, host.data(), sizeof(float) * o, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(s->m, 0, sizeof(float) * o) != hipSuccess ||
+        hipMemset(s->v, 0, sizeof(float) * o) != hipSuccess || pack_weights(s) != FSC_OK ||
+        hipStreamSynchronize(s->stream) != hipSuccess) {
+        sur_free(s);
+        return sur_fail(nullptr, FSC_E_HIP, "surrogate initialisation failed");
+    }
+    *out = s;
+    return FSC_OK;
+}
+
+int fsc_sur_destroy(fsc_sur *s) {
+    if (!s) return FSC_E_INVAL;
+    sur_free(s);
+    return FSC_OK;
+}
+
+const char *fsc_sur_last_error(const fsc_sur *s) { return s ? s->err.c_str() : g_sur_error.c_str(); }
+
+int fsc_sur_nparams(const fsc_sur *s, int64_t *n) {
+    if (!s || !n) return FSC_E_INVAL;
+    *n = s->nparams;
+    return FSC_OK;
+}
+
+int fsc_sur_set_params(fsc_sur *s, const float *host, int64_t n) {
+    if (!s || !host || n != s->nparams) return FSC_E_INVAL;
+    SCHK(s, hipMemcpyAsync(s->params, host, sizeof(float) * n, hipMemcpyHostToDevice, s->stream));
+    int rc = pack_weights(s);
+    if (rc) return rc;
+    SCHK(s, hipMemsetAsync(s->m, 0, sizeof(float) * n, s->stream));
+    SCHK(s, hipMemsetAsync(s->v, 0, sizeof(float) * n, s->stream));
+    s->adam_t = 0;
+    SCHK(s, hipStreamSynchronize(s->stream));
+    return FSC_OK;
+}
+
+int fsc_sur_get_params(fsc_sur *s, float *host, int64_t n) {
+    if (!s || !host || n != s->nparams) return FSC_E_INVAL;
+    SCHK(s, hipMemcpyAsync(host, s->params, sizeof(float) * n, hipMemcpyDeviceToHost, s->stream));
+    SCHK(s, hipStreamSynchronize(s->stream));
+    return FSC_OK;
+}
+
+int fsc_sur_set_norm(fsc_sur *s, float mean, float in_scale, float out_scale) {
+    if (!s || !(in_scale > 0.f) || !(out_scale > 0.f)) return FSC_E_INVAL;
+    s->mean = mean;
+    s->in_scale = in_scale;
+    s->out_scale = out_scale;
+    return FSC_OK;
+}
+
+int fsc_sur_forward(fsc_sur *s, const float *dev_in, float *dev_out, int batch) {
+    if (!s || !dev_in || !dev_out) return FSC_E_INVAL;
+    int rc = check_batch(s, batch);
+    if (rc) return rc;
+    rc = sur_forward_core(s, dev_in, batch);
+    if (rc) return rc;
+    const int P = batch * s->H * s->W;
+    hipLaunchKernelGGL(k_pred, dim3(unsigned((P + 255) / 256)), dim3(256), 0, s->stream, dev_in,
+                       s->y, s->ysum, P, s->H * s->W, s->out_scale, dev_out);
+    SCHK(s, hipGetLastError());
+    return FSC_OK;
+}
+
+int fsc_sur_grad(fsc_sur *s, const float *dev_in, const float *dev_target, int batch,
+                 float *host_grad, double *loss) {
+    if (!s || !dev_in || !dev_target) return FSC_E_INVAL;
+    int rc = check_batch(s, batch);
+    if (rc) return rc;
+    rc = sur_forward_core(s, dev_in, batch);
+    if (rc) return rc;
+    rc = sur_backward(s, dev_in, dev_target, batch);
+    if (rc) return rc;
+    if (host_grad)
+        SCHK(s, hipMemcpyAsync(host_grad, s->grads, sizeof(float) * s->nparams,
+                               hipMemcpyDeviceToHost, s->stream));
+    double l = 0.0;
+    SCHK(s, hipMemcpyAsync(&l, s->loss, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    SCHK(s, hipStreamSynchronize(s->stream));
+    if (loss) *loss = l / double(batch * s->H * s->W);
+    return FSC_OK;
+}
+
+int fsc_sur_train_step(fsc_sur *s, const float *dev_in, const float *dev_target, int batch,
+                       float lr, double *loss) {
+    if (!s || !dev_in || !dev_target || !(lr > 0.f)) return FSC_E_INVAL;
+    int rc = check_batch(s, batch);
+    if (rc) return rc;
+    rc = sur_forward_core(s, dev_in, batch);
+    if (rc) return rc;
+    rc = sur_backward(s, dev_in, dev_target, batch);
+    if (rc) return rc;
+    s->adam_t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float bc1 = 1.f - std::pow(b1, float(s->adam_t));
+    const float bc2 = 1.f - std::pow(b2, float(s->adam_t));
+    hipLaunchKernelGGL(k_adam, dim3(unsigned((s->nparams + 255) / 256)), dim3(256), 0, s->stream,
+                       s->params, s->grads, s->m, s->v, int(s->nparams), lr, b1, b2, 1e-8f, bc1,
+                       bc2);
+    SCHK(s, hipGetLastError());
+    rc = pack_weights(s);
+    if (rc) return rc;
+    if (loss) {
+        double l = 0.0;
+        SCHK(s, hipMemcpyAsync(&l, s->loss, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        SCHK(s, hipStreamSynchronize(s->stream));
+        *loss = l / double(batch * s->H * s->W);
+    }
+    return FSC_OK;
+}
+
+int fsc_mfma_probe(const float *host_a, const float *host_b, float *host_c) {
+    if (!host_a || !host_b || !host_c) return FSC_E_INVAL;
+    float *d = nullptr;
+    if (hipMalloc(&d, sizeof(float) * (16 * 32 + 32 * 16 + 16 * 16)) != hipSuccess) return FSC_E_OOM;
+    hipError_t e = hipMemcpy(d, host_a, sizeof(float) * 512, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d + 512, host_b, sizeof(float) * 512, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, nullptr, d, d + 512, d + 1024);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(host_c, d + 1024, sizeof(float) * 256, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    return e == hipSuccess ? FSC_OK : FSC_E_HIP;
+}
+
+}  // extern "C"

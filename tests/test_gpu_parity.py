@@ -299,6 +299,59 @@ def test_autotune_leaves_state_and_results_unchanged():
         assert t["blocks"] > 0 and t["tx"] in (64, 128, 256)
 
 
+def test_checkpoint_resume_is_bit_exact(tmp_path):
+    specs = [((64, 64), 0.9, 0.5), ((40, 48), 0.8, 2.0)]
+    plist = [_params(2, sh, 4, "fp32", T_hat=th, rho0=r0, kBT=1e-4, seed=9, replica=k)
+             for k, (sh, th, r0) in enumerate(specs)]
+    path = str(tmp_path / "ens.ckpt")
+    a = fsc.Ensemble(plist)
+    a.init_uniform()
+    a.run(60, sk_every=10)
+    a.save(path)
+    a.run(50, sk_every=10)
+    b = fsc.Ensemble(plist)
+    b.load(path)
+    assert b.t == 60
+    b.run(50, sk_every=10)
+    for k in range(len(specs)):
+        assert np.array_equal(a.get_populations(k), b.get_populations(k))
+        # S(k) bins are summed with FP64 atomics: equal up to the order of the
+        # additions (last bits); the mode counts are exact
+        kinds = [fsc.FSC_SK_AXIS] + ([fsc.FSC_SK_RADIAL] if k == 0 else [])
+        for kind in kinds:
+            (sb, qb, cb), (sa, qa, ca) = b.read_sk(k, kind), a.read_sk(k, kind)
+            assert np.allclose(sb, sa, rtol=1e-12, atol=0) and np.allclose(qb, qa, rtol=1e-12, atol=0)
+            assert np.array_equal(cb, ca)
+    # another seed, a truncated file, a missing file: refused, state untouched
+    other = fsc.Ensemble([plist[0], _params(2, specs[1][0], 4, "fp32", T_hat=0.8, rho0=2.0,
+                                            kBT=1e-4, seed=10, replica=1)])
+    other.init_uniform()
+    with pytest.raises(fsc.FscError, match="invalid argument"):
+        other.load(path)
+    assert other.t == 0
+    trunc = str(tmp_path / "trunc.ckpt")
+    with open(path, "rb") as src, open(trunc, "wb") as dst:
+        dst.write(src.read()[:4000])
+    before = b.get_populations(1)
+    with pytest.raises(fsc.FscError, match="file error"):
+        b.load(trunc)
+    with pytest.raises(fsc.FscError, match="file error"):
+        b.load(str(tmp_path / "missing.ckpt"))
+    assert b.t == 110 and np.array_equal(b.get_populations(1), before)
+    for e in (a, b, other):
+        e.close()
+    # single lattice, FP64, D3Q19
+    p3 = _params(3, (10, 12, 14), 4, "fp64", T_hat=0.9, rho0=0.5, kBT=1e-4, seed=2)
+    with fsc.Lattice(p3) as x, fsc.Lattice(p3) as y:
+        x.init_uniform()
+        x.step(7)
+        x.save(path)
+        x.step(5)
+        y.load(path)
+        y.step(5)
+        assert np.array_equal(x.get_populations(), y.get_populations())
+
+
 # ------------------------------------------------ full-size sampled parity ---
 @pytest.mark.parametrize("case", ["deep_quench_4096", "metastable_256cube"])
 def test_full_size_one_step_matches_oracle(case):
