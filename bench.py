@@ -63,6 +63,65 @@ def traffic_from_profile(stencil: str, noise: bool, tiling: dict):
     return None
 
 
+COPY_BYTES = 1 << 30  # size of the calibration copy in copy_ceiling()
+PMC_ARGS = "--steps 64 --warmup 8 --kernel-steps 16 --no-cpu-baseline --no-surrogate"
+
+
+def ingest_pmc(fetch_csv: str, write_csv: str, out_path: str):
+    """Builds profiles/step_traffic.json from two rocprofv3 counter runs of
+    this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Both
+    counters are scaled so that the plain 1 GiB copy of copy_ceiling() reads
+    1 GiB fetched and 1 GiB written; the step kernels' per-launch means are
+    then HBM bytes per launch."""
+    import csv
+    from collections import defaultdict
+
+    def load(path, counter):
+        sums, counts, copies = defaultdict(float), defaultdict(int), []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                name, grid, v = r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])
+                if "fsc::k_copy" in name:
+                    copies.append((grid, v))
+                elif "fsc::k_step<" in name:
+                    key = (name.replace("void ", "").split("(")[0], grid)
+                    sums[key] += v
+                    counts[key] += 1
+        # the calibration copy is the most frequent k_copy launch
+        grids = defaultdict(list)
+        for g, v in copies:
+            grids[g].append(v)
+        cal = max(grids.values(), key=len)
+        scale = COPY_BYTES / (sum(cal) / len(cal) * 1024.0)
+        return {k: sums[k] / counts[k] * 1024.0 * scale for k in sums}, counts, scale
+
+    fetch, counts, fscale = load(fetch_csv, "FETCH_SIZE")
+    write, _, wscale = load(write_csv, "WRITE_SIZE")
+    entries = []
+    for key in sorted(fetch):
+        if key not in write:
+            continue
+        entries.append(dict(kernel=key[0], grid_threads=key[1], launches=counts[key],
+                            fetch_bytes=int(fetch[key]), write_bytes=int(write[key]),
+                            bytes_per_launch=int(fetch[key] + write[key])))
+    doc = dict(kernel_hash=kernel_hash(),
+               commands=[f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch_dir> -o run "
+                         f"-- python3 bench.py {PMC_ARGS}",
+                         f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write_dir> -o run "
+                         f"-- python3 bench.py {PMC_ARGS}",
+                         "python3 bench.py --ingest-pmc <fetch_dir>/run_counter_collection.csv "
+                         "<write_dir>/run_counter_collection.csv"],
+               calibration=dict(note="plain 16-byte copy (fsc_copy) of 1 GiB; counter KiB x scale "
+                                     "x 1024 = bytes", fetch_scale=round(fscale, 4),
+                                write_scale=round(wscale, 4)),
+               entries=entries)
+    with open(out_path, "w") as fh:
+        json.dump(doc, fh, indent=1)
+    return doc
+
+
 def time_steps(obj, steps: int, stream, torch):
     """Average duration of one fused step launch (HIP events on the library's
     stream), over `steps` launches without measurement."""
@@ -153,8 +212,31 @@ def cpu_baseline(I, budget_s: float):
         sample.append(f"r{r['replica']}:{r['nx']}^2x{nsteps}")
     return dict(value=done_lups / t_used / 1e6, unit="MLUPS", cores=O.max_threads(),
                 kind="oracle",
-                sample=f"{len(sample)} of the 64 ensemble replicas x {nsteps} steps each "
-                       f"({', '.join(sample)}), {t_used:.1f} s")
+                sample=f"{len(sample)} of the 64 ensemble replicas (sides 128-512) x {nsteps} "
+                       f"steps each, {done_lups / 1e6:.0f} M lattice updates in {t_used:.1f} s")
+
+
+def run_surrogate(torch):
+    """The committed coarse-grained surrogate on held-out seeds of the 1024^2
+    deep quench: rollout from the lattice state at t = 2048, S(k, t) error per
+    stride against the lattice, the horizon within 5%, and the wall-clock
+    speedup over the lattice for the same strides on this GPU."""
+    from paper_2212_07848_amd import surrogate as SU
+    sur, meta = SU.load_model()
+    ev = SU.evaluate(torch, sur, range(8), n=1024, t0_snaps=(8,), n_out=16, seed_base=1000)
+    sur.close()
+    st = ev["starts"][0]
+    h = st["horizon_5pct"]
+    return {"workload": "d2q9_1024x1024_fp32_e8_quench, 8x8 block means, stride 256 steps",
+            "model": f"{meta['layers']}-layer 3x3 conv, 32 channels, input (rho_t, rho_t - "
+                     f"rho_t-256), BF16 MFMA / FP32 accumulate",
+            "held_out_seeds": len(ev["seeds"]), "t0": st["t0"],
+            "horizon_strides_at_5pct": h, "horizon_lattice_steps": h * ev["stride"],
+            "persistence_horizon_strides": st["persistence_horizon_5pct"],
+            "sk_rel_err_per_stride": [round(r["sk_rel_err"], 4) for r in st["rows"]],
+            "speedup_at_5pct": round(st["speedup"], 1),
+            "lattice_s_per_stride": round(st["lbm_seconds"] / ev["n_out"], 5),
+            "surrogate_s_per_stride": round(st["surrogate_seconds"] / ev["n_out"], 6)}
 
 
 def main():
@@ -167,7 +249,14 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/step_traffic.json from two rocprofv3 counter runs")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        doc = ingest_pmc(*args.ingest_pmc, os.path.join(ROOT, "profiles", "step_traffic.json"))
+        print(f"{len(doc['entries'])} step-kernel launch shapes, calibration {doc['calibration']}")
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -219,6 +308,8 @@ def main():
         extra[I.DEEP_QUENCH["name"] + "_noise_free"] = {
             k: (round(v, 3) if isinstance(v, float) else v) for k, v in e.items()}
         out["extra"] = extra
+    if not args.no_surrogate:
+        out["surrogate"] = run_surrogate(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(I, args.cpu_budget)
     print(json.dumps(out))

@@ -31,8 +31,11 @@
  *     call.  Device buffers are owned by the library unless passed in through
  *     fsc_create_external (then the caller keeps ownership and must keep them
  *     alive until fsc_destroy).
- *   - All device work is enqueued on the hipStream_t given at creation (NULL =
- *     the null stream).  Calls that return host data synchronise that stream.
+ *   - All device work is enqueued on the hipStream_t given at creation.  A
+ *     lattice or ensemble created with NULL makes a stream of its own (its
+ *     step chunks are captured into HIP graphs, which the null stream cannot
+ *     hold); the surrogate and the field functions take NULL as the device's
+ *     default stream.  Calls that return host data synchronise the stream.
  *     A context is not thread safe; distinct contexts are independent.
  */
 #ifndef FSC_H
@@ -221,23 +224,30 @@ int fsc_ens_read_series(fsc_ens *ens, int replica, double *out, int max_rows, in
 /* Learned coarse-grained surrogate (not in the paper).                     */
 /*                                                                          */
 /* A periodic convolutional network advances the block-averaged density of  */
-/* a phase-separating 2D lattice by a fixed number of lattice steps:        */
-/*   x = (rho - mean)/in_scale; a_0 = SiLU(conv(x)); a_l = SiLU(conv(a_l-1)),*/
-/*   l = 1..layers-2 (32 channels); y = conv(a_layers-2);                    */
-/*   rho' = rho + out_scale (y - <y>_image)   (conserves each image's mean)  */
-/* conv = 3x3 cross-correlation, circular padding.  The 32 -> 32 layers run  */
-/* on BF16 matrix cores with FP32 accumulation (forward, backward-data and   */
-/* backward-weight); parameters are FP32, trained by Adam on the loss        */
-/* mean((y - <y>) - (target - rho)/out_scale)^2.  Fields are device float    */
-/* arrays [batch][H][W]; calls run on the surrogate's stream (NULL: its own) */
-/* and return after enqueueing, except those returning host data.           */
+/* a phase-separating 2D lattice by a fixed stride of k lattice steps:      */
+/*   x_0 = (rho_t - mean)/in_scale                                          */
+/*   x_1 = (rho_t - rho_{t-k})/out_scale          (in_ch = 2 only)          */
+/*   a_0 = SiLU(conv(x)); a_l = SiLU(conv(a_l-1)), l = 1..layers-2 (32 ch);  */
+/*   y = conv(a_layers-2); rho_{t+k} = rho_t + out_scale (y - <y>_image)    */
+/* (each image's mean is conserved).  conv = 3x3 cross-correlation with     */
+/* circular padding.  The 32 -> 32 layers run on BF16 matrix cores with     */
+/* FP32 accumulation (forward, backward-data and backward-weight); the      */
+/* parameters are FP32, trained by Adam on the loss                         */
+/* mean((y - <y>) - (target - rho_t)/out_scale)^2.  Fields are device float  */
+/* arrays [batch][H][W] (prev = rho_{t-k}, in = rho_t); calls run on the    */
+/* stream given at creation (NULL: the device's default stream) and return  */
+/* after enqueueing, except those returning host data.  The caller orders   */
+/* its own writes of the inputs before, and reads of the outputs after,     */
+/* on that stream.  Errors: FSC_E_INVAL (bad sizes, batch out of            */
+/* range, prev missing for in_ch = 2), FSC_E_OOM, FSC_E_HIP.                */
 /* ----------------------------------------------------------------------- */
 typedef struct fsc_sur fsc_sur;
 
-/* layers in [3, 16]; W a multiple of 32; max_batch * H * W < 2^26.  Weights
- * are drawn from `seed` (He-uniform), biases zero. */
-int fsc_sur_create(int layers, int H, int W, int max_batch, uint64_t seed, void *stream,
-                   fsc_sur **out);
+/* layers in [3, 16]; in_ch 1 or 2; W a multiple of 32; max_batch * H * W <
+ * 2^26.  Weights and biases are drawn from `seed`, uniform in
+ * +-1/sqrt(fan_in) (fan_in = 9 c_in). */
+int fsc_sur_create(int layers, int in_ch, int H, int W, int max_batch, uint64_t seed,
+                   void *stream, fsc_sur **out);
 int fsc_sur_destroy(fsc_sur *s);
 const char *fsc_sur_last_error(const fsc_sur *s);
 /* Parameters: one float vector, per layer W[c_out][c_in][3][3] then b[c_out]. */
@@ -245,14 +255,16 @@ int fsc_sur_nparams(const fsc_sur *s, int64_t *n);
 int fsc_sur_set_params(fsc_sur *s, const float *host, int64_t n); /* resets Adam state */
 int fsc_sur_get_params(fsc_sur *s, float *host, int64_t n);
 int fsc_sur_set_norm(fsc_sur *s, float mean, float in_scale, float out_scale);
-int fsc_sur_forward(fsc_sur *s, const float *dev_in, float *dev_out, int batch);
+/* dev_prev is ignored (may be NULL) when in_ch = 1. */
+int fsc_sur_forward(fsc_sur *s, const float *dev_prev, const float *dev_in, float *dev_out,
+                    int batch);
 /* Gradient of the loss (host float[nparams], may be NULL) and the loss. */
-int fsc_sur_grad(fsc_sur *s, const float *dev_in, const float *dev_target, int batch,
-                 float *host_grad, double *loss);
+int fsc_sur_grad(fsc_sur *s, const float *dev_prev, const float *dev_in, const float *dev_target,
+                 int batch, float *host_grad, double *loss);
 /* One Adam step (beta 0.9, 0.999, eps 1e-8) at learning rate lr; *loss (may be
  * NULL) gets the loss before the update. */
-int fsc_sur_train_step(fsc_sur *s, const float *dev_in, const float *dev_target, int batch,
-                       float lr, double *loss);
+int fsc_sur_train_step(fsc_sur *s, const float *dev_prev, const float *dev_in,
+                       const float *dev_target, int batch, float lr, double *loss);
 
 /* Block-averaged density of the current state over factor x factor blocks
  * into dev_out[(ny/factor) x (nx/factor)] (2D lattices, sides divisible by

@@ -4,12 +4,16 @@ The surrogate advances the block-averaged density of a phase-separating run
 by a fixed number of lattice steps.  It is not part of the paper; its
 definition (this build's) is:
 
-  x      = (rho - mean) / in_scale                          input normalisation
-  a_0    = SiLU(conv(x; W_0, b_0))                          1 -> C channels
+  x_0    = (rho - mean) / in_scale                          input normalisation
+  x_1    = (rho - prev) / out_scale                         last increment (K = 2)
+  a_0    = SiLU(conv(x; W_0, b_0))                          K -> C channels
   a_l    = SiLU(conv(a_{l-1}; W_l, b_l)),  l = 1 .. L-2     C -> C
   y      = conv(a_{L-2}; W_{L-1}, b_{L-1})                  C -> 1
   yhat   = y - <y>_image                                    mean-free increment
   rho'   = rho + out_scale * yhat                           conserves the mean
+
+rho is the coarse field at time t, prev the one a stride earlier and rho' the
+prediction a stride later; K = 1 networks see rho only.
 
 conv is a 3x3 cross-correlation with circular padding (the lattice is
 periodic); SiLU(z) = z / (1 + exp(-z)).  Training loss: mean over pixels and
@@ -23,23 +27,23 @@ from __future__ import annotations
 import numpy as np
 
 
-def layer_shapes(channels: int, layers: int):
+def layer_shapes(channels: int, layers: int, in_ch: int = 1):
     shapes = []
     for l in range(layers):
-        ci = 1 if l == 0 else channels
+        ci = in_ch if l == 0 else channels
         co = 1 if l == layers - 1 else channels
         shapes.append((co, ci))
     return shapes
 
 
-def n_params(channels: int, layers: int) -> int:
-    return sum(co * ci * 9 + co for co, ci in layer_shapes(channels, layers))
+def n_params(channels: int, layers: int, in_ch: int = 1) -> int:
+    return sum(co * ci * 9 + co for co, ci in layer_shapes(channels, layers, in_ch))
 
 
-def unpack(params: np.ndarray, channels: int, layers: int):
+def unpack(params: np.ndarray, channels: int, layers: int, in_ch: int = 1):
     out = []
     o = 0
-    for co, ci in layer_shapes(channels, layers):
+    for co, ci in layer_shapes(channels, layers, in_ch):
         W = params[o:o + co * ci * 9].reshape(co, ci, 3, 3)
         o += co * ci * 9
         b = params[o:o + co]
@@ -86,10 +90,20 @@ def dsilu(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=False):
-    """rho: [B, H, W] -> prediction [B, H, W] (and the intermediates)."""
-    P = unpack(np.asarray(params, dtype=np.float64), channels, layers)
-    x = ((np.asarray(rho, dtype=np.float64) - mean) / in_scale)[:, None]
+def network_input(rho, prev, mean, in_scale, out_scale):
+    rho = np.asarray(rho, dtype=np.float64)
+    chans = [(rho - mean) / in_scale]
+    if prev is not None:
+        chans.append((rho - np.asarray(prev, dtype=np.float64)) / out_scale)
+    return np.stack(chans, axis=1)
+
+
+def forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=False, prev=None):
+    """rho (and prev for two-channel networks): [B, H, W] -> prediction [B, H, W]
+    (and the intermediates)."""
+    in_ch = 1 if prev is None else 2
+    P = unpack(np.asarray(params, dtype=np.float64), channels, layers, in_ch)
+    x = network_input(rho, prev, mean, in_scale, out_scale)
     zs, acts = [], [x]
     a = x
     for l, (W, b) in enumerate(P):
@@ -107,9 +121,9 @@ def forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=False
     return pred
 
 
-def loss_and_grad(params, rho, target, channels, layers, mean, in_scale, out_scale):
+def loss_and_grad(params, rho, target, channels, layers, mean, in_scale, out_scale, prev=None):
     rho = np.asarray(rho, dtype=np.float64)
-    _, c = forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=True)
+    _, c = forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=True, prev=prev)
     r = (np.asarray(target, dtype=np.float64) - rho) / out_scale
     e = c["yhat"] - r
     M = e.size
@@ -130,12 +144,12 @@ def loss_and_grad(params, rho, target, channels, layers, mean, in_scale, out_sca
     return loss, flat
 
 
-def init_params(channels: int, layers: int, seed: int) -> np.ndarray:
+def init_params(channels: int, layers: int, seed: int, in_ch: int = 1) -> np.ndarray:
     """He-style uniform initialisation (the library's own initialiser is
     separate; tests pass parameters explicitly)."""
     rng = np.random.default_rng(seed)
     out = []
-    for co, ci in layer_shapes(channels, layers):
+    for co, ci in layer_shapes(channels, layers, in_ch):
         bound = np.sqrt(6.0 / (ci * 9))
         out.append(rng.uniform(-bound, bound, size=co * ci * 9))
         out.append(np.zeros(co))

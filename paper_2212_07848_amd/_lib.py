@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes as C
 import math
 import os
+import sys
 
 import numpy as np
 
@@ -127,7 +128,8 @@ def lib():
         "fsc_ens_get_tiling": ([vp, C.POINTER(C.c_int)], C.c_int),
         "fsc_copy": ([vp, vp, C.c_int64, vp], C.c_int),
         "fsc_philox": ([u32p, u32p, u32p, C.c_int64], C.c_int),
-        "fsc_sur_create": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, vp, C.POINTER(vp)],
+        "fsc_sur_create": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, vp,
+                            C.POINTER(vp)],
                            C.c_int),
         "fsc_sur_destroy": ([vp], C.c_int),
         "fsc_sur_last_error": ([vp], C.c_char_p),
@@ -135,9 +137,9 @@ def lib():
         "fsc_sur_set_params": ([vp, fp, C.c_int64], C.c_int),
         "fsc_sur_get_params": ([vp, fp, C.c_int64], C.c_int),
         "fsc_sur_set_norm": ([vp, C.c_float, C.c_float, C.c_float], C.c_int),
-        "fsc_sur_forward": ([vp, vp, vp, C.c_int], C.c_int),
-        "fsc_sur_grad": ([vp, vp, vp, C.c_int, fp, dp], C.c_int),
-        "fsc_sur_train_step": ([vp, vp, vp, C.c_int, C.c_float, dp], C.c_int),
+        "fsc_sur_forward": ([vp, vp, vp, vp, C.c_int], C.c_int),
+        "fsc_sur_grad": ([vp, vp, vp, vp, C.c_int, fp, dp], C.c_int),
+        "fsc_sur_train_step": ([vp, vp, vp, vp, C.c_int, C.c_float, dp], C.c_int),
         "fsc_coarsen": ([vp, C.c_int, vp], C.c_int),
         "fsc_ens_coarsen": ([vp, C.c_int, C.c_int, vp], C.c_int),
         "fsc_field_nbins": ([C.c_int, C.POINTER(C.c_int)], C.c_int),
@@ -165,6 +167,17 @@ def _check(rc, errfn=None, handle=None):
             m = errfn(handle)
             msg = m.decode() if m else ""
         raise FscError(rc, msg)
+
+
+def _torch_stream_or(stream):
+    """`stream`, or torch's current stream when none is given and torch is in
+    use: calls on torch tensors are then ordered with torch's own work."""
+    if stream is not None:
+        return stream
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_available():
+        return torch.cuda.current_stream()
+    return None
 
 
 def _stream_handle(stream):
@@ -429,17 +442,21 @@ def _fp(a):
 
 class Surrogate:
     """The learned coarse-grained surrogate (fsc_sur).  Device fields are
-    passed as objects with data_ptr() (torch tensors) or raw pointers."""
+    passed as objects with data_ptr() (torch tensors) or raw pointers; `prev`
+    (the field one stride earlier) is used by two-channel networks only.  The
+    calls run on `stream`, by default torch's current stream at creation."""
 
-    def __init__(self, layers: int, H: int, W: int, max_batch: int, seed: int = 0, stream=None):
+    def __init__(self, layers: int, H: int, W: int, max_batch: int, seed: int = 0, stream=None,
+                 in_ch: int = 2):
         L = lib()
         self._h = C.c_void_p()
-        _check(L.fsc_sur_create(layers, H, W, max_batch, C.c_uint64(seed), _stream_handle(stream),
-                                C.byref(self._h)), L.fsc_sur_last_error, None)
+        _check(L.fsc_sur_create(layers, in_ch, H, W, max_batch, C.c_uint64(seed),
+                                _stream_handle(_torch_stream_or(stream)), C.byref(self._h)),
+               L.fsc_sur_last_error, None)
         n = C.c_int64()
         self._c(L.fsc_sur_nparams(self._h, C.byref(n)))
         self.nparams = n.value
-        self.layers, self.H, self.W = layers, H, W
+        self.layers, self.in_ch, self.H, self.W = layers, in_ch, H, W
 
     def _c(self, rc):
         _check(rc, lib().fsc_sur_last_error, self._h)
@@ -457,6 +474,8 @@ class Surrogate:
 
     @staticmethod
     def _ptr(x):
+        if x is None:
+            return None
         return C.c_void_p(x.data_ptr() if hasattr(x, "data_ptr") else int(x))
 
     def get_params(self):
@@ -472,20 +491,22 @@ class Surrogate:
     def set_norm(self, mean: float, in_scale: float, out_scale: float):
         self._c(lib().fsc_sur_set_norm(self._h, mean, in_scale, out_scale))
 
-    def forward(self, x, out, batch: int):
-        self._c(lib().fsc_sur_forward(self._h, self._ptr(x), self._ptr(out), int(batch)))
+    def forward(self, prev, x, out, batch: int):
+        self._c(lib().fsc_sur_forward(self._h, self._ptr(prev), self._ptr(x), self._ptr(out),
+                                      int(batch)))
 
-    def grad(self, x, target, batch: int):
+    def grad(self, prev, x, target, batch: int):
         g = np.zeros(self.nparams, dtype=np.float32)
         loss = C.c_double()
-        self._c(lib().fsc_sur_grad(self._h, self._ptr(x), self._ptr(target), int(batch), _fp(g),
-                                   C.byref(loss)))
+        self._c(lib().fsc_sur_grad(self._h, self._ptr(prev), self._ptr(x), self._ptr(target),
+                                   int(batch), _fp(g), C.byref(loss)))
         return loss.value, g
 
-    def train_step(self, x, target, batch: int, lr: float, want_loss: bool = True):
+    def train_step(self, prev, x, target, batch: int, lr: float, want_loss: bool = True):
         loss = C.c_double()
-        self._c(lib().fsc_sur_train_step(self._h, self._ptr(x), self._ptr(target), int(batch),
-                                         float(lr), C.byref(loss) if want_loss else None))
+        self._c(lib().fsc_sur_train_step(self._h, self._ptr(prev), self._ptr(x), self._ptr(target),
+                                         int(batch), float(lr),
+                                         C.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
 
 
@@ -496,8 +517,8 @@ def field_sk(fields, batch: int, n: int, stream=None):
     shells = np.zeros((batch, nb.value))
     L = np.zeros(batch)
     ptr = C.c_void_p(fields.data_ptr() if hasattr(fields, "data_ptr") else int(fields))
-    _check(lib().fsc_field_sk(ptr, batch, n, n, _stream_handle(stream), _dp(shells), _dp(L),
-                              nb.value))
+    _check(lib().fsc_field_sk(ptr, batch, n, n, _stream_handle(_torch_stream_or(stream)),
+                              _dp(shells), _dp(L), nb.value))
     return shells, L
 
 

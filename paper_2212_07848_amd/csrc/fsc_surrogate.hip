@@ -4,9 +4,12 @@
 // it is the inference/training path next to the lattice, judged against the
 // lattice's own S(k, t) and L(t).
 //
-// Network (C = 32 hidden channels, L layers):
-//   x = (rho - mean)/in_scale;  a_0 = SiLU(conv(x));  a_l = SiLU(conv(a_{l-1}))
-//   y = conv(a_{L-2});  rho' = rho + out_scale (y - <y>_image)
+// Network (C = 32 hidden channels, L layers, K = 1 or 2 input channels):
+//   x_0 = (rho_t - mean)/in_scale,  x_1 = (rho_t - rho_{t-k})/out_scale (K = 2)
+//   a_0 = SiLU(conv(x));  a_l = SiLU(conv(a_{l-1}));  y = conv(a_{L-2})
+//   rho_{t+k} = rho_t + out_scale (y - <y>_image)
+// The second channel, the last increment, carries the flow that the density
+// alone does not determine.
 // conv = 3x3 cross-correlation with circular padding.  The C -> C layers run
 // as implicit GEMMs on v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32
 // accumulation), forward, backward-data and backward-weight; the 1 -> C and
@@ -61,10 +64,24 @@ __global__ void k_mfma_probe(const float *A, const float *B, float *Cm) {
 }
 
 // ---------------------------------------------------------------------------
-// Layer 0 (1 -> C) forward, FP32: one thread per pixel.
+// Network input X[p][K] (FP32) from the current and previous fields.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_first(const float *__restrict__ in, int B, int H, int W,
-                                               float mean, float inv_scale,
+__global__ void __launch_bounds__(256) k_input(const float *__restrict__ cur,
+                                               const float *__restrict__ prev, int P, int K,
+                                               float mean, float inv_in, float inv_out,
+                                               float *__restrict__ X) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const float c = cur[p];
+    X[size_t(p) * K] = (c - mean) * inv_in;
+    if (K == 2) X[size_t(p) * K + 1] = (c - prev[p]) * inv_out;
+}
+
+// ---------------------------------------------------------------------------
+// Layer 0 (K -> C) forward, FP32: one thread per pixel.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, int B, int H, int W,
                                                const float *__restrict__ w,
                                                const float *__restrict__ b, float *__restrict__ z,
                                                bf16 *__restrict__ a) {
@@ -72,18 +89,22 @@ __global__ void __launch_bounds__(256) k_first(const float *__restrict__ in, int
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= P) return;
     const int x = p % W, t = p / W, y = t % H, n = t / H;
-    float xi[9];
+    float xi[K][9];
 #pragma unroll
     for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx)
-            xi[ky * 3 + kx] =
-                (in[(n * H + wrapi(y + ky - 1, H)) * W + wrapi(x + kx - 1, W)] - mean) * inv_scale;
+        for (int kx = 0; kx < 3; ++kx) {
+            const size_t q = size_t((n * H + wrapi(y + ky - 1, H)) * W + wrapi(x + kx - 1, W)) * K;
+#pragma unroll
+            for (int ci = 0; ci < K; ++ci) xi[ci][ky * 3 + kx] = X[q + ci];
+        }
 #pragma unroll
     for (int co = 0; co < SC; ++co) {
         float acc = b[co];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) acc += w[co * 9 + k] * xi[k];
+        for (int ci = 0; ci < K; ++ci)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) acc += w[(co * K + ci) * 9 + k] * xi[ci][k];
         z[size_t(p) * SC + co] = acc;
         a[size_t(p) * SC + co] = bf16(silu(acc));
     }
@@ -292,16 +313,20 @@ __global__ void __launch_bounds__(256) k_last_wgrad(const float *__restrict__ g,
     }
 }
 
-// Weight gradient of layer 0: dW[c][t] = sum_p dZ0[p][c] x[p + off(t)], db[c] = sum dZ0.
+// Weight gradient of layer 0: dW[c][ci][t] = sum_p dZ0[p][c] X[p + off(t)][ci],
+// db[c] = sum_p dZ0[p][c].  Block: 32 channels x 8 pixel groups; FP32 atomics.
+template <int K>
 __global__ void __launch_bounds__(256) k_first_wgrad(const bf16 *__restrict__ dz,
-                                                     const float *__restrict__ in, int B, int H,
-                                                     int W, float mean, float inv_scale,
-                                                     float *__restrict__ dw,
+                                                     const float *__restrict__ X, int B, int H,
+                                                     int W, float *__restrict__ dw,
                                                      float *__restrict__ db, int chunk) {
-    __shared__ float red[8][SC][10];
+    constexpr int NT = 9 * K + 1;
+    __shared__ float red[8][SC][NT];
     const int c = threadIdx.x & 31, grp = threadIdx.x >> 5;
     const int P = B * H * W;
-    float acc[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float acc[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) acc[k] = 0.f;
     const int p_begin = blockIdx.x * chunk, p_end = min(P, p_begin + chunk);
     for (int p = p_begin + grp; p < p_end; p += 8) {
         const int x = p % W, t = p / W, yy = t % H, n = t / H;
@@ -310,21 +335,21 @@ __global__ void __launch_bounds__(256) k_first_wgrad(const bf16 *__restrict__ dz
         for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
-                const float xv =
-                    (in[(n * H + wrapi(yy + ky - 1, H)) * W + wrapi(x + kx - 1, W)] - mean) * inv_scale;
-                acc[ky * 3 + kx] += d * xv;
+                const size_t q = size_t((n * H + wrapi(yy + ky - 1, H)) * W + wrapi(x + kx - 1, W)) * K;
+#pragma unroll
+                for (int ci = 0; ci < K; ++ci) acc[ci * 9 + ky * 3 + kx] += d * X[q + ci];
             }
-        acc[9] += d;
+        acc[NT - 1] += d;
     }
 #pragma unroll
-    for (int k = 0; k < 10; ++k) red[grp][c][k] = acc[k];
+    for (int k = 0; k < NT; ++k) red[grp][c][k] = acc[k];
     __syncthreads();
     if (grp == 0) {
 #pragma unroll
-        for (int k = 0; k < 10; ++k) {
+        for (int k = 0; k < NT; ++k) {
             float s = 0.f;
             for (int q = 0; q < 8; ++q) s += red[q][c][k];
-            if (k < 9) atomicAdd(&dw[c * 9 + k], s);
+            if (k < NT - 1) atomicAdd(&dw[c * 9 * K + k], s);
             else atomicAdd(&db[c], s);
         }
     }
@@ -514,7 +539,7 @@ hipError_t launch_field_cplx(const float *f, int n, void *c, hipStream_t s) {
 using namespace fsc;
 
 struct fsc_sur {
-    int layers = 5, H = 0, W = 0, maxB = 0;
+    int layers = 5, in_ch = 1, H = 0, W = 0, maxB = 0;
     float mean = 1.f, in_scale = 1.f, out_scale = 1.f;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -525,7 +550,7 @@ struct fsc_sur {
     std::vector<float *> z;            // [layers - 1] of P x 32
     std::vector<bf16 *> a;             // [layers - 1] of P x 32
     bf16 *dzA = nullptr, *dzB = nullptr;
-    float *y = nullptr, *gbuf = nullptr;
+    float *y = nullptr, *gbuf = nullptr, *X = nullptr;
     double *ysum = nullptr, *gsum = nullptr, *loss = nullptr;
     int64_t adam_t = 0;
     std::string err;
@@ -553,8 +578,8 @@ int nmid(const fsc_sur *s) { return s->layers - 2; }
 void sur_free(fsc_sur *s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
-    void *ptrs[] = {s->params, s->grads, s->m, s->v, s->wf, s->wb, s->dzA, s->dzB,
-                    s->y,      s->gbuf,  s->ysum, s->gsum, s->loss};
+    void *ptrs[] = {s->params, s->grads, s->m,    s->v,    s->wf,   s->wb, s->dzA,
+                    s->dzB,    s->y,     s->gbuf, s->ysum, s->gsum, s->loss, s->X};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto p : s->z)
@@ -581,12 +606,18 @@ int check_batch(fsc_sur *s, int batch) {
 }
 
 // forward pass up to y (and the per-image sums of y)
-int sur_forward_core(fsc_sur *s, const float *in, int B) {
+int sur_forward_core(fsc_sur *s, const float *prev, const float *cur, int B) {
     const int P = B * s->H * s->W;
     const unsigned nb = unsigned((P + 255) / 256);
-    const float inv = 1.f / s->in_scale;
-    hipLaunchKernelGGL(k_first, dim3(nb), dim3(256), 0, s->stream, in, B, s->H, s->W, s->mean, inv,
-                       s->params + s->woff[0], s->params + s->boff[0], s->z[0], s->a[0]);
+    hipLaunchKernelGGL(k_input, dim3(nb), dim3(256), 0, s->stream, cur, prev, P, s->in_ch, s->mean,
+                       1.f / s->in_scale, 1.f / s->out_scale, s->X);
+    SCHK(s, hipGetLastError());
+    if (s->in_ch == 2)
+        hipLaunchKernelGGL(k_first<2>, dim3(nb), dim3(256), 0, s->stream, s->X, B, s->H, s->W,
+                           s->params + s->woff[0], s->params + s->boff[0], s->z[0], s->a[0]);
+    else
+        hipLaunchKernelGGL(k_first<1>, dim3(nb), dim3(256), 0, s->stream, s->X, B, s->H, s->W,
+                           s->params + s->woff[0], s->params + s->boff[0], s->z[0], s->a[0]);
     SCHK(s, hipGetLastError());
     const int tiles = P / 16;
     const unsigned mb = unsigned(std::min(2048, std::max(1, tiles / 16)));
@@ -640,9 +671,19 @@ int sur_backward(fsc_sur *s, const float *in, const float *tgt, int B) {
         SCHK(s, hipGetLastError());
         std::swap(dz, dzn);
     }
-    hipLaunchKernelGGL(k_first_wgrad, dim3(cb), dim3(256), 0, s->stream, dz, in, B, H, W, s->mean,
-                       1.f / s->in_scale, s->grads + s->woff[0], s->grads + s->boff[0], chunk);
+    if (s->in_ch == 2)
+        hipLaunchKernelGGL(k_first_wgrad<2>, dim3(cb), dim3(256), 0, s->stream, dz, s->X, B, H, W,
+                           s->grads + s->woff[0], s->grads + s->boff[0], chunk);
+    else
+        hipLaunchKernelGGL(k_first_wgrad<1>, dim3(cb), dim3(256), 0, s->stream, dz, s->X, B, H, W,
+                           s->grads + s->woff[0], s->grads + s->boff[0], chunk);
     SCHK(s, hipGetLastError());
+    return FSC_OK;
+}
+
+int check_inputs(fsc_sur *s, const float *prev, const float *cur) {
+    if (!cur || (s->in_ch == 2 && !prev))
+        return sur_fail(s, FSC_E_INVAL, "missing input field (two-channel networks need prev)");
     return FSC_OK;
 }
 
@@ -650,27 +691,23 @@ int sur_backward(fsc_sur *s, const float *in, const float *tgt, int B) {
 
 extern "C" {
 
-int fsc_sur_create(int layers, int H, int W, int max_batch, uint64_t seed, void *stream,
-                   fsc_sur **out) {
+int fsc_sur_create(int layers, int in_ch, int H, int W, int max_batch, uint64_t seed,
+                   void *stream, fsc_sur **out) {
     if (!out) return FSC_E_INVAL;
     *out = nullptr;
-    if (layers < 3 || layers > 16 || H < 1 || W < 16 || (W % 32) || max_batch < 1 ||
-        int64_t(max_batch) * H * W >= (int64_t(1) << 26))
+    if (layers < 3 || layers > 16 || (in_ch != 1 && in_ch != 2) || H < 1 || W < 16 || (W % 32) ||
+        max_batch < 1 || int64_t(max_batch) * H * W >= (int64_t(1) << 26))
         return sur_fail(nullptr, FSC_E_INVAL,
-                        "need 3 <= layers <= 16, W a multiple of 32, batch*H*W < 2^26");
+                        "need 3 <= layers <= 16, in_ch 1 or 2, W a multiple of 32, batch*H*W < 2^26");
     fsc_sur *s = new fsc_sur();
     s->layers = layers;
+    s->in_ch = in_ch;
     s->H = H;
     s->W = W;
     s->maxB = max_batch;
+    // NULL is the device's default (null) stream, so that calls are ordered
+    // with other work on it (torch's default stream is the null stream)
     s->stream = static_cast<hipStream_t>(stream);
-    if (!s->stream) {
-        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete s;
-            return sur_fail(nullptr, FSC_E_HIP, "stream creation failed");
-        }
-        s->own_stream = true;
-    }
     // parameter layout: per layer W[co][ci][3][3] then b[co]
     int64_t o = 0;
     std::vector<float> host;
@@ -684,13 +721,15 @@ int fsc_sur_create(int layers, int H, int W, int max_batch, uint64_t seed, void 
         return double(zz >> 11) * (2.0 / 9007199254740992.0) - 1.0;
     };
     for (int l = 0; l < layers; ++l) {
-        const int ci = l == 0 ? 1 : SC, co = l == layers - 1 ? 1 : SC;
+        const int ci = l == 0 ? in_ch : SC, co = l == layers - 1 ? 1 : SC;
         s->woff.push_back(o);
-        const double bound = std::sqrt(6.0 / (ci * 9));
+        // uniform in +-1/sqrt(fan_in) for weights and biases: a small initial
+        // map keeps the rollouts of early training (used as inputs) tame
+        const double bound = 1.0 / std::sqrt(double(ci * 9));
         for (int k = 0; k < co * ci * 9; ++k) host.push_back(float(bound * rnd()));
         o += co * ci * 9;
         s->boff.push_back(o);
-        for (int k = 0; k < co; ++k) host.push_back(0.f);
+        for (int k = 0; k < co; ++k) host.push_back(float(bound * rnd()));
         o += co;
     }
     s->nparams = o;
@@ -705,6 +744,7 @@ int fsc_sur_create(int layers, int H, int W, int max_batch, uint64_t seed, void 
               hipMalloc(&s->dzB, sizeof(bf16) * P * SC) == hipSuccess &&
               hipMalloc(&s->y, sizeof(float) * P) == hipSuccess &&
               hipMalloc(&s->gbuf, sizeof(float) * P) == hipSuccess &&
+              hipMalloc(&s->X, sizeof(float) * P * in_ch) == hipSuccess &&
               hipMalloc(&s->ysum, sizeof(double) * max_batch) == hipSuccess &&
               hipMalloc(&s->gsum, sizeof(double) * max_batch) == hipSuccess &&
               hipMalloc(&s->loss, sizeof(double)) == hipSuccess;
@@ -773,11 +813,14 @@ int fsc_sur_set_norm(fsc_sur *s, float mean, float in_scale, float out_scale) {
     return FSC_OK;
 }
 
-int fsc_sur_forward(fsc_sur *s, const float *dev_in, float *dev_out, int batch) {
-    if (!s || !dev_in || !dev_out) return FSC_E_INVAL;
-    int rc = check_batch(s, batch);
+int fsc_sur_forward(fsc_sur *s, const float *dev_prev, const float *dev_in, float *dev_out,
+                    int batch) {
+    if (!s || !dev_out) return FSC_E_INVAL;
+    int rc = check_inputs(s, dev_prev, dev_in);
     if (rc) return rc;
-    rc = sur_forward_core(s, dev_in, batch);
+    rc = check_batch(s, batch);
+    if (rc) return rc;
+    rc = sur_forward_core(s, dev_prev, dev_in, batch);
     if (rc) return rc;
     const int P = batch * s->H * s->W;
     hipLaunchKernelGGL(k_pred, dim3(unsigned((P + 255) / 256)), dim3(256), 0, s->stream, dev_in,
@@ -786,12 +829,14 @@ int fsc_sur_forward(fsc_sur *s, const float *dev_in, float *dev_out, int batch) 
     return FSC_OK;
 }
 
-int fsc_sur_grad(fsc_sur *s, const float *dev_in, const float *dev_target, int batch,
-                 float *host_grad, double *loss) {
-    if (!s || !dev_in || !dev_target) return FSC_E_INVAL;
-    int rc = check_batch(s, batch);
+int fsc_sur_grad(fsc_sur *s, const float *dev_prev, const float *dev_in, const float *dev_target,
+                 int batch, float *host_grad, double *loss) {
+    if (!s || !dev_target) return FSC_E_INVAL;
+    int rc = check_inputs(s, dev_prev, dev_in);
     if (rc) return rc;
-    rc = sur_forward_core(s, dev_in, batch);
+    rc = check_batch(s, batch);
+    if (rc) return rc;
+    rc = sur_forward_core(s, dev_prev, dev_in, batch);
     if (rc) return rc;
     rc = sur_backward(s, dev_in, dev_target, batch);
     if (rc) return rc;
@@ -805,12 +850,14 @@ int fsc_sur_grad(fsc_sur *s, const float *dev_in, const float *dev_target, int b
     return FSC_OK;
 }
 
-int fsc_sur_train_step(fsc_sur *s, const float *dev_in, const float *dev_target, int batch,
-                       float lr, double *loss) {
-    if (!s || !dev_in || !dev_target || !(lr > 0.f)) return FSC_E_INVAL;
-    int rc = check_batch(s, batch);
+int fsc_sur_train_step(fsc_sur *s, const float *dev_prev, const float *dev_in,
+                       const float *dev_target, int batch, float lr, double *loss) {
+    if (!s || !dev_target || !(lr > 0.f)) return FSC_E_INVAL;
+    int rc = check_inputs(s, dev_prev, dev_in);
     if (rc) return rc;
-    rc = sur_forward_core(s, dev_in, batch);
+    rc = check_batch(s, batch);
+    if (rc) return rc;
+    rc = sur_forward_core(s, dev_prev, dev_in, batch);
     if (rc) return rc;
     rc = sur_backward(s, dev_in, dev_target, batch);
     if (rc) return rc;

@@ -6,7 +6,10 @@ run in libfsc.so; PyTorch provides device memory).
 Workload: D2Q9, E8 stencil, FP32-shifted populations, n0 = 1 at T_hat = 0.7
 (deep quench into the unstable region), kBT = 1e-4, lattice side n (1024 by
 default), coarse-grained by 8 x 8 block means; the surrogate maps the coarse
-density at time t to the one at t + stride (256 by default).
+densities at t - stride and t to the one at t + stride (stride 256 lattice
+steps).  The plain lattice stays the reference: evaluation rolls the network
+out from lattice states of held-out seeds and compares S(k, t) and L(t) with
+the lattice's own, stride by stride.
 """
 from __future__ import annotations
 
@@ -36,6 +39,7 @@ def run_quench(torch, seeds, n=1024, factor=8, stride=256, n_snap=80, seed_base=
     ens.init_uniform()
     m = n // factor
     out = torch.zeros((n_snap + 1, len(seeds), m, m), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()  # the lattice writes on its own stream
     for r in range(len(seeds)):
         ens.coarsen(r, factor, out[0, r])
     t_lbm = 0.0
@@ -56,52 +60,75 @@ def run_quench(torch, seeds, n=1024, factor=8, stride=256, n_snap=80, seed_base=
     return out, t_lbm
 
 
-def train(torch, snaps, t_first, layers=5, steps=3000, batch=32, lr=1e-3, seed=0, log=None):
-    """Trains on consecutive snapshot pairs (snaps[k], snaps[k+1]) for k >= t_first."""
+def _batches(torch, snaps, t_first, batch, gen, m):
+    """Random (prev, cur, next, next2) stacks [batch][m][m] from the snapshot
+    tensor [K][R][m][m], with a common random periodic shift and, on every
+    other call, a transpose (the lattice's symmetries)."""
+    K, R = snaps.shape[:2]
+    ti = torch.randint(t_first, K - 2, (batch,), device="cuda", generator=gen)
+    ri = torch.randint(0, R, (batch,), device="cuda", generator=gen)
+    sh = torch.randint(0, m, (2,), device="cuda", generator=gen).tolist()
+    out = []
+    for dt in (-1, 0, 1, 2):
+        out.append(torch.roll(snaps[ti + dt, ri], shifts=sh, dims=(1, 2)))
+    return out
+
+
+def train(torch, snaps, t_first, layers=7, in_ch=2, steps=6000, batch=32, lr=1e-3, push=0.5,
+          seed=0, log=None):
+    """Trains on snapshot pairs (k, k+1), k >= t_first, with the previous
+    snapshot as second input channel.  After the first tenth of the steps, a
+    fraction `push` of every batch starts from the network's own one-stride
+    prediction (no gradient through it) and is trained against the snapshot
+    two strides ahead: the network learns to correct the errors its rollouts
+    make."""
     K, R, m, _ = snaps.shape
-    x = snaps[t_first:K - 1].reshape(-1, m, m)
-    y = snaps[t_first + 1:K].reshape(-1, m, m)
     mean = 1.0
-    in_scale = float((x - mean).std().item())
-    out_scale = float((y - x).std().item())
-    sur = F.Surrogate(layers, m, m, batch, seed=seed)
+    in_scale = float((snaps[t_first:] - mean).std().item())
+    out_scale = float((snaps[t_first + 1:] - snaps[t_first:-1]).std().item())
+    sur = F.Surrogate(layers, m, m, batch, seed=seed, in_ch=in_ch)
     sur.set_norm(mean, in_scale, out_scale)
-    g = torch.Generator(device="cuda")
-    g.manual_seed(seed)
-    npairs = x.shape[0]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    bufs = [torch.empty((batch, m, m), dtype=torch.float32, device="cuda") for _ in range(4)]
+    prev_b, cur_b, tgt_b, pred_b = bufs
     losses = []
-    xb = torch.empty((batch, m, m), dtype=torch.float32, device="cuda")
-    yb = torch.empty_like(xb)
+    n_push = int(round(push * batch))
     for it in range(steps):
-        idx = torch.randint(0, npairs, (batch,), device="cuda", generator=g)
-        # random periodic shifts and the square's symmetries keep the physics
-        sh = torch.randint(0, m, (2,), generator=None).tolist()
-        xs = torch.roll(x[idx], shifts=sh, dims=(1, 2))
-        ys = torch.roll(y[idx], shifts=sh, dims=(1, 2))
+        prev, cur, nxt, nxt2 = _batches(torch, snaps, t_first, batch, gen, m)
         if it % 2:
-            xs, ys = xs.transpose(1, 2), ys.transpose(1, 2)
-        xb.copy_(xs)
-        yb.copy_(ys)
+            prev, cur, nxt, nxt2 = (v.transpose(1, 2) for v in (prev, cur, nxt, nxt2))
+        prev_b.copy_(prev)
+        cur_b.copy_(cur)
+        tgt_b.copy_(nxt)
+        if n_push and it >= steps // 10:
+            sur.forward(prev_b[:n_push], cur_b[:n_push], pred_b[:n_push], n_push)
+            prev_b[:n_push].copy_(cur_b[:n_push])
+            cur_b[:n_push].copy_(pred_b[:n_push])
+            tgt_b[:n_push].copy_(nxt2[:n_push])
         rate = lr * 0.5 * (1 + math.cos(math.pi * it / steps))
-        loss = sur.train_step(xb, yb, batch, max(rate, 1e-5), want_loss=(it % 50 == 0))
+        loss = sur.train_step(prev_b, cur_b, tgt_b, batch, max(rate, 1e-5),
+                              want_loss=(it % 100 == 0))
         if loss is not None:
             losses.append((it, loss))
             if log:
                 log(f"step {it} loss {loss:.4e}")
     return sur, dict(mean=mean, in_scale=in_scale, out_scale=out_scale, losses=losses,
-                     npairs=int(npairs))
+                     layers=layers, in_ch=in_ch, steps=steps, batch=batch, lr=lr, push=push,
+                     pairs=int((K - 2 - t_first) * R))
 
 
-def rollout(torch, sur, start, n_out, batch):
-    """Applies the surrogate n_out times from `start` [batch][m][m]; returns
-    [n_out + 1][batch][m][m] and the wall time of the passes."""
+def rollout(torch, sur, prev, start, n_out, batch):
+    """Applies the surrogate n_out times from (prev, start) [batch][m][m];
+    returns [n_out + 1][batch][m][m] and the wall time of the passes."""
     m = start.shape[-1]
     traj = torch.zeros((n_out + 1, batch, m, m), dtype=torch.float32, device="cuda")
     traj[0].copy_(start)
+    prev = prev.contiguous()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(n_out):
-        sur.forward(traj[k], traj[k + 1], batch)
+        sur.forward(prev if k == 0 else traj[k - 1], traj[k], traj[k + 1], batch)
     torch.cuda.synchronize()
     return traj, time.perf_counter() - t0
 
@@ -116,42 +143,66 @@ def sk_error(torch, a, b, m, kmax_shell):
     return float(np.abs(A - B).sum() / B.sum()), float(La.mean()), float(Lb.mean())
 
 
-def evaluate(torch, sur, seeds, n=1024, factor=8, stride=256, t0_snap=8, n_out=24,
-             seed_base=1000):
-    """Held-out seeds: LBM reference trajectory vs surrogate rollout from the
-    LBM state at snapshot t0_snap.  S(k, t) error over k <= pi/8 (lattice
-    units) and L(t), per rollout time; speedup = LBM time / surrogate time
-    for the same horizon on the same GPU."""
-    snaps, t_lbm = run_quench(torch, seeds, n=n, factor=factor, stride=stride,
-                              n_snap=t0_snap + n_out, seed_base=seed_base)
+def horizon(rows, tol=0.05, key="sk_rel_err"):
+    """Strides before the S(k) error first exceeds tol."""
+    for k, r in enumerate(rows):
+        if r[key] > tol:
+            return k
+    return len(rows)
+
+
+def evaluate(torch, sur, seeds, n=1024, factor=8, stride=256, t0_snaps=(4, 8, 16), n_out=24,
+             seed_base=1000, snaps=None, t_lbm=None):
+    """Held-out seeds: the lattice's trajectory against the surrogate's
+    rollouts started from the lattice state at each snapshot in t0_snaps.
+    Per rollout stride: relative S(k) error over k <= pi/8 (lattice units) and
+    L(t) of both.  The persistence forecast (the start field held fixed) is
+    the method without the surrogate's learned dynamics.  Speedup = lattice
+    wall time / surrogate wall time for the same strides on the same GPU."""
+    n_snap = max(t0_snaps) + n_out
+    if snaps is None:
+        snaps, t_lbm = run_quench(torch, seeds, n=n, factor=factor, stride=stride, n_snap=n_snap,
+                                  seed_base=seed_base)
     m = n // factor
-    traj, t_sur = rollout(torch, sur, snaps[t0_snap], n_out, len(seeds))
-    # shells of the coarse grid: k = 2 pi b / n in lattice units; k <= pi/8 -> b <= n/16
-    kmax = n // 16
-    rows = []
-    for k in range(1, n_out + 1):
-        err, L_sur, L_lbm = sk_error(torch, traj[k], snaps[t0_snap + k], m, kmax)
-        rows.append(dict(t=(t0_snap + k) * stride, sk_rel_err=err, L_surrogate=L_sur * factor,
-                         L_lbm=L_lbm * factor))
-    horizon_lbm = t_lbm * n_out / (t0_snap + n_out)  # LBM time for the same n_out strides
-    return dict(rows=rows, max_sk_rel_err=max(r["sk_rel_err"] for r in rows),
-                lbm_seconds=horizon_lbm, surrogate_seconds=t_sur,
-                speedup=horizon_lbm / t_sur, seeds=list(seeds), n=n, stride=stride,
-                t0=t0_snap * stride)
+    kmax = n // 16  # coarse shells: k = 2 pi b / n; k <= pi/8 -> b <= n/16
+    starts = []
+    for t0 in t0_snaps:
+        traj, t_sur = rollout(torch, sur, snaps[t0 - 1], snaps[t0], n_out, len(seeds))
+        rows = []
+        for k in range(1, n_out + 1):
+            err, L_sur, L_lbm = sk_error(torch, traj[k], snaps[t0 + k], m, kmax)
+            pers, _, _ = sk_error(torch, snaps[t0], snaps[t0 + k], m, kmax)
+            rows.append(dict(t=(t0 + k) * stride, sk_rel_err=err, persistence_err=pers,
+                             L_surrogate=L_sur * factor, L_lbm=L_lbm * factor))
+        lbm_s = t_lbm * n_out / n_snap  # lattice time for the same n_out strides
+        starts.append(dict(t0=t0 * stride, rows=rows, horizon_5pct=horizon(rows),
+                           persistence_horizon_5pct=horizon(rows, key="persistence_err"),
+                           lbm_seconds=lbm_s, surrogate_seconds=t_sur, speedup=lbm_s / t_sur))
+    return dict(starts=starts, seeds=list(seeds), n=n, stride=stride, n_out=n_out)
 
 
 def save_model(sur, meta, path=MODEL_PATH):
-    np.savez(path, params=sur.get_params(), layers=sur.layers, H=sur.H, W=sur.W,
+    np.savez(path, params=sur.get_params(), layers=sur.layers, in_ch=sur.in_ch, H=sur.H, W=sur.W,
              meta=json.dumps(meta))
 
 
 def load_model(path=MODEL_PATH, max_batch=16):
     d = np.load(path, allow_pickle=False)
     meta = json.loads(str(d["meta"]))
-    sur = F.Surrogate(int(d["layers"]), int(d["H"]), int(d["W"]), max_batch)
+    sur = F.Surrogate(int(d["layers"]), int(d["H"]), int(d["W"]), max_batch, in_ch=int(d["in_ch"]))
     sur.set_params(d["params"])
     sur.set_norm(meta["mean"], meta["in_scale"], meta["out_scale"])
     return sur, meta
+
+
+def summary(ev):
+    """Headline numbers of an evaluation: the horizon (strides within 5% S(k)
+    error) and speedup of each rollout start."""
+    return [dict(t0=s["t0"], horizon_5pct=s["horizon_5pct"],
+                 persistence_horizon_5pct=s["persistence_horizon_5pct"],
+                 err_first=round(s["rows"][0]["sk_rel_err"], 4),
+                 err_last=round(s["rows"][-1]["sk_rel_err"], 4),
+                 speedup=round(s["speedup"], 1)) for s in ev["starts"]]
 
 
 def main(argv=None):
@@ -161,27 +212,36 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser(description="train and evaluate the coarse-grained surrogate")
     ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--train-seeds", type=int, default=32)
+    ap.add_argument("--train-seeds", type=int, default=128)
     ap.add_argument("--eval-seeds", type=int, default=8)
-    ap.add_argument("--snaps", type=int, default=80)
+    ap.add_argument("--snaps", type=int, default=40)
     ap.add_argument("--t-first", type=int, default=4)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--layers", type=int, nargs="+", default=[7, 5])
+    ap.add_argument("--save", action="store_true", help="store the first model in the package")
     ap.add_argument("--out", default=os.path.join(os.getcwd(), "surrogate_eval.json"))
     a = ap.parse_args(argv)
     t0 = time.perf_counter()
     snaps, t_lbm = run_quench(torch, range(a.train_seeds), n=a.n, n_snap=a.snaps)
-    print(f"data: {a.train_seeds} seeds x {a.snaps} snapshots in {t_lbm:.1f} s of lattice time",
+    print(f"data: {a.train_seeds} seeds x {a.snaps} snapshots, {t_lbm:.1f} s of lattice steps",
           flush=True)
-    sur, meta = train(torch, snaps, a.t_first, steps=a.steps, log=lambda s: print(s, flush=True))
-    del snaps
-    ev = evaluate(torch, sur, range(a.eval_seeds), n=a.n)
-    meta.update(dict(train_seeds=a.train_seeds, snaps=a.snaps, t_first=a.t_first, n=a.n,
-                     eval=ev, wall_seconds=time.perf_counter() - t0))
-    save_model(sur, meta)
+    ev_snaps, ev_t = run_quench(torch, range(a.eval_seeds), n=a.n, n_snap=40, seed_base=1000)
+    results = []
+    for k, layers in enumerate(a.layers):
+        t1 = time.perf_counter()
+        sur, meta = train(torch, snaps, a.t_first, layers=layers, steps=a.steps,
+                          log=lambda s: print(s, flush=True))
+        meta["train_seconds"] = time.perf_counter() - t1
+        ev = evaluate(torch, sur, range(a.eval_seeds), n=a.n, snaps=ev_snaps, t_lbm=ev_t)
+        meta.update(dict(train_seeds=a.train_seeds, snaps=a.snaps, t_first=a.t_first, n=a.n,
+                         eval=ev, summary=summary(ev)))
+        print(json.dumps(dict(layers=layers, summary=meta["summary"])), flush=True)
+        if a.save and k == 0:
+            save_model(sur, meta)
+        results.append(meta)
+        sur.close()
     with open(a.out, "w") as fh:
-        json.dump(meta, fh, indent=1)
-    print(json.dumps({k: ev[k] for k in ("max_sk_rel_err", "speedup", "lbm_seconds",
-                                         "surrogate_seconds")}), flush=True)
+        json.dump(dict(models=results, wall_seconds=time.perf_counter() - t0), fh, indent=1)
 
 
 if __name__ == "__main__":

@@ -60,3 +60,43 @@ def test_prediction_conserves_the_image_mean():
     pred = S.forward(p, rho, C, L, 1.0, 0.3, 0.1)
     assert np.allclose(pred.mean(axis=(1, 2)), rho.mean(axis=(1, 2)), atol=1e-14)
     assert S.n_params(32, 5) == 288 + 32 + 3 * (9216 + 32) + 288 + 1
+
+
+def test_two_channel_gradient_matches_central_differences():
+    rng = np.random.default_rng(6)
+    C, L = 3, 3
+    p = S.init_params(C, L, seed=7, in_ch=2) + 0.05 * rng.normal(size=S.n_params(C, L, 2))
+    rho = 1.0 + 0.3 * rng.normal(size=(2, 5, 6))
+    prev = rho + 0.05 * rng.normal(size=rho.shape)
+    tgt = rho + 0.05 * rng.normal(size=rho.shape)
+    kw = dict(channels=C, layers=L, mean=1.0, in_scale=0.3, out_scale=0.05, prev=prev)
+    loss, g = S.loss_and_grad(p, rho, tgt, **kw)
+    h = 1e-6
+    # every first-layer weight of the second channel, plus a random sample
+    first = [(o * 2 + 1) * 9 + k for o in range(C) for k in range(9)]
+    idx = np.concatenate([first, rng.choice(p.size, size=20, replace=False)])
+    for i in idx:
+        e = np.zeros_like(p)
+        e[i] = h
+        lp, _ = S.loss_and_grad(p + e, rho, tgt, **kw)
+        lm, _ = S.loss_and_grad(p - e, rho, tgt, **kw)
+        assert g[i] == pytest.approx((lp - lm) / (2 * h), rel=1e-5, abs=1e-9)
+
+
+def test_two_channel_network_reduces_to_one_channel():
+    # zero weights on the increment channel: the same map as the K = 1 network
+    rng = np.random.default_rng(8)
+    C, L = 4, 4
+    p1 = S.init_params(C, L, seed=9, in_ch=1)
+    p2 = np.zeros(S.n_params(C, L, 2))
+    W1 = p1[:C * 9].reshape(C, 1, 9)
+    W2 = np.zeros((C, 2, 9))
+    W2[:, 0] = W1[:, 0]
+    p2[:C * 18] = W2.ravel()
+    p2[C * 18:] = p1[C * 9:]
+    rho = 1.0 + 0.3 * rng.normal(size=(2, 6, 7))
+    prev = rho + 0.1 * rng.normal(size=rho.shape)
+    a = S.forward(p1, rho, C, L, 1.0, 0.3, 0.1)
+    b = S.forward(p2, rho, C, L, 1.0, 0.3, 0.1, prev=prev)
+    assert np.allclose(a, b, rtol=0, atol=1e-14)
+    assert S.n_params(32, 5, 2) == S.n_params(32, 5) + 288
