@@ -331,7 +331,7 @@ void build_desc(fsc_ens *e) {
     }
     // marching length: enough blocks to fill 256 CUs several times over,
     // but long marches so that the 2R halo planes stay a small overhead
-    int H = int(std::min<int64_t>(256, std::max<int64_t>(16, work / e->target_blocks)));
+    int H = int(std::min<int64_t>(256, std::max<int64_t>(8, work / e->target_blocks)));
     int tile_begin = 0;
     for (auto &r : e->reps) {
         RepDesc d{};
@@ -481,7 +481,9 @@ int ens_autotune(fsc_ens *e) {
     }
     TileShape shapes[8];
     const int nshape = tile_shapes(e->D, e->stencil, e->precision, shapes, 8);
-    const int64_t targets[3] = {1024, 2048, 4096};
+    // block counts around one and a few rounds of the ~1.5-2k blocks that
+    // are resident at once (256 CUs x 6-8 blocks of 256 threads)
+    const int64_t targets[] = {768, 1024, 1536, 2048, 3072, 4096, 6144};
     hipEvent_t a, b;
     HIPCHK(e, hipEventCreate(&a));
     HIPCHK(e, hipEventCreate(&b));

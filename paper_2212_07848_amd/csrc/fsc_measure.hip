@@ -481,22 +481,25 @@ hipError_t launch_series_finalize(double *mom, double *series, int *series_n, in
 // Plain device copy (16-byte lanes, grid-stride): the practical HBM
 // read+write ceiling and the calibration for the memory-traffic counters.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_copy(const uint4 *__restrict__ src,
-                                              uint4 *__restrict__ dst, int64_t n16) {
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_copy(const u32x4 *__restrict__ src,
+                                              u32x4 *__restrict__ dst, int64_t n16) {
     // each block moves 4 consecutive 4 KiB pieces per iteration: four
-    // independent 16-byte loads per lane are in flight before the stores
+    // independent 16-byte loads per lane are in flight before the stores;
+    // non-temporal loads and stores (the fastest plain copy measured on gfx950)
     const int64_t stride = int64_t(gridDim.x) * 1024;
     for (int64_t base = int64_t(blockIdx.x) * 1024; base < n16; base += stride) {
-        uint4 v[4];
+        u32x4 v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t k = base + u * 256 + threadIdx.x;
-            if (k < n16) v[u] = src[k];
+            if (k < n16) v[u] = __builtin_nontemporal_load(src + k);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t k = base + u * 256 + threadIdx.x;
-            if (k < n16) dst[k] = v[u];
+            if (k < n16) __builtin_nontemporal_store(v[u], dst + k);
         }
     }
 }
@@ -505,9 +508,9 @@ hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t s)
     if (bytes <= 0 || (bytes & 15)) return hipErrorInvalidValue;
     const int64_t n16 = bytes / 16;
     const int64_t want = (n16 + 1023) / 1024;
-    const unsigned blocks = unsigned(want < 4096 ? want : 4096);
-    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, static_cast<const uint4 *>(src),
-                       static_cast<uint4 *>(dst), n16);
+    const unsigned blocks = unsigned(want < 16384 ? want : 16384);
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, static_cast<const u32x4 *>(src),
+                       static_cast<u32x4 *>(dst), n16);
     return hipGetLastError();
 }
 
