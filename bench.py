@@ -57,9 +57,14 @@ def traffic_from_profile(stencil: str, noise: bool, tiling: dict):
     tag = f"{stencil}, float, {'true' if noise else 'false'}, {tiling['tx']}, {tiling['ty']}, " \
           f"{tiling['pf']}>"
     threads = tiling["blocks"] * tiling["tx"] * tiling["ty"]
-    for e in doc["entries"]:
-        if e["kernel"].endswith(tag) and e["grid_threads"] == threads:
-            return e["bytes_per_launch"]
+    same = [e for e in doc["entries"] if e["kernel"].endswith(tag)]
+    for e in same:
+        if e["grid_threads"] == threads:
+            return e["bytes_per_launch"], "same kernel and launch shape"
+    if same:  # the autotuner picked another march length than in the counter run
+        e = min(same, key=lambda e: abs(e["grid_threads"] - threads))
+        return e["bytes_per_launch"], f"same kernel, nearest launch shape ({e['grid_threads']} " \
+                                      f"threads in the counter run, {threads} here)"
     return None
 
 
@@ -106,6 +111,8 @@ def ingest_pmc(fetch_csv: str, write_csv: str, out_path: str):
         entries.append(dict(kernel=key[0], grid_threads=key[1], launches=counts[key],
                             fetch_bytes=int(fetch[key]), write_bytes=int(write[key]),
                             bytes_per_launch=int(fetch[key] + write[key])))
+    for e in entries:
+        e["kernel"] = e["kernel"].replace("fsc::", "")
     doc = dict(kernel_hash=kernel_hash(),
                commands=[f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch_dir> -o run "
                          f"-- python3 bench.py {PMC_ARGS}",
@@ -118,8 +125,69 @@ def ingest_pmc(fetch_csv: str, write_csv: str, out_path: str):
                                 write_scale=round(wscale, 4)),
                entries=entries)
     with open(out_path, "w") as fh:
-        json.dump(doc, fh, indent=1)
+        head = {k: v for k, v in doc.items() if k != "entries"}
+        fh.write(json.dumps(head, indent=1)[:-2] + ',\n "entries": [\n')
+        fh.write(",\n".join("  " + json.dumps(e) for e in entries) + "\n ]\n}\n")
     return doc
+
+
+TRACE_ARGS = "--steps 400 --warmup 40 --kernel-steps 200 --no-cpu-baseline --no-surrogate"
+
+
+def summarize_trace(trace_dir: str, log_path: str, out_path: str):
+    """Markdown summary of a `rocprofv3 --kernel-trace --stats --output-format
+    csv` run of this script: rocprofv3's own per-kernel statistics, the
+    per-launch-shape means of the step kernels from the dispatch trace, and
+    the same run's HIP-event timing of the benchmarked launch shape."""
+    import csv
+    from collections import defaultdict
+    with open(os.path.join(trace_dir, "run_kernel_stats.csv")) as fh:
+        stats = list(csv.DictReader(fh))
+    shapes = defaultdict(list)
+    with open(os.path.join(trace_dir, "run_kernel_trace.csv")) as fh:
+        for r in csv.DictReader(fh):
+            if "fsc::k_step<" in r["Kernel_Name"]:
+                key = (r["Kernel_Name"].replace("void ", "").split("(")[0], int(r["Grid_Size_X"]))
+                shapes[key].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    bench = None
+    with open(log_path) as fh:
+        for line in fh:
+            if line.startswith('{"metric"'):
+                bench = json.loads(line)
+    lines = ["# Fused step kernels: rocprofv3 kernel trace of bench.py", "",
+             "Command (repository root as working directory, TMPDIR=/tmp):", "",
+             f"    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
+             f"python3 bench.py {TRACE_ARGS} > <log>",
+             f"    python3 bench.py --summarize-trace <dir> <log> <this file>", ""]
+    if bench:
+        rf = bench["roofline"]
+        t = rf["tiling"]
+        grid = t["blocks"] * t["tx"] * t["ty"]
+        key = next((k for k in shapes if k[1] == grid and k[0].endswith(
+            f"StencilE4_2D, float, true, {t['tx']}, {t['ty']}, {t['pf']}>")), None)
+        lines += ["## Benchmarked launch (64-replica D2Q9 ensemble, one launch per step)", "",
+                  f"- launch shape: {t['tx']}x{t['ty']} threads, prefetch {t['pf']}, "
+                  f"{t['blocks']} blocks ({grid} threads)",
+                  f"- HIP events in the same run: {rf['avg_launch_us']} us per launch"]
+        if key:
+            v = shapes[key]
+            lines.append(f"- rocprofv3 dispatch trace: {sum(v) / len(v) / 1e3:.2f} us mean over "
+                         f"{len(v)} dispatches (min {min(v) / 1e3:.2f}, max {max(v) / 1e3:.2f})")
+        lines += [f"- algorithmic bytes per launch: {bench['config']['lattice_updates_per_step']} "
+                  f"nodes x {rf['algorithmic_bytes_per_lup']} B", ""]
+    lines += ["## Step kernels by launch shape (dispatch trace)", "",
+              "| kernel | grid threads | dispatches | mean us |", "|---|---|---|---|"]
+    for (name, grid), v in sorted(shapes.items(), key=lambda kv: -sum(kv[1]))[:16]:
+        lines.append(f"| `{name.replace('fsc::', '')}` | {grid} | {len(v)} | "
+                     f"{sum(v) / len(v) / 1e3:.2f} |")
+    lines += ["", "## rocprofv3 kernel statistics (run_kernel_stats.csv, top 12)", "",
+              "| kernel | calls | mean us | % of GPU time |", "|---|---|---|---|"]
+    for r in stats[:12]:
+        name = r["Name"].replace("void ", "").split("(")[0].replace("fsc::", "")
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{r['Percentage']} |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def time_steps(obj, steps: int, stream, torch):
@@ -252,7 +320,12 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/step_traffic.json from two rocprofv3 counter runs")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "LOG", "OUT_MD"),
+                    help="write a markdown summary of a rocprofv3 kernel-trace run")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
     if args.ingest_pmc:
         doc = ingest_pmc(*args.ingest_pmc, os.path.join(ROOT, "profiles", "step_traffic.json"))
         print(f"{len(doc['entries'])} step-kernel launch shapes, calibration {doc['calibration']}")
@@ -273,7 +346,8 @@ def main():
     mlups = r["lups"] * args.steps / r["dt"] / 1e6
     bpl = bytes_per_lup(2, "fp32")
     achieved = r["lups"] * bpl / r["t_step"] / 1e9
-    traffic = traffic_from_profile("StencilE4_2D", True, r["tiling"])
+    tr = traffic_from_profile("StencilE4_2D", True, r["tiling"])
+    traffic, traffic_note = tr if tr else (None, "no counter run of this kernel source")
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -292,7 +366,8 @@ def main():
                    "kBT": 1e-13, "collision": "MRT all rates 1 (BGK tau=1)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_step<D2Q9,E4,float,noise>",
+                     "traffic": traffic, "traffic_source": traffic_note,
+                     "kernel": "k_step<D2Q9,E4,float,noise>",
                      "algorithmic_bytes_per_lup": bpl,
                      "avg_launch_us": round(r["t_step"] * 1e6, 2),
                      "tiling": r["tiling"]},
