@@ -492,6 +492,17 @@ __global__ void __launch_bounds__(TX *TY)
             const int m = m0 + j;
             if (m >= len) break;
             const int s = first + dir * m;
+            // The noise of this plane depends on neither memory nor LDS: it is
+            // generated first, so that it fills the wait for the prefetched
+            // plane and the barrier (nothing is scheduled across a barrier).
+            real z[NN];
+            if constexpr (NOISE) {
+                const uint32_t node = uint32_t(x + nx * (y + (D == 3 ? ny * s : s)));
+                node_normals<L, real>(node, step32, d.seed_hi, d.key0, d.key1, z);
+            } else {
+#pragma unroll
+                for (int k = 0; k < NN; ++k) z[k] = real(0);
+            }
             // plane s + dir R has arrived: its dpsi goes to LDS
             // PF = 0: plane s + dir R is loaded here, right before its dpsi is needed
             if constexpr (PF == 0) load_plane(s + dir * R, xo_m, F[(j + R) % NSLOT]);
@@ -523,14 +534,6 @@ __global__ void __launch_bounds__(TX *TY)
             const real pre = G * (psi0 + lds[sl[R]][ty + RY][tx + R]);
             const real Fv[3] = {pre * g[0], pre * g[1], pre * g[2]};
 
-            real z[NN];
-            if constexpr (NOISE) {
-                const uint32_t node = uint32_t(x + nx * (y + (D == 3 ? ny * s : s)));
-                node_normals<L, real>(node, step32, d.seed_hi, d.key0, d.key1, z);
-            } else {
-#pragma unroll
-                for (int k = 0; k < NN; ++k) z[k] = real(0);
-            }
             real(&fv)[Q] = F[j % NSLOT];
             if constexpr (D == 2) collide_d2q9<real, NOISE>(fv, rho0, Fv, lc, ac, z);
             else collide_d3q19<real, NOISE>(fv, rho0, Fv, lc, ac, z);
