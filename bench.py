@@ -260,28 +260,56 @@ def copy_ceiling(torch, fsc, nbytes=1 << 30, reps=20):
     return 2 * nbytes / t / 1e9
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(I, budget_s: float):
     """The FP64 oracle on a bounded sample of the ensemble workload: whole
-    replicas of the same workload, stepped until the time budget is used."""
+    replicas of the same workload, stepped until the time budget is used, on
+    all host threads and then on one."""
     import oracle as O
     reps = I.ensemble_replicas(n=64, seed=0, kBT=1e-13)
-    done_lups, t_used, sample = 0, 0.0, []
-    for r in reps:
-        if t_used > budget_s:
-            break
-        G = O.coupling_from_reduced_temperature(r["T_hat"])
-        f = O.uniform_state(2, (r["ny"], r["nx"]), r["rho0"])
-        nsteps = 40
-        t0 = time.perf_counter()
-        O.step(f, nsteps, G=G, kind=4, kBT=r["kBT"], seed=r["seed"], replica=r["replica"])
-        dt = time.perf_counter() - t0
-        t_used += dt
-        done_lups += r["nx"] * r["ny"] * nsteps
-        sample.append(f"r{r['replica']}:{r['nx']}^2x{nsteps}")
-    return dict(value=done_lups / t_used / 1e6, unit="MLUPS", cores=O.max_threads(),
-                kind="oracle",
-                sample=f"{len(sample)} of the 64 ensemble replicas (sides 128-512) x {nsteps} "
-                       f"steps each, {done_lups / 1e6:.0f} M lattice updates in {t_used:.1f} s")
+    nsteps = 40
+
+    def run(budget):
+        done_lups, t_used, nrep = 0, 0.0, 0
+        for r in reps:
+            if t_used > budget:
+                break
+            G = O.coupling_from_reduced_temperature(r["T_hat"])
+            f = O.uniform_state(2, (r["ny"], r["nx"]), r["rho0"])
+            t0 = time.perf_counter()
+            O.step(f, nsteps, G=G, kind=4, kBT=r["kBT"], seed=r["seed"], replica=r["replica"])
+            t_used += time.perf_counter() - t0
+            done_lups += r["nx"] * r["ny"] * nsteps
+            nrep += 1
+        return done_lups, t_used, nrep
+
+    threads = O.max_threads()
+    lups, t_used, nrep = run(budget_s)
+    O.set_threads(1)
+    lups1, t1, nrep1 = run(budget_s / 4)
+    O.set_threads(threads)
+    return dict(value=lups / t_used / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+                cpu=cpu_model(), single_core_value=round(lups1 / t1 / 1e6, 3),
+                sample=f"the first {nrep} of the 64 ensemble replicas (sides 128-512) x {nsteps} "
+                       f"steps each, {lups / 1e6:.0f} M lattice updates in {t_used:.1f} s on "
+                       f"{threads} threads; single thread: {nrep1} replicas in {t1:.1f} s")
+
+
+def surrogate_flops(meta, pixels: int) -> int:
+    """Multiply-add FLOPs of one network pass over `pixels` pixels (2 per MAC)."""
+    C, K, L = 32, meta.get("in_ch", 2), meta["layers"]
+    per_pixel = 2 * 9 * (K * C + (L - 2) * C * C + C)
+    return per_pixel * pixels
 
 
 def run_surrogate(torch):
@@ -303,6 +331,8 @@ def run_surrogate(torch):
             "persistence_horizon_strides": st["persistence_horizon_5pct"],
             "sk_rel_err_per_stride": [round(r["sk_rel_err"], 4) for r in st["rows"]],
             "speedup_at_5pct": round(st["speedup"], 1),
+            "bf16_tflops_in_rollout": round(surrogate_flops(meta, 128 * 128) * len(ev["seeds"])
+                                            * ev["n_out"] / st["surrogate_seconds"] / 1e12, 1),
             "lattice_s_per_stride": round(st["lbm_seconds"] / ev["n_out"], 5),
             "surrogate_s_per_stride": round(st["surrogate_seconds"] / ev["n_out"], 6)}
 

@@ -50,6 +50,8 @@ def _load():
                              C.c_uint64, C.c_uint32, C.c_int64, C.c_int64]
     lib.orc_conserved.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp]
     lib.orc_max_threads.argtypes = []
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_set_threads.restype = None
     _lib = lib
     return lib
 
@@ -61,6 +63,11 @@ def _dp(a: np.ndarray):
 
 def max_threads() -> int:
     return int(_load().orc_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's OpenMP loops."""
+    _load().orc_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------

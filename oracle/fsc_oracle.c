@@ -537,3 +537,13 @@ int orc_max_threads(void) {
     return 1;
 #endif
 }
+
+/* Thread count of the OpenMP loops (timing of the oracle on one core). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

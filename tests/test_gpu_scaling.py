@@ -1,0 +1,28 @@
+"""The S(k -> 0) scaling study on the GPU: S(0) extrapolated from the
+lattice's own low-k axis bins against Eq. 16 at each state point, and the
+exponents through those points against the exponents of the exact S(0) at
+the same points (which tend to -1/2 towards the spinodal, Eq. 10, and to -1
+towards the critical point along the binodal, Eq. 8)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+fsc = pytest.importorskip("paper_2212_07848_amd")
+from paper_2212_07848_amd import scaling as SC  # noqa: E402
+
+
+def test_scaling_study_reduced():
+    pts = SC.state_points(T_spin=0.8, spin_d=(0.1, 0.03, 0.01), bin_T=(0.9, 0.95, 0.98))
+    res, wall = SC.run(pts, n=64, seeds=32, burn=4000, steps=20000)
+    for r in res:
+        ratio = r["S0_fit"] / r["S0_exact"]
+        print(r["kind"], r["side"], r["T_hat"], r["d"], round(ratio, 4))
+        assert abs(ratio - 1) < 0.06, (r["kind"], r["side"], r["d"], ratio)
+        # every measured mode against Eq. 16
+        S, ex = np.array(r["S"]), np.array(r["S_exact"])
+        assert np.max(np.abs(S / ex - 1)) < 0.1
+    ex = SC.exponents(res)
+    print(ex, "lattice seconds", wall)
+    for key, e in ex.items():
+        assert abs(e["measured"] - e["exact_same_points"]) < 0.06, (key, e)
