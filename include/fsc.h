@@ -199,6 +199,8 @@ int fsc_ens_get_step(const fsc_ens *ens, int64_t *step);
 int fsc_ens_get_populations(fsc_ens *ens, int replica, double *host_f);
 int fsc_ens_set_populations(fsc_ens *ens, int replica, const double *host_f);
 int fsc_ens_stats(fsc_ens *ens, int replica, double *out8);
+/* Density of one replica's current state, host double [nz][ny][nx]. */
+int fsc_ens_density(fsc_ens *ens, int replica, double *host_rho);
 int fsc_ens_sk_nbins(const fsc_ens *ens, int replica, int kind, int *nbins);
 int fsc_ens_read_sk(fsc_ens *ens, int replica, int kind, double *sum, double *sumsq,
                     int64_t *count, int nbins);

@@ -32,7 +32,7 @@ EXPORTS = [
     "fsc_measure_sk", "fsc_sk_nbins", "fsc_read_sk", "fsc_series_enable", "fsc_read_series",
     "fsc_ens_create", "fsc_ens_destroy", "fsc_ens_last_error", "fsc_ens_init_uniform",
     "fsc_ens_run", "fsc_ens_get_step", "fsc_ens_get_populations", "fsc_ens_set_populations",
-    "fsc_ens_stats", "fsc_ens_sk_nbins", "fsc_ens_read_sk", "fsc_ens_sk_reset",
+    "fsc_ens_stats", "fsc_ens_density", "fsc_ens_sk_nbins", "fsc_ens_read_sk", "fsc_ens_sk_reset",
     "fsc_ens_save", "fsc_ens_load", "fsc_ens_series_enable", "fsc_ens_read_series",
     "fsc_autotune", "fsc_ens_autotune", "fsc_get_tiling", "fsc_ens_get_tiling",
     "fsc_copy", "fsc_philox", "fsc_normals",
@@ -122,6 +122,7 @@ def lib():
         "fsc_ens_sk_nbins": ([vp, C.c_int, C.c_int, C.POINTER(C.c_int)], C.c_int),
         "fsc_ens_read_sk": ([vp, C.c_int, C.c_int, dp, dp, i64p, C.c_int], C.c_int),
         "fsc_ens_sk_reset": ([vp], C.c_int),
+        "fsc_ens_density": ([vp, C.c_int, dp], C.c_int),
         "fsc_autotune": ([vp], C.c_int),
         "fsc_ens_autotune": ([vp], C.c_int),
         "fsc_get_tiling": ([vp, C.POINTER(C.c_int)], C.c_int),
@@ -404,6 +405,13 @@ class Ensemble:
 
     def sk_reset(self):
         self._c(lib().fsc_ens_sk_reset(self._h))
+
+    def density(self, r: int):
+        p = self.plist[r]
+        shape = (p.ny, p.nx) if p.D == 2 else (p.nz, p.ny, p.nx)
+        out = np.empty(shape)
+        self._c(lib().fsc_ens_density(self._h, r, _dp(out)))
+        return out
 
     def save(self, path: str):
         """Checkpoint of every replica (see fsc_ens_save)."""

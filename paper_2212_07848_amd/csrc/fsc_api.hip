@@ -774,6 +774,26 @@ int ens_init_uniform(fsc_ens *e) {
     return ens_sk_reset(e);
 }
 
+// Density n(x) of one replica's current state into host doubles [nz][ny][nx].
+int ens_density(fsc_ens *e, int ri, double *host_rho) {
+    Rep &r = e->reps[ri];
+    void *tmp = nullptr;
+    if (hipMalloc(&tmp, r.esz * size_t(r.N)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e, FSC_E_OOM, "density buffer");
+    }
+    hipError_t ec = launch_density_real(r.geom(), r.p.precision, r.buf[e->step & 1], tmp, e->stream);
+    std::vector<unsigned char> raw(r.esz * size_t(r.N));
+    if (ec == hipSuccess) ec = hipMemcpyAsync(raw.data(), tmp, raw.size(), hipMemcpyDeviceToHost, e->stream);
+    if (ec == hipSuccess) ec = hipStreamSynchronize(e->stream);
+    (void)hipFree(tmp);
+    if (ec != hipSuccess) return fail(e, FSC_E_HIP, hipGetErrorString(ec));
+    for (int64_t s = 0; s < r.N; ++s)
+        host_rho[s] = r.p.rho0 + (r.esz == 4 ? double(reinterpret_cast<float *>(raw.data())[s])
+                                             : reinterpret_cast<double *>(raw.data())[s]);
+    return FSC_OK;
+}
+
 // ---- checkpoints -----------------------------------------------------------
 // File layout (native byte order): magic "FSCK", u32 version, u32 replica count,
 // u32 zero, i64 step; then per replica: its resolved fsc_params, i64 S(k)
@@ -956,23 +976,7 @@ int fsc_get_step(const fsc_ctx *ctx, int64_t *step) {
 
 int fsc_density(fsc_ctx *ctx, double *host_rho) {
     if (!ctx || !host_rho) return FSC_E_INVAL;
-    fsc_ens *e = ctx->e;
-    Rep &r = e->reps[0];
-    void *tmp = nullptr;
-    if (hipMalloc(&tmp, r.esz * size_t(r.N)) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(e, FSC_E_OOM, "density buffer");
-    }
-    hipError_t ec = launch_density_real(r.geom(), r.p.precision, r.buf[e->step & 1], tmp, e->stream);
-    std::vector<unsigned char> raw(r.esz * size_t(r.N));
-    if (ec == hipSuccess) ec = hipMemcpyAsync(raw.data(), tmp, raw.size(), hipMemcpyDeviceToHost, e->stream);
-    if (ec == hipSuccess) ec = hipStreamSynchronize(e->stream);
-    (void)hipFree(tmp);
-    if (ec != hipSuccess) return fail(e, FSC_E_HIP, hipGetErrorString(ec));
-    for (int64_t s = 0; s < r.N; ++s)
-        host_rho[s] = r.p.rho0 + (r.esz == 4 ? double(reinterpret_cast<float *>(raw.data())[s])
-                                             : reinterpret_cast<double *>(raw.data())[s]);
-    return FSC_OK;
+    return ens_density(ctx->e, 0, host_rho);
 }
 
 int fsc_stats(fsc_ctx *ctx, double *out8) {
@@ -1054,6 +1058,11 @@ int fsc_ens_read_sk(fsc_ens *ens, int replica, int kind, double *sum, double *su
     return rc ? rc : ens_read_sk(ens, replica, kind, sum, sumsq, count, nbins);
 }
 int fsc_ens_sk_reset(fsc_ens *ens) { return ens ? ens_sk_reset(ens) : FSC_E_INVAL; }
+int fsc_ens_density(fsc_ens *ens, int replica, double *host_rho) {
+    if (!ens || !host_rho) return FSC_E_INVAL;
+    int rc = rep_index(ens, replica);
+    return rc ? rc : ens_density(ens, replica, host_rho);
+}
 int fsc_ens_save(fsc_ens *ens, const char *path) {
     return ens && path ? ens_save(ens, path) : FSC_E_INVAL;
 }
