@@ -223,6 +223,31 @@ int fsc_ens_read_series(fsc_ens *ens, int replica, double *out, int max_rows, in
                         int *row_len);
 
 /* ----------------------------------------------------------------------- */
+/* Exact linear theory for any wave vector.                                 */
+/* ----------------------------------------------------------------------- */
+
+/* Stationary structure factor of the fluctuating step linearised around the
+ * homogeneous state n0 = p->rho0 (Eq. 12 with the force of Eq. 1 linearised):
+ * S(k) = 1^T X 1, X = sum_j A^j Qn (A^j)^H, where A(k) is the linearised
+ * step (collision with the Guo source, then streaming) and Qn(k) the
+ * covariance of the noise; on a lattice axis with the E4 stencil this is
+ * Eq. 16.  host_k: nk wave vectors [nk][D] in lattice units (k = 2 pi m / L);
+ * host_s: nk doubles (out).  Uses p's D, stencil, T_hat or G, rho0, rates and
+ * kBT (sides are ignored).  FP64 on the GPU, one workgroup per wave vector;
+ * synchronous on `stream` (NULL: the default stream).  Errors: FSC_E_INVAL,
+ * FSC_E_OOM, FSC_E_HIP. */
+int fsc_linear_sk(const fsc_params *p, const double *host_k, int64_t nk, double *host_s,
+                  void *stream);
+/* The same averaged over the radial shells b = round(|m|) of all wave
+ * vectors m != 0 of p's square (2D) or cubic (3D) lattice, as the radial bins
+ * of fsc_read_sk: host_shell_mean[b] and, if not NULL, host_count[b] modes,
+ * b < nbins (shells beyond are dropped).  Uses the symmetry of the square /
+ * cube (one wave vector per orbit).  FSC_E_INVAL unless the sides are
+ * equal. */
+int fsc_linear_sk_radial(const fsc_params *p, double *host_shell_mean, int64_t *host_count,
+                         int nbins, void *stream);
+
+/* ----------------------------------------------------------------------- */
 /* Learned coarse-grained surrogate (not in the paper).                     */
 /*                                                                          */
 /* A periodic convolutional network advances the block-averaged density of  */

@@ -35,7 +35,7 @@ EXPORTS = [
     "fsc_ens_stats", "fsc_ens_density", "fsc_ens_sk_nbins", "fsc_ens_read_sk", "fsc_ens_sk_reset",
     "fsc_ens_save", "fsc_ens_load", "fsc_ens_series_enable", "fsc_ens_read_series",
     "fsc_autotune", "fsc_ens_autotune", "fsc_get_tiling", "fsc_ens_get_tiling",
-    "fsc_copy", "fsc_philox", "fsc_normals",
+    "fsc_copy", "fsc_philox", "fsc_normals", "fsc_linear_sk", "fsc_linear_sk_radial",
     "fsc_sur_create", "fsc_sur_destroy", "fsc_sur_last_error", "fsc_sur_nparams",
     "fsc_sur_set_params", "fsc_sur_get_params", "fsc_sur_set_norm", "fsc_sur_forward",
     "fsc_sur_grad", "fsc_sur_train_step", "fsc_coarsen", "fsc_ens_coarsen", "fsc_field_nbins",
@@ -123,6 +123,8 @@ def lib():
         "fsc_ens_read_sk": ([vp, C.c_int, C.c_int, dp, dp, i64p, C.c_int], C.c_int),
         "fsc_ens_sk_reset": ([vp], C.c_int),
         "fsc_ens_density": ([vp, C.c_int, dp], C.c_int),
+        "fsc_linear_sk": ([pp, dp, C.c_int64, dp, vp], C.c_int),
+        "fsc_linear_sk_radial": ([pp, dp, i64p, C.c_int, vp], C.c_int),
         "fsc_autotune": ([vp], C.c_int),
         "fsc_ens_autotune": ([vp], C.c_int),
         "fsc_get_tiling": ([vp, C.POINTER(C.c_int)], C.c_int),
@@ -528,6 +530,24 @@ def field_sk(fields, batch: int, n: int, stream=None):
     _check(lib().fsc_field_sk(ptr, batch, n, n, _stream_handle(_torch_stream_or(stream)),
                               _dp(shells), _dp(L), nb.value))
     return shells, L
+
+
+def linear_sk(p: Params, kvecs) -> np.ndarray:
+    """Exact stationary S(k) of the linearised step at wave vectors [nk][D]."""
+    k = np.ascontiguousarray(kvecs, dtype=np.float64).reshape(-1, p.D)
+    out = np.zeros(k.shape[0])
+    _check(lib().fsc_linear_sk(C.byref(p), _dp(k), k.shape[0], _dp(out), None))
+    return out
+
+
+def linear_sk_radial(p: Params, nbins: int):
+    """Shell means of the exact linear S(k) over the lattice's wave vectors,
+    binned like the radial structure-factor bins; returns (mean, modes)."""
+    mean = np.zeros(nbins)
+    cnt = np.zeros(nbins, dtype=np.int64)
+    _check(lib().fsc_linear_sk_radial(C.byref(p), _dp(mean), cnt.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      nbins, None))
+    return mean, cnt
 
 
 def mfma_probe(A: np.ndarray, B: np.ndarray) -> np.ndarray:

@@ -29,6 +29,7 @@ SOURCES = [
     "fsc_step_d3e4_f64.hip",
     "fsc_measure.hip",
     "fsc_surrogate.hip",
+    "fsc_linear.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
