@@ -218,6 +218,19 @@ int fsc_ens_sk_reset(fsc_ens *ens);
  * Time-series rows (fsc_ens_series_enable) are not part of the file. */
 int fsc_ens_save(fsc_ens *ens, const char *path);
 int fsc_ens_load(fsc_ens *ens, const char *path);
+/* Recorded mode amplitudes (for the dynamic structure factor).  Once
+ * enabled, every S(k) sample (fsc_measure_sk, or the samples of fsc_run /
+ * fsc_ens_run) also stores the complex amplitudes
+ * dn^(k) = sum_x (n(x) - n0) e^{-i k.x} of the modes m = 1..nm along each
+ * lattice axis (k = 2 pi m / side) as a row [D][nm][2] of doubles (real,
+ * imaginary); rows past `capacity` are dropped.  Enabling (capacity >= 1,
+ * 1 <= nm <= side/2) allocates and clears the rows; capacity 0 disables.
+ * fsc_read_modes copies min(recorded, max_rows) rows to `out` and returns
+ * the number recorded in *nrows.  Errors: FSC_E_INVAL, FSC_E_OOM, FSC_E_HIP. */
+int fsc_modes_enable(fsc_ctx *ctx, int nm, int capacity);
+int fsc_read_modes(fsc_ctx *ctx, double *out, int max_rows, int *nrows);
+int fsc_ens_modes_enable(fsc_ens *ens, int nm, int capacity);
+int fsc_ens_read_modes(fsc_ens *ens, int replica, double *out, int max_rows, int *nrows);
 int fsc_ens_series_enable(fsc_ens *ens, int capacity);
 int fsc_ens_read_series(fsc_ens *ens, int replica, double *out, int max_rows, int *nrows,
                         int *row_len);
@@ -246,6 +259,15 @@ int fsc_linear_sk(const fsc_params *p, const double *host_k, int64_t nk, double 
  * equal. */
 int fsc_linear_sk_radial(const fsc_params *p, double *host_shell_mean, int64_t *host_count,
                          int nbins, void *stream);
+/* Time correlation of the linearised dynamics in the stationary state:
+ * C(k, tau) = <dn^(k, t + tau) dn^(k, t)*> / N = 1^T A^tau X 1 (C(k, 0) is
+ * fsc_linear_sk), for nk wave vectors host_k [nk][D] and nlag lags
+ * host_lags[] >= 0 in lattice steps (ascending); host_c [nk][nlag][2]
+ * (real, imaginary; the imaginary part vanishes for the symmetric lattices
+ * here).  Its Fourier transform over tau is the dynamic structure factor
+ * S(k, omega) of the linearised step.  Errors as fsc_linear_sk. */
+int fsc_linear_corr(const fsc_params *p, const double *host_k, int64_t nk, const int *host_lags,
+                    int nlag, double *host_c, void *stream);
 
 /* ----------------------------------------------------------------------- */
 /* Learned coarse-grained surrogate (not in the paper).                     */

@@ -33,9 +33,11 @@ EXPORTS = [
     "fsc_ens_create", "fsc_ens_destroy", "fsc_ens_last_error", "fsc_ens_init_uniform",
     "fsc_ens_run", "fsc_ens_get_step", "fsc_ens_get_populations", "fsc_ens_set_populations",
     "fsc_ens_stats", "fsc_ens_density", "fsc_ens_sk_nbins", "fsc_ens_read_sk", "fsc_ens_sk_reset",
-    "fsc_ens_save", "fsc_ens_load", "fsc_ens_series_enable", "fsc_ens_read_series",
+    "fsc_ens_save", "fsc_ens_load", "fsc_modes_enable", "fsc_read_modes", "fsc_ens_modes_enable",
+    "fsc_ens_read_modes", "fsc_ens_series_enable", "fsc_ens_read_series",
     "fsc_autotune", "fsc_ens_autotune", "fsc_get_tiling", "fsc_ens_get_tiling",
     "fsc_copy", "fsc_philox", "fsc_normals", "fsc_linear_sk", "fsc_linear_sk_radial",
+    "fsc_linear_corr",
     "fsc_sur_create", "fsc_sur_destroy", "fsc_sur_last_error", "fsc_sur_nparams",
     "fsc_sur_set_params", "fsc_sur_get_params", "fsc_sur_set_norm", "fsc_sur_forward",
     "fsc_sur_grad", "fsc_sur_train_step", "fsc_coarsen", "fsc_ens_coarsen", "fsc_field_nbins",
@@ -124,6 +126,11 @@ def lib():
         "fsc_ens_sk_reset": ([vp], C.c_int),
         "fsc_ens_density": ([vp, C.c_int, dp], C.c_int),
         "fsc_linear_sk": ([pp, dp, C.c_int64, dp, vp], C.c_int),
+        "fsc_linear_corr": ([pp, dp, C.c_int64, C.POINTER(C.c_int), C.c_int, dp, vp], C.c_int),
+        "fsc_modes_enable": ([vp, C.c_int, C.c_int], C.c_int),
+        "fsc_read_modes": ([vp, dp, C.c_int, C.POINTER(C.c_int)], C.c_int),
+        "fsc_ens_modes_enable": ([vp, C.c_int, C.c_int], C.c_int),
+        "fsc_ens_read_modes": ([vp, C.c_int, dp, C.c_int, C.POINTER(C.c_int)], C.c_int),
         "fsc_linear_sk_radial": ([pp, dp, i64p, C.c_int, vp], C.c_int),
         "fsc_autotune": ([vp], C.c_int),
         "fsc_ens_autotune": ([vp], C.c_int),
@@ -289,6 +296,19 @@ class Lattice:
     def sk_reset(self):
         self._c(lib().fsc_sk_reset(self._h))
 
+    def modes_enable(self, nm: int, capacity: int):
+        """Record the axis-mode amplitudes m = 1..nm at every S(k) sample."""
+        self._c(lib().fsc_modes_enable(self._h, int(nm), int(capacity)))
+        self._modes_nm = int(nm)
+
+    def read_modes(self):
+        """Recorded amplitudes as complex [rows][D][nm]."""
+        n = C.c_int()
+        self._c(lib().fsc_read_modes(self._h, None, 0, C.byref(n)))
+        out = np.zeros((max(n.value, 1), self.D, self._modes_nm, 2))
+        self._c(lib().fsc_read_modes(self._h, _dp(out), n.value, C.byref(n)))
+        return (out[..., 0] + 1j * out[..., 1])[:n.value]
+
     def save(self, path: str):
         """Checkpoint: step, populations as stored, S(k) accumulators."""
         self._c(lib().fsc_save(self._h, os.fsencode(path)))
@@ -414,6 +434,20 @@ class Ensemble:
         out = np.empty(shape)
         self._c(lib().fsc_ens_density(self._h, r, _dp(out)))
         return out
+
+    def modes_enable(self, nm: int, capacity: int):
+        """Record the axis-mode amplitudes m = 1..nm of every replica at every sample."""
+        self._c(lib().fsc_ens_modes_enable(self._h, int(nm), int(capacity)))
+        self._modes_nm = int(nm)
+
+    def read_modes(self, r: int):
+        """Recorded amplitudes of replica r as complex [rows][D][nm]."""
+        n = C.c_int()
+        self._c(lib().fsc_ens_read_modes(self._h, r, None, 0, C.byref(n)))
+        D = self.plist[r].D
+        out = np.zeros((max(n.value, 1), D, self._modes_nm, 2))
+        self._c(lib().fsc_ens_read_modes(self._h, r, _dp(out), n.value, C.byref(n)))
+        return (out[..., 0] + 1j * out[..., 1])[:n.value]
 
     def save(self, path: str):
         """Checkpoint of every replica (see fsc_ens_save)."""
@@ -548,6 +582,16 @@ def linear_sk_radial(p: Params, nbins: int):
     _check(lib().fsc_linear_sk_radial(C.byref(p), _dp(mean), cnt.ctypes.data_as(C.POINTER(C.c_int64)),
                                       nbins, None))
     return mean, cnt
+
+
+def linear_corr(p: Params, kvecs, lags) -> np.ndarray:
+    """Exact C(k, tau) of the linearised step, complex [nk][nlag]."""
+    k = np.ascontiguousarray(kvecs, dtype=np.float64).reshape(-1, p.D)
+    lg = np.ascontiguousarray(lags, dtype=np.int32)
+    out = np.zeros((k.shape[0], len(lg), 2))
+    _check(lib().fsc_linear_corr(C.byref(p), _dp(k), k.shape[0],
+                                 lg.ctypes.data_as(C.POINTER(C.c_int)), len(lg), _dp(out), None))
+    return out[..., 0] + 1j * out[..., 1]
 
 
 def mfma_probe(A: np.ndarray, B: np.ndarray) -> np.ndarray:

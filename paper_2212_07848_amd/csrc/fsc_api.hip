@@ -60,6 +60,10 @@ struct Rep {
     double *d_mom = nullptr, *d_series = nullptr;
     int *d_series_n = nullptr;
     int series_cap = 0;
+    // recorded axis-mode amplitudes per sample -- see fsc_modes_enable
+    double *d_modes = nullptr;
+    int *d_modes_n = nullptr;
+    int modes_nm = 0, modes_cap = 0;
     Geometry geom() const { return Geometry{p.D, p.nx, p.ny, p.nz, N}; }
 };
 
@@ -271,6 +275,58 @@ int enqueue_measure(Rep &r, int par, fsc_ens *e, uint32_t step_off) {
     if (ser)
         HIPCHK(e, launch_series_finalize(r.d_mom, r.d_series, r.d_series_n, r.series_cap,
                                          2 + r.n_rad, e->d_step, step_off, e->stream));
+    if (r.modes_cap > 0)
+        HIPCHK(e, launch_record_modes(g, r.p.precision, a, r.modes_nm, r.d_modes, r.d_modes_n,
+                                      r.modes_cap, e->stream));
+    return FSC_OK;
+}
+
+int modes_enable(fsc_ens *e, Rep &r, int nm, int cap) {
+    (void)hipStreamSynchronize(e->stream);
+    if (r.d_modes) {
+        (void)hipFree(r.d_modes);
+        r.d_modes = nullptr;
+    }
+    r.modes_cap = 0;
+    r.modes_nm = 0;
+    if (!r.d_modes_n) {
+        if (hipMalloc(&r.d_modes_n, sizeof(int)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(e, FSC_E_OOM, "mode recorder allocation failed");
+        }
+    }
+    if (cap > 0) {
+        const int sides[3] = {r.p.nx, r.p.ny, r.p.nz};
+        for (int d = 0; d < r.p.D; ++d)
+            if (nm > sides[d] / 2) return fail(e, FSC_E_INVAL, "nm exceeds half a side");
+        const size_t bytes = sizeof(double) * 2 * size_t(cap) * size_t(r.p.D) * size_t(nm);
+        if (hipMalloc(&r.d_modes, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(e, FSC_E_OOM, "mode recorder allocation failed");
+        }
+        HIPCHK(e, hipMemsetAsync(r.d_modes, 0, bytes, e->stream));
+        r.modes_cap = cap;
+        r.modes_nm = nm;
+    }
+    HIPCHK(e, hipMemsetAsync(r.d_modes_n, 0, sizeof(int), e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    return FSC_OK;
+}
+
+int modes_read(fsc_ens *e, Rep &r, double *out, int max_rows, int *nrows) {
+    int n = 0;
+    if (r.d_modes_n) {
+        HIPCHK(e, hipMemcpyAsync(&n, r.d_modes_n, sizeof(int), hipMemcpyDeviceToHost, e->stream));
+        HIPCHK(e, hipStreamSynchronize(e->stream));
+    }
+    n = std::min(n, r.modes_cap);
+    const int m = std::min(n, max_rows);
+    if (m > 0 && out) {
+        HIPCHK(e, hipMemcpyAsync(out, r.d_modes, sizeof(double) * 2 * size_t(m) * r.p.D * r.modes_nm,
+                                 hipMemcpyDeviceToHost, e->stream));
+        HIPCHK(e, hipStreamSynchronize(e->stream));
+    }
+    if (nrows) *nrows = n;
     return FSC_OK;
 }
 
@@ -647,8 +703,9 @@ void ens_free(fsc_ens *e) {
             if (r.buf[0]) (void)hipFree(r.buf[0]);
             if (r.buf[1]) (void)hipFree(r.buf[1]);
         }
-        void *ptrs[] = {r.d_sk,     r.cbuf,       r.ctmp,  r.tw[0],     r.tw[1],     r.tw[2],
-                        r.d_stats,  r.d_partials, r.d_mom, r.d_series, r.d_series_n};
+        void *ptrs[] = {r.d_sk,     r.cbuf,       r.ctmp,  r.tw[0],     r.tw[1],      r.tw[2],
+                        r.d_stats,  r.d_partials, r.d_mom, r.d_series, r.d_series_n, r.d_modes,
+                        r.d_modes_n};
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
     }
@@ -1100,6 +1157,31 @@ int fsc_ens_read_series(fsc_ens *ens, int replica, double *out, int max_rows, in
     if (!ens) return FSC_E_INVAL;
     int rc = rep_index(ens, replica);
     return rc ? rc : series_read(ens, ens->reps[replica], out, max_rows, nrows, row_len);
+}
+
+// ---- recorded mode amplitudes ---------------------------------------------------
+int fsc_modes_enable(fsc_ctx *ctx, int nm, int capacity) {
+    if (!ctx || capacity < 0 || (capacity > 0 && nm < 1)) return FSC_E_INVAL;
+    drop_graphs(ctx->e);
+    return modes_enable(ctx->e, ctx->e->reps[0], nm, capacity);
+}
+int fsc_read_modes(fsc_ctx *ctx, double *out, int max_rows, int *nrows) {
+    if (!ctx) return FSC_E_INVAL;
+    return modes_read(ctx->e, ctx->e->reps[0], out, max_rows, nrows);
+}
+int fsc_ens_modes_enable(fsc_ens *ens, int nm, int capacity) {
+    if (!ens || capacity < 0 || (capacity > 0 && nm < 1)) return FSC_E_INVAL;
+    drop_graphs(ens);
+    for (auto &r : ens->reps) {
+        int rc = modes_enable(ens, r, nm, capacity);
+        if (rc) return rc;
+    }
+    return FSC_OK;
+}
+int fsc_ens_read_modes(fsc_ens *ens, int replica, double *out, int max_rows, int *nrows) {
+    if (!ens) return FSC_E_INVAL;
+    int rc = rep_index(ens, replica);
+    return rc ? rc : modes_read(ens, ens->reps[replica], out, max_rows, nrows);
 }
 
 // ---- tiling ---------------------------------------------------------------

@@ -87,6 +87,11 @@ hipError_t launch_series_finalize(double *mom, double *series, int *series_n, in
                                   int row_len, const uint64_t *step_base, uint32_t step_off,
                                   hipStream_t s);
 
+// Complex amplitudes of the axis modes m = 1..nm of a transformed density
+// into row *rec_n of rec[cap][D][nm][2] (the row counter advances).
+hipError_t launch_record_modes(const Geometry &g, int precision, const void *spec, int nm, double *rec,
+                               int *rec_n, int cap, hipStream_t s);
+
 // Block means of the density over f x f blocks (2D) into out[(ny/f) x (nx/f)].
 hipError_t launch_coarsen(const Geometry &g, int precision, const void *buf, double rho0, int f,
                           float *out, hipStream_t s);

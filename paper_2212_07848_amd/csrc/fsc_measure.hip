@@ -478,6 +478,41 @@ hipError_t launch_series_finalize(double *mom, double *series, int *series_n, in
 }
 
 // ---------------------------------------------------------------------------
+// Mode recorder: the complex amplitudes of the modes m = 1..nm along each
+// lattice axis of the transformed density (natural [z][y][x] order), as
+// doubles, into row *rec_n of rec[cap][D][nm][2]; the row counter advances.
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ void __launch_bounds__(256) k_record_modes(Geometry g, const cplx<real> *__restrict__ spec,
+                                                      int nm, double *__restrict__ rec,
+                                                      int *__restrict__ rec_n, int cap) {
+    const int row = rec_n[0];
+    const int total = g.D * nm;
+    if (row < cap) {
+        for (int q = threadIdx.x; q < total; q += 256) {
+            const int d = q / nm, m = q % nm + 1;
+            const int64_t stride = d == 0 ? 1 : (d == 1 ? int64_t(g.nx) : int64_t(g.nx) * g.ny);
+            const cplx<real> v = spec[int64_t(m) * stride];
+            rec[(size_t(row) * total + q) * 2] = double(v.re);
+            rec[(size_t(row) * total + q) * 2 + 1] = double(v.im);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) rec_n[0] = row + 1;
+}
+
+hipError_t launch_record_modes(const Geometry &g, int precision, const void *spec, int nm, double *rec,
+                               int *rec_n, int cap, hipStream_t s) {
+    if (precision == 0)
+        hipLaunchKernelGGL(k_record_modes<float>, dim3(1), dim3(256), 0, s, g,
+                           static_cast<const cplx<float> *>(spec), nm, rec, rec_n, cap);
+    else
+        hipLaunchKernelGGL(k_record_modes<double>, dim3(1), dim3(256), 0, s, g,
+                           static_cast<const cplx<double> *>(spec), nm, rec, rec_n, cap);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Plain device copy (16-byte lanes, grid-stride): the practical HBM
 // read+write ceiling and the calibration for the memory-traffic counters.
 // ---------------------------------------------------------------------------
