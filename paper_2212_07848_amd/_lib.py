@@ -419,9 +419,11 @@ class Ensemble:
         assert f.shape == self._shape(r)
         self._c(lib().fsc_ens_set_populations(self._h, r, _dp(f)))
 
-    def stats(self, r: int):
+    def stats(self, r: int, allow_diverged: bool = False):
         out = np.empty(8)
-        self._c(lib().fsc_ens_stats(self._h, r, _dp(out)))
+        rc = lib().fsc_ens_stats(self._h, r, _dp(out))
+        if rc != 0 and not (allow_diverged and rc == -4):
+            self._c(rc)
         return dict(mass=out[0], mom=out[1:4].copy(), rho_min=out[4], rho_max=out[5],
                     bad=int(out[6]), nodes=int(out[7]))
 
