@@ -350,6 +350,18 @@ int fsc_ens_autotune(fsc_ens *ens);
 int fsc_get_tiling(const fsc_ctx *ctx, int *out4);
 int fsc_ens_get_tiling(const fsc_ens *ens, int *out4);
 
+/* The tile shapes compiled for a lattice kind: writes up to `max` triples
+ * (tile x, tile y, prefetch depth) to host out3[3 max] and returns how many
+ * exist (the first is the default), or FSC_E_INVAL for an unsupported kind. */
+int fsc_tile_shapes(int D, int stencil, int precision, int *out3, int max);
+
+/* Fixes the tiling instead of tuning it: one of the compiled shapes, and a
+ * marching length chosen to give about target_blocks (>= 1) workgroups per
+ * step.  Results do not depend on it.  FSC_E_INVAL for a shape that is not
+ * compiled for the lattice. */
+int fsc_set_tiling(fsc_ctx *ctx, int tx, int ty, int pf, int64_t target_blocks);
+int fsc_ens_set_tiling(fsc_ens *ens, int tx, int ty, int pf, int64_t target_blocks);
+
 /* ----------------------------------------------------------------------- */
 /* Diagnostics.                                                             */
 /* ----------------------------------------------------------------------- */

@@ -36,6 +36,7 @@ EXPORTS = [
     "fsc_ens_save", "fsc_ens_load", "fsc_modes_enable", "fsc_read_modes", "fsc_ens_modes_enable",
     "fsc_ens_read_modes", "fsc_ens_series_enable", "fsc_ens_read_series",
     "fsc_autotune", "fsc_ens_autotune", "fsc_get_tiling", "fsc_ens_get_tiling",
+    "fsc_tile_shapes", "fsc_set_tiling", "fsc_ens_set_tiling",
     "fsc_copy", "fsc_philox", "fsc_normals", "fsc_linear_sk", "fsc_linear_sk_radial",
     "fsc_linear_corr",
     "fsc_sur_create", "fsc_sur_destroy", "fsc_sur_last_error", "fsc_sur_nparams",
@@ -136,6 +137,9 @@ def lib():
         "fsc_ens_autotune": ([vp], C.c_int),
         "fsc_get_tiling": ([vp, C.POINTER(C.c_int)], C.c_int),
         "fsc_ens_get_tiling": ([vp, C.POINTER(C.c_int)], C.c_int),
+        "fsc_tile_shapes": ([C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int], C.c_int),
+        "fsc_set_tiling": ([vp, C.c_int, C.c_int, C.c_int, C.c_int64], C.c_int),
+        "fsc_ens_set_tiling": ([vp, C.c_int, C.c_int, C.c_int, C.c_int64], C.c_int),
         "fsc_copy": ([vp, vp, C.c_int64, vp], C.c_int),
         "fsc_philox": ([u32p, u32p, u32p, C.c_int64], C.c_int),
         "fsc_sur_create": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, vp,
@@ -256,6 +260,9 @@ class Lattice:
         out = (C.c_int * 4)()
         self._c(lib().fsc_get_tiling(self._h, out))
         return dict(tx=out[0], ty=out[1], pf=out[2], blocks=out[3])
+
+    def set_tiling(self, tx: int, ty: int, pf: int, target_blocks: int = 2048):
+        self._c(lib().fsc_set_tiling(self._h, int(tx), int(ty), int(pf), int(target_blocks)))
 
     def set_populations(self, f: np.ndarray, step: int = 0):
         f = np.ascontiguousarray(f, dtype=np.float64)
@@ -399,6 +406,9 @@ class Ensemble:
         out = (C.c_int * 4)()
         self._c(lib().fsc_ens_get_tiling(self._h, out))
         return dict(tx=out[0], ty=out[1], pf=out[2], blocks=out[3])
+
+    def set_tiling(self, tx: int, ty: int, pf: int, target_blocks: int = 2048):
+        self._c(lib().fsc_ens_set_tiling(self._h, int(tx), int(ty), int(pf), int(target_blocks)))
 
     def run(self, n: int, sk_every: int = 0):
         self._c(lib().fsc_ens_run(self._h, int(n), int(sk_every)))
@@ -566,6 +576,17 @@ def field_sk(fields, batch: int, n: int, stream=None):
     _check(lib().fsc_field_sk(ptr, batch, n, n, _stream_handle(_torch_stream_or(stream)),
                               _dp(shells), _dp(L), nb.value))
     return shells, L
+
+
+def tile_shapes(D: int, stencil: int, precision: str = "fp32"):
+    """Compiled (tile x, tile y, prefetch depth) shapes of a lattice kind; the first is the default."""
+    prec = {"fp32": FSC_FP32_SHIFTED, "fp64": FSC_FP64}[precision] if isinstance(precision, str) \
+        else int(precision)
+    out = (C.c_int * 48)()
+    n = lib().fsc_tile_shapes(int(D), int(stencil), prec, out, 16)
+    if n < 0:
+        raise FscError(n, "unsupported lattice kind")
+    return [(out[3 * i], out[3 * i + 1], out[3 * i + 2]) for i in range(min(n, 16))]
 
 
 def linear_sk(p: Params, kvecs) -> np.ndarray:

@@ -387,7 +387,7 @@ void build_desc(fsc_ens *e) {
     }
     // marching length: enough blocks to fill 256 CUs several times over,
     // but long marches so that the 2R halo planes stay a small overhead
-    int H = int(std::min<int64_t>(256, std::max<int64_t>(8, work / e->target_blocks)));
+    int H = int(std::min<int64_t>(256, std::max<int64_t>(1, work / e->target_blocks)));
     int tile_begin = 0;
     for (auto &r : e->reps) {
         RepDesc d{};
@@ -539,7 +539,7 @@ int ens_autotune(fsc_ens *e) {
     const int nshape = tile_shapes(e->D, e->stencil, e->precision, shapes, 8);
     // block counts around one and a few rounds of the ~1.5-2k blocks that
     // are resident at once (256 CUs x 6-8 blocks of 256 threads)
-    const int64_t targets[] = {768, 1024, 1536, 2048, 3072, 4096, 6144};
+    const int64_t targets[] = {768, 1024, 1536, 2048, 3072, 4096, 6144, 8192, 12288, 16384, 24576, 32768, 65536};
     hipEvent_t a, b;
     HIPCHK(e, hipEventCreate(&a));
     HIPCHK(e, hipEventCreate(&b));
@@ -1197,6 +1197,41 @@ static int get_tiling(const fsc_ens *e, int *out4) {
 }
 int fsc_get_tiling(const fsc_ctx *ctx, int *out4) { return ctx ? get_tiling(ctx->e, out4) : FSC_E_INVAL; }
 int fsc_ens_get_tiling(const fsc_ens *ens, int *out4) { return ens ? get_tiling(ens, out4) : FSC_E_INVAL; }
+
+int fsc_tile_shapes(int D, int stencil, int precision, int *out3, int max) {
+    if (!((D == 2 && (stencil == FSC_E4 || stencil == FSC_E8)) || (D == 3 && stencil == FSC_E4)) ||
+        (precision != FSC_FP32_SHIFTED && precision != FSC_FP64) || max < 0 || (max > 0 && !out3))
+        return FSC_E_INVAL;
+    TileShape t[16];
+    const int n = tile_shapes(D, stencil, precision, t, 16);
+    for (int i = 0; i < n && i < max; ++i) {
+        out3[3 * i] = t[i].tx;
+        out3[3 * i + 1] = t[i].ty;
+        out3[3 * i + 2] = t[i].pf;
+    }
+    return n;
+}
+
+static int set_tiling(fsc_ens *e, int tx, int ty, int pf, int64_t target_blocks) {
+    if (target_blocks < 1) return fail(e, FSC_E_INVAL, "target_blocks < 1");
+    TileShape t[16];
+    const int n = tile_shapes(e->D, e->stencil, e->precision, t, 16);
+    for (int i = 0; i < n; ++i)
+        if (t[i].tx == tx && t[i].ty == ty && t[i].pf == pf) {
+            e->tile = t[i];
+            e->target_blocks = target_blocks;
+            drop_graphs(e);
+            e->autotune = 1;  // an explicit choice is never re-tuned
+            return upload_desc(e);
+        }
+    return fail(e, FSC_E_INVAL, "tile shape not compiled for this lattice (see fsc_tile_shapes)");
+}
+int fsc_set_tiling(fsc_ctx *ctx, int tx, int ty, int pf, int64_t target_blocks) {
+    return ctx ? set_tiling(ctx->e, tx, ty, pf, target_blocks) : FSC_E_INVAL;
+}
+int fsc_ens_set_tiling(fsc_ens *ens, int tx, int ty, int pf, int64_t target_blocks) {
+    return ens ? set_tiling(ens, tx, ty, pf, target_blocks) : FSC_E_INVAL;
+}
 
 // ---- coarse-graining and field measurement (surrogate inputs/outputs) ---
 int fsc_coarsen(fsc_ctx *ctx, int factor, float *dev_out) {

@@ -520,30 +520,22 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_copy(const u32x4 *__restrict__ src,
                                               u32x4 *__restrict__ dst, int64_t n16) {
-    // each block moves 4 consecutive 4 KiB pieces per iteration: four
-    // independent 16-byte loads per lane are in flight before the stores;
-    // non-temporal loads and stores (the fastest plain copy measured on gfx950)
-    const int64_t stride = int64_t(gridDim.x) * 1024;
-    for (int64_t base = int64_t(blockIdx.x) * 1024; base < n16; base += stride) {
-        u32x4 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t k = base + u * 256 + threadIdx.x;
-            if (k < n16) v[u] = __builtin_nontemporal_load(src + k);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t k = base + u * 256 + threadIdx.x;
-            if (k < n16) __builtin_nontemporal_store(v[u], dst + k);
-        }
-    }
+    // One 16-byte element per lane and a grid that covers the buffer once
+    // (the loop runs only for buffers beyond 2^38 bytes).  Blocks are
+    // dispatched in address order, so the lanes in flight at any moment touch
+    // one compact address range; a grid-stride copy with fewer, longer-lived
+    // blocks spreads them over the whole buffer and measured 10% slower.
+    // Non-temporal loads and stores.
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n16; k += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
 }
 
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t s) {
     if (bytes <= 0 || (bytes & 15)) return hipErrorInvalidValue;
     const int64_t n16 = bytes / 16;
-    const int64_t want = (n16 + 1023) / 1024;
-    const unsigned blocks = unsigned(want < 16384 ? want : 16384);
+    const int64_t want = (n16 + 255) / 256;
+    const unsigned blocks = unsigned(want < (int64_t(1) << 30) ? want : (int64_t(1) << 30));
     hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, static_cast<const u32x4 *>(src),
                        static_cast<u32x4 *>(dst), n16);
     return hipGetLastError();
