@@ -89,6 +89,11 @@ struct fsc_ens {
     uint64_t *d_step = nullptr;
     int64_t step = 0;
     int total_tiles = 0;
+    // batched S(k) sample of all replicas: host copy of the device table and its plan
+    std::vector<MeasRep> meas;
+    MeasPlan mplan;
+    MeasRep *d_meas = nullptr;
+    int *d_mpre = nullptr;
     std::string err;
     std::map<std::pair<int, std::pair<int64_t, int64_t>>, GraphEntry> graphs;
 };
@@ -238,46 +243,75 @@ int ensure_fft(Rep &r, fsc_ens *e) {
     return FSC_OK;
 }
 
-// enqueues one S(k) sample of replica r from buffer `par`; the sampled state
-// is `step_off` steps past the device step counter
-int enqueue_measure(Rep &r, int par, fsc_ens *e, uint32_t step_off) {
-    const Geometry g = r.geom();
-    HIPCHK(e, launch_density_complex(g, r.p.precision, r.buf[par], r.cbuf, e->stream));
-    void *a = r.cbuf, *b = r.ctmp;
-    int dims[3] = {r.p.nx, r.p.ny, r.p.nz};
-    // pass d transforms the contiguous axis then rotates (n0,n1,n2) -> (n1,n2,n0)
-    int n0 = dims[0], n1 = dims[1], n2 = dims[2];
-    for (int d = 0; d < r.p.D; ++d) {
-        // lattice axis d is contiguous in pass d; a unit middle axis makes the
-        // rotation a plain transpose of (n2 x n0)
-        if (n1 == 1) HIPCHK(e, launch_fft_axis(r.p.precision, a, b, r.tw[d], n0, n2, 1, e->stream));
-        else HIPCHK(e, launch_fft_axis(r.p.precision, a, b, r.tw[d], n0, n1, n2, e->stream));
-        const int t0 = n0;
-        n0 = n1;
-        n1 = n2;
-        n2 = t0;
-        std::swap(a, b);
+// The device table of the batched S(k) sample is rebuilt from the replicas'
+// current buffers before any sample is enqueued (outside graph capture).  When
+// it changes (first use, series or mode recorder switched on or resized) the
+// stream is drained, the table uploaded and the captured graphs dropped, since
+// their launch sizes come from it.  Needs ensure_fft on every replica.
+void drop_graphs(fsc_ens *e);
+
+int ensure_measure_plan(fsc_ens *e) {
+    const int n = int(e->reps.size());
+    std::vector<MeasRep> m(static_cast<size_t>(n));
+    for (int k = 0; k < n; ++k) {
+        const Rep &r = e->reps[k];
+        MeasRep &x = m[size_t(k)];
+        std::memset(&x, 0, sizeof(MeasRep));
+        if (!r.cbuf) return fail(e, FSC_E_STATE, "S(k) buffers missing");
+        x.buf[0] = r.buf[0];
+        x.buf[1] = r.buf[1];
+        x.cbuf = r.cbuf;
+        x.ctmp = r.ctmp;
+        for (int d = 0; d < 3; ++d) x.tw[d] = r.tw[d];
+        x.g = r.geom();
+        const size_t na = size_t(r.p.D) * r.n_axis;
+        x.t.axis_sum = r.d_sk;
+        x.t.axis_sq = r.d_sk + na;
+        x.t.rad_sum = r.n_rad ? r.d_sk + 2 * na : nullptr;
+        x.t.rad_sq = r.n_rad ? r.d_sk + 2 * na + r.n_rad : nullptr;
+        x.t.n_axis = r.n_axis;
+        x.t.n_rad = r.n_rad;
+        const bool ser = r.series_cap > 0;
+        x.t.mom = ser ? r.d_mom : nullptr;
+        x.t.series = ser ? r.d_series : nullptr;
+        x.t.series_n = r.d_series_n;
+        x.t.series_cap = r.series_cap;
+        x.series_n = r.d_series_n;
+        x.invN = 1.0 / double(r.N);
+        if (r.modes_cap > 0) {
+            x.modes = r.d_modes;
+            x.modes_n = r.d_modes_n;
+            x.modes_nm = r.modes_nm;
+            x.modes_cap = r.modes_cap;
+        }
     }
-    BinTargets t;
-    const size_t na = size_t(r.p.D) * r.n_axis;
-    t.axis_sum = r.d_sk;
-    t.axis_sq = r.d_sk + na;
-    t.rad_sum = r.n_rad ? r.d_sk + 2 * na : nullptr;
-    t.rad_sq = r.n_rad ? r.d_sk + 2 * na + r.n_rad : nullptr;
-    t.n_axis = r.n_axis;
-    t.n_rad = r.n_rad;
-    const bool ser = r.series_cap > 0;
-    t.mom = ser ? r.d_mom : nullptr;
-    t.series = ser ? r.d_series : nullptr;
-    t.series_n = r.d_series_n;
-    t.series_cap = r.series_cap;
-    HIPCHK(e, launch_bin(g, r.p.precision, a, t, e->stream));
-    if (ser)
-        HIPCHK(e, launch_series_finalize(r.d_mom, r.d_series, r.d_series_n, r.series_cap,
-                                         2 + r.n_rad, e->d_step, step_off, e->stream));
-    if (r.modes_cap > 0)
-        HIPCHK(e, launch_record_modes(g, r.p.precision, a, r.modes_nm, r.d_modes, r.d_modes_n,
-                                      r.modes_cap, e->stream));
+    if (e->d_meas && m.size() == e->meas.size() &&
+        std::memcmp(m.data(), e->meas.data(), sizeof(MeasRep) * m.size()) == 0)
+        return FSC_OK;
+    MeasPlan P;
+    P.esz = e->reps[0].esz;
+    if (measure_plan(m.data(), n, P)) return fail(e, FSC_E_NOTSUP, "S(k) sample sizes out of range");
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    if (!e->d_meas) {
+        if (hipMalloc(&e->d_meas, sizeof(MeasRep) * size_t(n)) != hipSuccess ||
+            hipMalloc(&e->d_mpre, sizeof(int) * P.pre.size()) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(e, FSC_E_OOM, "S(k) table allocation failed");
+        }
+    }
+    drop_graphs(e);
+    HIPCHK(e, hipMemcpy(e->d_meas, m.data(), sizeof(MeasRep) * size_t(n), hipMemcpyHostToDevice));
+    HIPCHK(e, hipMemcpy(e->d_mpre, P.pre.data(), sizeof(int) * P.pre.size(), hipMemcpyHostToDevice));
+    e->meas = std::move(m);
+    e->mplan = std::move(P);
+    return FSC_OK;
+}
+
+// enqueues one S(k) sample of every replica from buffer `par`; the sampled
+// state is `step_off` steps past the device step counter
+int enqueue_measure(fsc_ens *e, int par, uint32_t step_off) {
+    HIPCHK(e, launch_measure(e->mplan, e->d_meas, e->d_mpre, e->precision, par, e->d_step, step_off,
+                             e->stream));
     return FSC_OK;
 }
 
@@ -489,10 +523,8 @@ int enqueue_steps(fsc_ens *e, int parity, int64_t n, int64_t sk_every, int64_t *
         HIPCHK(e, launch_step(L, e->stream));
         if (sk_every > 0 && (k + 1) % sk_every == 0) {
             const int par = (parity + int((k + 1) & 1)) & 1;
-            for (auto &r : e->reps) {
-                int rc = enqueue_measure(r, par, e, uint32_t(k + 1));
-                if (rc) return rc;
-            }
+            int rc = enqueue_measure(e, par, uint32_t(k + 1));
+            if (rc) return rc;
             if (samples) ++*samples;
         }
     }
@@ -582,11 +614,14 @@ int ens_run(fsc_ens *e, int64_t nsteps, int64_t sk_every) {
     if (nsteps < 0) return fail(e, FSC_E_INVAL, "nsteps < 0");
     if (nsteps == 0) return FSC_OK;
     if (e->step + nsteps > (int64_t(1) << 32)) return fail(e, FSC_E_INVAL, "step counter would pass 2^32");
-    if (sk_every > 0)
+    if (sk_every > 0) {
         for (auto &r : e->reps) {
             int rc = ensure_fft(r, e);
             if (rc) return rc;
         }
+        int rc = ensure_measure_plan(e);
+        if (rc) return rc;
+    }
     if (e->autotune < 0) {
         int64_t nodes = 0;
         for (const auto &r : e->reps) nodes += r.N;
@@ -712,6 +747,8 @@ void ens_free(fsc_ens *e) {
     if (e->d_desc) (void)hipFree(e->d_desc);
     if (e->d_tile_begin) (void)hipFree(e->d_tile_begin);
     if (e->d_step) (void)hipFree(e->d_step);
+    if (e->d_meas) (void)hipFree(e->d_meas);
+    if (e->d_mpre) (void)hipFree(e->d_mpre);
     if (e->own_stream) (void)hipStreamDestroy(e->stream);
     delete e;
 }
@@ -1052,7 +1089,9 @@ int fsc_measure_sk(fsc_ctx *ctx) {
     Rep &r = e->reps[0];
     int rc = ensure_fft(r, e);
     if (rc) return rc;
-    rc = enqueue_measure(r, int(e->step & 1), e, 0);
+    rc = ensure_measure_plan(e);
+    if (rc) return rc;
+    rc = enqueue_measure(e, int(e->step & 1), 0);
     if (rc) return rc;
     r.nsamples += 1;
     return FSC_OK;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "fsc_device.h"
 
 namespace fsc {
@@ -44,10 +46,6 @@ struct Geometry {
     int64_t N;
 };
 
-// dn(x) = sum_i f_i(x) - rho0 of the streamed state, gathered from the stored
-// post-collision buffer; written as complex (re = dn, im = 0).
-hipError_t launch_density_complex(const Geometry &g, int precision, const void *buf, void *cplx,
-                                  hipStream_t s);
 // Real density deviation dn(x) (float or double by precision).
 hipError_t launch_density_real(const Geometry &g, int precision, const void *buf, void *out,
                                hipStream_t s);
@@ -81,16 +79,38 @@ struct BinTargets {
 };
 hipError_t launch_bin(const Geometry &g, int precision, const void *spec, const BinTargets &t,
                       hipStream_t s);
-// Closes one sample of the time series: row *series_n gets (step, L) with
-// L = 2 pi sum P / sum |k| P, the moments are cleared and the row advances.
-hipError_t launch_series_finalize(double *mom, double *series, int *series_n, int cap,
-                                  int row_len, const uint64_t *step_base, uint32_t step_off,
-                                  hipStream_t s);
-
-// Complex amplitudes of the axis modes m = 1..nm of a transformed density
-// into row *rec_n of rec[cap][D][nm][2] (the row counter advances).
-hipError_t launch_record_modes(const Geometry &g, int precision, const void *spec, int nm, double *rec,
-                               int *rec_n, int cap, hipStream_t s);
+// One replica's part of a batched S(k) sample: a device table filled by the
+// host.  The sampled density is dn(x) = sum_i f_i(x) - rho0 of the streamed
+// state, gathered from the stored post-collision buffer buf[parity].
+struct MeasRep {
+    const void *buf[2];   // population buffers
+    void *cbuf, *ctmp;    // complex work buffers of N elements each
+    const void *tw[3];    // twiddles per axis (see launch_twiddles)
+    Geometry g;
+    BinTargets t;         // accumulators; t.mom == nullptr: no time series
+    double invN;
+    int *series_n;        // the time series' row counter (t.series_n, writable)
+    double *modes;        // mode recorder rows [cap][D][nm][2], or null
+    int *modes_n;
+    int modes_nm, modes_cap;
+};
+// kinds of work in one sample; MK_FFT + d and MK_ROT + d for axis pass d
+constexpr int MK_DENSITY = 0, MK_FFT = 1, MK_ROT = 4, MK_BIN = 7, MK_MODES = 8, MK_COUNT = 9;
+struct MeasPlan {
+    int nrep = 0, D = 2;
+    size_t esz = 4;          // bytes of one real (set by the caller)
+    std::vector<int> pre;    // [MK_COUNT][nrep + 1]: first block of each replica per kind
+    size_t shm_fft[3] = {0, 0, 0}, shm_bin = 0;
+    bool any_series = false;
+};
+// Fills the block prefixes and LDS sizes of P from the host copy of the
+// replica table; -1 if a side exceeds 8192 or a grid exceeds 2^31 blocks.
+int measure_plan(const MeasRep *reps, int nrep, MeasPlan &P);
+// One S(k) sample of every replica in P (density, FFT passes, binning, mode
+// records, series rows), in at most 4 + 2 D launches.  The sampled state is
+// step_base[0] + step_off.
+hipError_t launch_measure(const MeasPlan &P, const MeasRep *dev_reps, const int *dev_pre, int precision,
+                          int parity, const uint64_t *step_base, uint32_t step_off, hipStream_t s);
 
 // Block means of the density over f x f blocks (2D) into out[(ny/f) x (nx/f)].
 hipError_t launch_coarsen(const Geometry &g, int precision, const void *buf, double rho0, int f,

@@ -36,11 +36,11 @@ __device__ inline void gather_node(const real *src, const Geometry &g, int x, in
 }
 
 template <class L, typename real, bool CPLX>
-__global__ void __launch_bounds__(256) k_density(Geometry g, const real *__restrict__ src,
-                                                 real *__restrict__ out) {
+__device__ inline void density_block(const Geometry &g, const real *__restrict__ src,
+                                     real *__restrict__ out, int blk) {
     const int strips = (g.nx + 255) / 256;
-    const int row = blockIdx.x / strips;
-    const int x = (blockIdx.x % strips) * 256 + threadIdx.x;
+    const int row = blk / strips;
+    const int x = (blk % strips) * 256 + threadIdx.x;
     if (x >= g.nx) return;
     const int y = row % g.ny, z = row / g.ny;
     real f[L::Q];
@@ -55,6 +55,12 @@ __global__ void __launch_bounds__(256) k_density(Geometry g, const real *__restr
     } else {
         out[s] = dn;
     }
+}
+
+template <class L, typename real, bool CPLX>
+__global__ void __launch_bounds__(256) k_density(Geometry g, const real *__restrict__ src,
+                                                 real *__restrict__ out) {
+    density_block<L, real, CPLX>(g, src, out, int(blockIdx.x));
 }
 
 template <class L, typename real>
@@ -81,10 +87,6 @@ static hipError_t density_dispatch(const Geometry &g, int precision, const void 
                           : density_impl<D3Q19, double>(g, buf, out, cplx, s);
 }
 
-hipError_t launch_density_complex(const Geometry &g, int precision, const void *buf, void *cplx,
-                                  hipStream_t s) {
-    return density_dispatch(g, precision, buf, cplx, true, s);
-}
 hipError_t launch_density_real(const Geometry &g, int precision, const void *buf, void *out,
                                hipStream_t s) {
     return density_dispatch(g, precision, buf, out, false, s);
@@ -241,15 +243,11 @@ hipError_t launch_twiddles(int precision, void *tw, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Iterative radix-2 Cooley-Tukey on one line staged in LDS: bit-reversed
+// Iterative radix-2 Cooley-Tukey on one line staged in LDS (a[n]): bit-reversed
 // load, then log2(n) butterfly stages with twiddles W_len^k = tw[k * n/len].
 template <typename real>
-__global__ void __launch_bounds__(256) k_fft_pow2(cplx<real> *__restrict__ data,
-                                                  const cplx<real> *__restrict__ tw, int n,
-                                                  int logn) {
-    extern __shared__ unsigned char smem_raw[];
-    cplx<real> *a = reinterpret_cast<cplx<real> *>(smem_raw);
-    cplx<real> *line = data + int64_t(blockIdx.x) * n;
+__device__ inline void fft_line_pow2(cplx<real> *__restrict__ line, const cplx<real> *__restrict__ tw,
+                                     int n, int logn, cplx<real> *a) {
     for (int i = threadIdx.x; i < n; i += 256) {
         const int r = logn == 0 ? 0 : int(__brev(unsigned(i)) >> (32 - logn));
         a[r] = line[i];
@@ -274,11 +272,8 @@ __global__ void __launch_bounds__(256) k_fft_pow2(cplx<real> *__restrict__ data,
 
 // Direct DFT of one line (any n): X_k = sum_j x_j tw[(j k) mod n].
 template <typename real>
-__global__ void __launch_bounds__(256) k_dft(cplx<real> *__restrict__ data,
-                                             const cplx<real> *__restrict__ tw, int n) {
-    extern __shared__ unsigned char smem_raw[];
-    cplx<real> *a = reinterpret_cast<cplx<real> *>(smem_raw);
-    cplx<real> *line = data + int64_t(blockIdx.x) * n;
+__device__ inline void dft_line(cplx<real> *__restrict__ line, const cplx<real> *__restrict__ tw, int n,
+                                cplx<real> *a) {
     for (int i = threadIdx.x; i < n; i += 256) a[i] = line[i];
     __syncthreads();
     for (int k = threadIdx.x; k < n; k += 256) {
@@ -295,14 +290,29 @@ __global__ void __launch_bounds__(256) k_dft(cplx<real> *__restrict__ data,
     }
 }
 
-// out[(i0 * n2 + i2) * n1 + i1] = in[(i2 * n1 + i1) * n0 + i0], via 32x32 LDS tiles
 template <typename real>
-__global__ void __launch_bounds__(256) k_rotate(const cplx<real> *__restrict__ in,
-                                                cplx<real> *__restrict__ out, int n0, int n1,
-                                                int n2) {
-    __shared__ cplx<real> tile[32][33];
-    const int i2 = blockIdx.z;
-    const int b0 = blockIdx.x * 32, b1 = blockIdx.y * 32;
+__global__ void __launch_bounds__(256) k_fft_pow2(cplx<real> *__restrict__ data,
+                                                  const cplx<real> *__restrict__ tw, int n,
+                                                  int logn) {
+    extern __shared__ unsigned char smem_raw[];
+    fft_line_pow2<real>(data + int64_t(blockIdx.x) * n, tw, n, logn,
+                        reinterpret_cast<cplx<real> *>(smem_raw));
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_dft(cplx<real> *__restrict__ data,
+                                             const cplx<real> *__restrict__ tw, int n) {
+    extern __shared__ unsigned char smem_raw[];
+    dft_line<real>(data + int64_t(blockIdx.x) * n, tw, n, reinterpret_cast<cplx<real> *>(smem_raw));
+}
+
+// out[(i0 * n2 + i2) * n1 + i1] = in[(i2 * n1 + i1) * n0 + i0], via 32x32 LDS tiles;
+// block (b0, b1, i2) of the (ceil(n0/32), ceil(n1/32), n2) grid
+template <typename real>
+__device__ inline void rotate_block(const cplx<real> *__restrict__ in, cplx<real> *__restrict__ out,
+                                    int n0, int n1, int n2, int bx, int by, int i2,
+                                    cplx<real> (&tile)[32][33]) {
+    const int b0 = bx * 32, b1 = by * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int i1 = b1 + r, i0 = b0 + tx;
@@ -313,6 +323,14 @@ __global__ void __launch_bounds__(256) k_rotate(const cplx<real> *__restrict__ i
         const int i0 = b0 + r, i1 = b1 + tx;
         if (i0 < n0 && i1 < n1) out[(int64_t(i0) * n2 + i2) * n1 + i1] = tile[tx][r];
     }
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_rotate(const cplx<real> *__restrict__ in,
+                                                cplx<real> *__restrict__ out, int n0, int n1,
+                                                int n2) {
+    __shared__ cplx<real> tile[32][33];
+    rotate_block<real>(in, out, n0, n1, n2, int(blockIdx.x), int(blockIdx.y), int(blockIdx.z), tile);
 }
 
 hipError_t launch_fft_axis(int precision, void *data, void *tmp, const void *twiddle, int n0,
@@ -369,11 +387,9 @@ __device__ inline int isqrt_round(int64_t m) {
 __device__ inline int signed_mode(int q, int n) { return q <= n / 2 ? q : q - n; }
 
 template <typename real>
-__global__ void __launch_bounds__(256) k_bin(Geometry g, const cplx<real> *__restrict__ spec,
-                                             BinTargets t, double invN) {
-    extern __shared__ double wnd[];  // [2][W]
-    __shared__ double red[2][4];
-    const int row = blockIdx.x;
+__device__ inline void bin_row(const Geometry &g, const cplx<real> *__restrict__ spec,
+                               const BinTargets &t, double invN, int row, double *wnd,
+                               double (&red)[2][4]) {
     const int y = row % g.ny, z = row / g.ny;
     const int my = signed_mode(y, g.ny), mz = signed_mode(z, g.nz);
     const int64_t base2 = int64_t(my) * my + int64_t(mz) * mz;
@@ -441,6 +457,14 @@ __global__ void __launch_bounds__(256) k_bin(Geometry g, const cplx<real> *__res
     }
 }
 
+template <typename real>
+__global__ void __launch_bounds__(256) k_bin(Geometry g, const cplx<real> *__restrict__ spec,
+                                             BinTargets t, double invN) {
+    extern __shared__ double wnd[];  // [2][W]
+    __shared__ double red[2][4];
+    bin_row<real>(g, spec, t, invN, int(blockIdx.x), wnd, red);
+}
+
 hipError_t launch_bin(const Geometry &g, int precision, const void *spec, const BinTargets &t,
                       hipStream_t s) {
     const int64_t rows = int64_t(g.ny) * g.nz;
@@ -456,12 +480,13 @@ hipError_t launch_bin(const Geometry &g, int precision, const void *spec, const 
     return hipGetLastError();
 }
 
-__global__ void k_series_finalize(double *mom, double *series, int *series_n, int cap,
-                                  int row_len, const uint64_t *step_base, uint32_t step_off) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Closes one sample of a replica's time series: row *series_n gets (step, L)
+// with L = 2 pi sum P / sum |k| P, the moments are cleared and the row advances.
+__device__ inline void series_finalize(double *mom, double *series, int *series_n, int cap,
+                                       int row_len, uint64_t step) {
     const int row = series_n[0];
     if (series != nullptr && row < cap) {
-        series[size_t(row) * row_len] = double(step_base[0] + step_off);
+        series[size_t(row) * row_len] = double(step);
         series[size_t(row) * row_len + 1] = mom[1] > 0.0 ? 2.0 * M_PI * mom[0] / mom[1] : 0.0;
     }
     mom[0] = 0.0;
@@ -469,23 +494,13 @@ __global__ void k_series_finalize(double *mom, double *series, int *series_n, in
     series_n[0] = row + 1;
 }
 
-hipError_t launch_series_finalize(double *mom, double *series, int *series_n, int cap,
-                                  int row_len, const uint64_t *step_base, uint32_t step_off,
-                                  hipStream_t s) {
-    hipLaunchKernelGGL(k_series_finalize, dim3(1), dim3(64), 0, s, mom, series, series_n, cap,
-                       row_len, step_base, step_off);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // Mode recorder: the complex amplitudes of the modes m = 1..nm along each
 // lattice axis of the transformed density (natural [z][y][x] order), as
 // doubles, into row *rec_n of rec[cap][D][nm][2]; the row counter advances.
-// ---------------------------------------------------------------------------
 template <typename real>
-__global__ void __launch_bounds__(256) k_record_modes(Geometry g, const cplx<real> *__restrict__ spec,
-                                                      int nm, double *__restrict__ rec,
-                                                      int *__restrict__ rec_n, int cap) {
+__device__ inline void record_modes_block(const Geometry &g, const cplx<real> *__restrict__ spec,
+                                          int nm, double *__restrict__ rec, int *__restrict__ rec_n,
+                                          int cap) {
     const int row = rec_n[0];
     const int total = g.D * nm;
     if (row < cap) {
@@ -501,15 +516,197 @@ __global__ void __launch_bounds__(256) k_record_modes(Geometry g, const cplx<rea
     if (threadIdx.x == 0) rec_n[0] = row + 1;
 }
 
-hipError_t launch_record_modes(const Geometry &g, int precision, const void *spec, int nm, double *rec,
-                               int *rec_n, int cap, hipStream_t s) {
-    if (precision == 0)
-        hipLaunchKernelGGL(k_record_modes<float>, dim3(1), dim3(256), 0, s, g,
-                           static_cast<const cplx<float> *>(spec), nm, rec, rec_n, cap);
-    else
-        hipLaunchKernelGGL(k_record_modes<double>, dim3(1), dim3(256), 0, s, g,
-                           static_cast<const cplx<double> *>(spec), nm, rec, rec_n, cap);
+// ---------------------------------------------------------------------------
+// One S(k) sample of every replica of an ensemble in a fixed number of
+// launches (density, then per axis an FFT pass and a rotation, binning, mode
+// records, series rows), whatever the number of replicas.  Each launch is a
+// flat grid over the replicas: block b belongs to the replica r with
+// pre[r] <= b < pre[r + 1] (a prefix table per kind of work).
+// ---------------------------------------------------------------------------
+__device__ inline int rep_of(const int *__restrict__ pre, int nrep, int b) {
+    // largest r with pre[r] <= b; replicas without blocks of this kind have
+    // pre[r] == pre[r + 1] and are never returned
+    int lo = 0, hi = nrep - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Arguments of the FFT pass d (transform of the contiguous axis, then the
+// rotation (n0, n1, n2) -> (n1, n2, n0)); a unit middle axis makes the
+// rotation a plain transpose of (n2 x n0).
+struct PassDims {
+    int n0, n1, n2;
+};
+__host__ __device__ inline PassDims pass_dims(const Geometry &g, int d) {
+    int n0 = g.nx, n1 = g.ny, n2 = g.nz;
+    for (int k = 0; k < d; ++k) {
+        const int t = n0;
+        n0 = n1;
+        n1 = n2;
+        n2 = t;
+    }
+    return n1 == 1 ? PassDims{n0, n2, 1} : PassDims{n0, n1, n2};
+}
+
+template <class L, typename real>
+__global__ void __launch_bounds__(256) k_density_batch(const MeasRep *__restrict__ mr,
+                                                       const int *__restrict__ pre, int nrep, int par) {
+    const int r = rep_of(pre, nrep, int(blockIdx.x));
+    const MeasRep &m = mr[r];
+    density_block<L, real, true>(m.g, static_cast<const real *>(m.buf[par]), static_cast<real *>(m.cbuf),
+                                 int(blockIdx.x) - pre[r]);
+}
+
+// pass d works in place on cbuf (d even) or ctmp (d odd) and rotates into the other
+template <typename real>
+__global__ void __launch_bounds__(256) k_fft_batch(const MeasRep *__restrict__ mr,
+                                                   const int *__restrict__ pre, int nrep, int d) {
+    extern __shared__ unsigned char smem_raw[];
+    const int r = rep_of(pre, nrep, int(blockIdx.x));
+    const MeasRep &m = mr[r];
+    const PassDims p = pass_dims(m.g, d);
+    if (p.n0 <= 1) return;
+    cplx<real> *line = static_cast<cplx<real> *>((d & 1) ? m.ctmp : m.cbuf) +
+                       int64_t(int(blockIdx.x) - pre[r]) * p.n0;
+    const cplx<real> *tw = static_cast<const cplx<real> *>(m.tw[d]);
+    cplx<real> *a = reinterpret_cast<cplx<real> *>(smem_raw);
+    if ((p.n0 & (p.n0 - 1)) == 0) {
+        int logn = 0;
+        while ((1 << logn) < p.n0) ++logn;
+        fft_line_pow2<real>(line, tw, p.n0, logn, a);
+    } else {
+        dft_line<real>(line, tw, p.n0, a);
+    }
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_rotate_batch(const MeasRep *__restrict__ mr,
+                                                      const int *__restrict__ pre, int nrep, int d) {
+    __shared__ cplx<real> tile[32][33];
+    const int r = rep_of(pre, nrep, int(blockIdx.x));
+    const MeasRep &m = mr[r];
+    const PassDims p = pass_dims(m.g, d);
+    const int gx = (p.n0 + 31) / 32, gy = (p.n1 + 31) / 32;
+    const int lb = int(blockIdx.x) - pre[r];
+    const int bz = lb / (gx * gy), rem = lb % (gx * gy);
+    const void *in = (d & 1) ? m.ctmp : m.cbuf;
+    void *out = (d & 1) ? m.cbuf : m.ctmp;
+    rotate_block<real>(static_cast<const cplx<real> *>(in), static_cast<cplx<real> *>(out), p.n0, p.n1,
+                       p.n2, rem % gx, rem / gx, bz, tile);
+}
+
+// the transformed spectrum lies in cbuf after an even number of passes, else in ctmp
+template <typename real>
+__global__ void __launch_bounds__(256) k_bin_batch(const MeasRep *__restrict__ mr,
+                                                   const int *__restrict__ pre, int nrep) {
+    extern __shared__ double wnd[];
+    __shared__ double red[2][4];
+    const int r = rep_of(pre, nrep, int(blockIdx.x));
+    const MeasRep &m = mr[r];
+    const void *spec = (m.g.D & 1) ? m.ctmp : m.cbuf;
+    bin_row<real>(m.g, static_cast<const cplx<real> *>(spec), m.t, m.invN, int(blockIdx.x) - pre[r], wnd,
+                  red);
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_modes_batch(const MeasRep *__restrict__ mr,
+                                                     const int *__restrict__ pre, int nrep) {
+    const int r = rep_of(pre, nrep, int(blockIdx.x));
+    const MeasRep &m = mr[r];
+    const void *spec = (m.g.D & 1) ? m.ctmp : m.cbuf;
+    record_modes_block<real>(m.g, static_cast<const cplx<real> *>(spec), m.modes_nm, m.modes, m.modes_n,
+                             m.modes_cap);
+}
+
+__global__ void __launch_bounds__(64) k_series_batch(const MeasRep *__restrict__ mr, int nrep,
+                                                     const uint64_t *__restrict__ step_base,
+                                                     uint32_t step_off) {
+    for (int r = threadIdx.x; r < nrep; r += 64) {
+        const MeasRep &m = mr[r];
+        if (m.t.mom != nullptr)
+            series_finalize(m.t.mom, m.t.series, m.series_n, m.t.series_cap, 2 + m.t.n_rad,
+                            step_base[0] + step_off);
+    }
+}
+
+int measure_plan(const MeasRep *reps, int nrep, MeasPlan &P) {
+    P.nrep = nrep;
+    P.pre.assign(size_t(MK_COUNT) * (nrep + 1), 0);
+    for (int k = 0; k < 3; ++k) P.shm_fft[k] = 0;
+    P.shm_bin = 0;
+    P.any_series = false;
+    if (nrep < 1) return -1;
+    const int D = reps[0].g.D;
+    P.D = D;
+    int64_t tot[MK_COUNT] = {};
+    for (int r = 0; r < nrep; ++r) {
+        const MeasRep &m = reps[r];
+        const Geometry &g = m.g;
+        if (g.D != D) return -1;
+        int64_t n[MK_COUNT] = {};
+        n[MK_DENSITY] = int64_t((g.nx + 255) / 256) * g.ny * g.nz;
+        for (int d = 0; d < D; ++d) {
+            const PassDims p = pass_dims(g, d);
+            if (p.n0 > 8192) return -1;
+            n[MK_FFT + d] = int64_t(p.n1) * p.n2;
+            n[MK_ROT + d] = int64_t((p.n0 + 31) / 32) * ((p.n1 + 31) / 32) * p.n2;
+            const size_t sh = P.esz * 2 * size_t(p.n0);
+            if (sh > P.shm_fft[d]) P.shm_fft[d] = sh;
+        }
+        n[MK_BIN] = int64_t(g.ny) * g.nz;
+        n[MK_MODES] = m.modes_cap > 0 ? 1 : 0;
+        if (m.t.n_rad > 0) {
+            const size_t sh = sizeof(double) * 2 * size_t(g.nx / 2 + 3);
+            if (sh > P.shm_bin) P.shm_bin = sh;
+        }
+        if (m.t.mom != nullptr) P.any_series = true;
+        for (int k = 0; k < MK_COUNT; ++k) {
+            P.pre[size_t(k) * (nrep + 1) + r] = int(tot[k]);
+            tot[k] += n[k];
+            if (tot[k] > 0x7fffffff) return -1;
+        }
+    }
+    for (int k = 0; k < MK_COUNT; ++k) P.pre[size_t(k) * (nrep + 1) + nrep] = int(tot[k]);
+    if (P.shm_fft[0] > 160 * 1024 || P.shm_bin > 160 * 1024) return -1;
+    return 0;
+}
+
+template <class L, typename real>
+static hipError_t measure_impl(const MeasPlan &P, const MeasRep *mr, const int *pre, int par,
+                               const uint64_t *step_base, uint32_t step_off, hipStream_t s) {
+    const int nrep = P.nrep;
+    auto total = [&](int k) { return unsigned(P.pre[size_t(k) * (nrep + 1) + nrep]); };
+    auto pk = [&](int k) { return pre + size_t(k) * (nrep + 1); };
+    hipLaunchKernelGGL((k_density_batch<L, real>), dim3(total(MK_DENSITY)), dim3(256), 0, s, mr,
+                       pk(MK_DENSITY), nrep, par);
+    for (int d = 0; d < L::D; ++d) {
+        hipLaunchKernelGGL(k_fft_batch<real>, dim3(total(MK_FFT + d)), dim3(256), P.shm_fft[d], s, mr,
+                           pk(MK_FFT + d), nrep, d);
+        hipLaunchKernelGGL(k_rotate_batch<real>, dim3(total(MK_ROT + d)), dim3(256), 0, s, mr,
+                           pk(MK_ROT + d), nrep, d);
+    }
+    hipLaunchKernelGGL(k_bin_batch<real>, dim3(total(MK_BIN)), dim3(256), P.shm_bin, s, mr, pk(MK_BIN),
+                       nrep);
+    if (total(MK_MODES) > 0)
+        hipLaunchKernelGGL(k_modes_batch<real>, dim3(total(MK_MODES)), dim3(256), 0, s, mr, pk(MK_MODES),
+                           nrep);
+    if (P.any_series)
+        hipLaunchKernelGGL(k_series_batch, dim3(1), dim3(64), 0, s, mr, nrep, step_base, step_off);
     return hipGetLastError();
+}
+
+hipError_t launch_measure(const MeasPlan &P, const MeasRep *dev_reps, const int *dev_pre, int precision,
+                          int parity, const uint64_t *step_base, uint32_t step_off, hipStream_t s) {
+    if (P.nrep < 1 || P.pre.size() != size_t(MK_COUNT) * (P.nrep + 1)) return hipErrorInvalidValue;
+    if (P.D == 2)
+        return precision == 0 ? measure_impl<D2Q9, float>(P, dev_reps, dev_pre, parity, step_base, step_off, s)
+                              : measure_impl<D2Q9, double>(P, dev_reps, dev_pre, parity, step_base, step_off, s);
+    return precision == 0 ? measure_impl<D3Q19, float>(P, dev_reps, dev_pre, parity, step_base, step_off, s)
+                          : measure_impl<D3Q19, double>(P, dev_reps, dev_pre, parity, step_base, step_off, s);
 }
 
 // ---------------------------------------------------------------------------
