@@ -10,6 +10,13 @@ captured hipGraphs.  A "step" advances every replica by one time step.
 Prints one JSON line (value = MLUPS over the whole ensemble) with the
 roofline of the fused step kernel (HIP events on the library's stream) and
 the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+The step kernel is the one the autotuner picks: with the two-step kernel
+(temporal blocking) a launch advances two time steps with one read and one
+write of the populations, so its HBM traffic per lattice update halves and
+the vector ALUs become the bound; the roofline object then reports the ALU
+bound (VALU lane-instructions per launch from a counter run, over the live
+launch time, against the issue peak) and the HBM view beside it.
 """
 from __future__ import annotations
 
@@ -25,7 +32,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM roofline (FP32 D2Q9 fluct. SC); surrogate speedup at 5% S(k) err"
 HBM_PEAK_GBS = 8000.0
+# one non-packed VALU operation per lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 KERNEL_SOURCES = ["paper_2212_07848_amd/csrc/fsc_step_kernel.h",
+                  "paper_2212_07848_amd/csrc/fsc_step2_kernel.h",
                   "paper_2212_07848_amd/csrc/fsc_device.h"]
 
 
@@ -42,11 +52,25 @@ def bytes_per_lup(D: int, precision: str) -> int:
     return 2 * Q * (4 if precision == "fp32" else 8)
 
 
-def traffic_from_profile(stencil: str, noise: bool, tiling: dict):
-    """Measured HBM bytes per launch of the fused step (FETCH_SIZE + WRITE_SIZE,
-    scaled by the counters' reading of a plain copy of known size) from the
-    committed rocprofv3 summary, for the same kernel source and launch shape;
-    None when no such measurement exists."""
+def kernel_name(stencil: str, noise: bool, tiling: dict) -> str:
+    """Name of the step kernel a tiling launches (as rocprofv3 reports it)."""
+    n = "true" if noise else "false"
+    if tiling.get("steps", 1) == 2:
+        return f"k_step2<{stencil}, float, {n}, {tiling['tx']}>"
+    return f"k_step<D2Q9, {stencil}, float, {n}, {tiling['tx']}, {tiling['ty']}, {tiling['pf']}>"
+
+
+def grid_threads(tiling: dict) -> int:
+    extra = 64 if tiling.get("steps", 1) == 2 else 0  # the two-step kernel's edge wave
+    return tiling["blocks"] * (tiling["tx"] * tiling["ty"] + extra)
+
+
+def counters_from_profile(stencil: str, noise: bool, tiling: dict):
+    """Counter measurements of the step kernel per launch (HBM bytes:
+    FETCH_SIZE + WRITE_SIZE scaled by the counters' reading of a plain copy of
+    known size; VALU wave-instructions: SQ_INSTS_VALU) from the committed
+    rocprofv3 summary, for the same kernel source and launch shape (or the
+    nearest shape of the same kernel); (entry, note) or None."""
     path = os.path.join(ROOT, "profiles", "step_traffic.json")
     if not os.path.exists(path):
         return None
@@ -54,17 +78,16 @@ def traffic_from_profile(stencil: str, noise: bool, tiling: dict):
         doc = json.load(fh)
     if doc.get("kernel_hash") != kernel_hash():
         return None
-    tag = f"{stencil}, float, {'true' if noise else 'false'}, {tiling['tx']}, {tiling['ty']}, " \
-          f"{tiling['pf']}>"
-    threads = tiling["blocks"] * tiling["tx"] * tiling["ty"]
-    same = [e for e in doc["entries"] if e["kernel"].endswith(tag)]
+    name = kernel_name(stencil, noise, tiling)
+    threads = grid_threads(tiling)
+    same = [e for e in doc["entries"] if e["kernel"].endswith(name)]
     for e in same:
         if e["grid_threads"] == threads:
-            return e["bytes_per_launch"], "same kernel and launch shape"
+            return e, "same kernel and launch shape"
     if same:  # the autotuner picked another march length than in the counter run
         e = min(same, key=lambda e: abs(e["grid_threads"] - threads))
-        return e["bytes_per_launch"], f"same kernel, nearest launch shape ({e['grid_threads']} " \
-                                      f"threads in the counter run, {threads} here)"
+        return e, f"same kernel, nearest launch shape ({e['grid_threads']} threads in the " \
+                  f"counter run, {threads} here)"
     return None
 
 
@@ -72,16 +95,17 @@ COPY_BYTES = 1 << 30  # size of the calibration copy in copy_ceiling()
 PMC_ARGS = "--steps 64 --warmup 8 --kernel-steps 16 --no-cpu-baseline --no-surrogate"
 
 
-def ingest_pmc(fetch_csv: str, write_csv: str, out_path: str):
-    """Builds profiles/step_traffic.json from two rocprofv3 counter runs of
-    this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Both
-    counters are scaled so that the plain 1 GiB copy of copy_ceiling() reads
-    1 GiB fetched and 1 GiB written; the step kernels' per-launch means are
-    then HBM bytes per launch."""
+def ingest_pmc(fetch_csv: str, write_csv: str, valu_csv: str, out_path: str):
+    """Builds profiles/step_traffic.json from three rocprofv3 counter runs of
+    this script (FETCH_SIZE, WRITE_SIZE, SQ_INSTS_VALU).  FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) are scaled so that the plain 1 GiB copy of
+    copy_ceiling() reads 1 GiB fetched and 1 GiB written; the step kernels'
+    per-launch means are then HBM bytes per launch.  SQ_INSTS_VALU counts
+    the VALU instructions the waves issue (each acts on up to 64 lanes)."""
     import csv
     from collections import defaultdict
 
-    def load(path, counter):
+    def load(path, counter, calibrate=True):
         sums, counts, copies = defaultdict(float), defaultdict(int), []
         with open(path) as fh:
             for r in csv.DictReader(fh):
@@ -90,10 +114,12 @@ def ingest_pmc(fetch_csv: str, write_csv: str, out_path: str):
                 name, grid, v = r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])
                 if "fsc::k_copy" in name:
                     copies.append((grid, v))
-                elif "fsc::k_step<" in name:
+                elif "fsc::k_step<" in name or "fsc::k_step2<" in name:
                     key = (name.replace("void ", "").split("(")[0], grid)
                     sums[key] += v
                     counts[key] += 1
+        if not calibrate:
+            return {k: sums[k] / counts[k] for k in sums}, counts, 1.0
         # the calibration copy is the most frequent k_copy launch
         grids = defaultdict(list)
         for g, v in copies:
@@ -104,13 +130,15 @@ def ingest_pmc(fetch_csv: str, write_csv: str, out_path: str):
 
     fetch, counts, fscale = load(fetch_csv, "FETCH_SIZE")
     write, _, wscale = load(write_csv, "WRITE_SIZE")
+    valu, _, _ = load(valu_csv, "SQ_INSTS_VALU", calibrate=False)
     entries = []
     for key in sorted(fetch):
         if key not in write:
             continue
         entries.append(dict(kernel=key[0], grid_threads=key[1], launches=counts[key],
                             fetch_bytes=int(fetch[key]), write_bytes=int(write[key]),
-                            bytes_per_launch=int(fetch[key] + write[key])))
+                            bytes_per_launch=int(fetch[key] + write[key]),
+                            valu_insts_per_launch=int(valu[key]) if key in valu else None))
     for e in entries:
         e["kernel"] = e["kernel"].replace("fsc::", "")
     doc = dict(kernel_hash=kernel_hash(),
@@ -118,8 +146,11 @@ def ingest_pmc(fetch_csv: str, write_csv: str, out_path: str):
                          f"-- python3 bench.py {PMC_ARGS}",
                          f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write_dir> -o run "
                          f"-- python3 bench.py {PMC_ARGS}",
+                         f"rocprofv3 --pmc SQ_INSTS_VALU --output-format csv -d <valu_dir> -o run "
+                         f"-- python3 bench.py {PMC_ARGS}",
                          "python3 bench.py --ingest-pmc <fetch_dir>/run_counter_collection.csv "
-                         "<write_dir>/run_counter_collection.csv"],
+                         "<write_dir>/run_counter_collection.csv "
+                         "<valu_dir>/run_counter_collection.csv"],
                calibration=dict(note="plain 16-byte copy (fsc_copy) of 1 GiB; counter KiB x scale "
                                      "x 1024 = bytes", fetch_scale=round(fscale, 4),
                                 write_scale=round(wscale, 4)),
@@ -146,7 +177,7 @@ def summarize_trace(trace_dir: str, log_path: str, out_path: str):
     shapes = defaultdict(list)
     with open(os.path.join(trace_dir, "run_kernel_trace.csv")) as fh:
         for r in csv.DictReader(fh):
-            if "fsc::k_step<" in r["Kernel_Name"]:
+            if "fsc::k_step<" in r["Kernel_Name"] or "fsc::k_step2<" in r["Kernel_Name"]:
                 key = (r["Kernel_Name"].replace("void ", "").split("(")[0], int(r["Grid_Size_X"]))
                 shapes[key].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     bench = None
@@ -162,19 +193,19 @@ def summarize_trace(trace_dir: str, log_path: str, out_path: str):
     if bench:
         rf = bench["roofline"]
         t = rf["tiling"]
-        grid = t["blocks"] * t["tx"] * t["ty"]
-        key = next((k for k in shapes if k[1] == grid and k[0].endswith(
-            f"StencilE4_2D, float, true, {t['tx']}, {t['ty']}, {t['pf']}>")), None)
-        lines += ["## Benchmarked launch (64-replica D2Q9 ensemble, one launch per step)", "",
-                  f"- launch shape: {t['tx']}x{t['ty']} threads, prefetch {t['pf']}, "
-                  f"{t['blocks']} blocks ({grid} threads)",
+        grid = grid_threads(t)
+        kname = kernel_name("StencilE4_2D", True, t)
+        key = next((k for k in shapes if k[1] == grid and k[0].endswith(kname)), None)
+        lines += [f"## Benchmarked launch (64-replica D2Q9 ensemble, {t.get('steps', 1)} step(s) "
+                  f"per launch)", "",
+                  f"- kernel: `{kname}`, {t['blocks']} blocks ({grid} threads)",
                   f"- HIP events in the same run: {rf['avg_launch_us']} us per launch"]
         if key:
             v = shapes[key]
             lines.append(f"- rocprofv3 dispatch trace: {sum(v) / len(v) / 1e3:.2f} us mean over "
                          f"{len(v)} dispatches (min {min(v) / 1e3:.2f}, max {max(v) / 1e3:.2f})")
         lines += [f"- algorithmic bytes per launch: {bench['config']['lattice_updates_per_step']} "
-                  f"nodes x {rf['algorithmic_bytes_per_lup']} B", ""]
+                  f"nodes x {rf['algorithmic_bytes_per_node_per_launch']} B", ""]
     lines += ["## Step kernels by launch shape (dispatch trace)", "",
               "| kernel | grid threads | dispatches | mean us |", "|---|---|---|---|"]
     for (name, grid), v in sorted(shapes.items(), key=lambda kv: -sum(kv[1]))[:16]:
@@ -237,9 +268,11 @@ def run_single(cfg, steps, torch, fsc, kBT=None):
     tiling = lat.tiling
     lat.close()
     n = cfg["nx"] * cfg["ny"] * cfg["nz"]
-    return dict(mlups=n / t / 1e6, gbs=n * bytes_per_lup(cfg["D"], cfg["precision"]) / t / 1e9,
+    # bandwidth at the single-step traffic (one read and one write per update)
+    return dict(mlups=n / t / 1e6,
+                equivalent_single_step_gbs=n * bytes_per_lup(cfg["D"], cfg["precision"]) / t / 1e9,
                 ms_per_step=t * 1e3, tiling=f"{tiling['tx']}x{tiling['ty']}/pf{tiling['pf']}"
-                                              f"/{tiling['blocks']}blk")
+                                              f"/{tiling['blocks']}blk/{tiling['steps']}step")
 
 
 def copy_ceiling(torch, fsc, nbytes=1 << 30, reps=20):
@@ -348,8 +381,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/step_traffic.json from two rocprofv3 counter runs")
+    ap.add_argument("--ingest-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "VALU_CSV"),
+                    help="write profiles/step_traffic.json from three rocprofv3 counter runs")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "LOG", "OUT_MD"),
                     help="write a markdown summary of a rocprofv3 kernel-trace run")
     args = ap.parse_args()
@@ -375,9 +408,28 @@ def main():
     r = run_ensemble(args, torch, fsc, I)
     mlups = r["lups"] * args.steps / r["dt"] / 1e6
     bpl = bytes_per_lup(2, "fp32")
-    achieved = r["lups"] * bpl / r["t_step"] / 1e9
-    tr = traffic_from_profile("StencilE4_2D", True, r["tiling"])
-    traffic, traffic_note = tr if tr else (None, "no counter run of this kernel source")
+    tiling = r["tiling"]
+    steps_per_launch = tiling.get("steps", 1)
+    t_launch = r["t_step"] * steps_per_launch
+    # algorithmic HBM bytes per launch: one read and one write of every
+    # population of every node, whatever the number of steps the launch makes
+    hbm = r["lups"] * bpl / t_launch / 1e9
+    cnt = counters_from_profile("StencilE4_2D", True, tiling)
+    traffic, valu, note = None, None, "no counter run of this kernel source"
+    if cnt:
+        entry, note = cnt
+        traffic = entry["bytes_per_launch"]
+        if entry.get("valu_insts_per_launch"):
+            valu = entry["valu_insts_per_launch"] * 64 / t_launch / 1e12  # lane-ops, T/s
+    hbm_view = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": traffic}
+    alu_view = None if valu is None else {
+        "bound": "alu", "achieved": round(valu, 2), "peak": round(VALU_PEAK_TOPS, 2),
+        "unit": "Tlane-op/s", "frac": round(valu / VALU_PEAK_TOPS, 4), "traffic": traffic}
+    # the binding roofline is the one nearer its peak
+    main_view, other = hbm_view, alu_view
+    if alu_view and alu_view["frac"] > hbm_view["frac"]:
+        main_view, other = alu_view, hbm_view
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -394,20 +446,24 @@ def main():
         "config": {"workload": I.ENSEMBLE["name"], "replicas": r["nrep"], "sides": r["sides"],
                    "lattice_updates_per_step": r["lups"], "stencil": "E4", "sk_every": 100,
                    "kBT": 1e-13, "collision": "MRT all rates 1 (BGK tau=1)"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "traffic_source": traffic_note,
-                     "kernel": "k_step<D2Q9,E4,float,noise>",
-                     "algorithmic_bytes_per_lup": bpl,
-                     "avg_launch_us": round(r["t_step"] * 1e6, 2),
-                     "tiling": r["tiling"]},
+        "roofline": dict(main_view, **{
+            "traffic_source": note,
+            "kernel": kernel_name("StencilE4_2D", True, tiling),
+            "steps_per_launch": steps_per_launch,
+            "algorithmic_bytes_per_node_per_launch": bpl,
+            "avg_launch_us": round(t_launch * 1e6, 2),
+            # the single-step roofline of the metric: 72 B per lattice update
+            "equivalent_single_step_gbs": round(r["lups"] * bpl / r["t_step"] / 1e9, 1),
+            "equivalent_single_step_frac": round(r["lups"] * bpl / r["t_step"] / 1e9 / HBM_PEAK_GBS, 4),
+            "other": other,
+            "tiling": tiling}),
     }
     out["roofline"]["copy_ceiling_gbs"] = round(copy_ceiling(torch, fsc), 1)
     if not args.no_extra:
         extra = {}
         for cfg, steps in ((I.DEEP_QUENCH, 300), (I.METASTABLE_3D, 200)):
             e = run_single(cfg, steps, torch, fsc)
-            e["frac_hbm"] = round(e["gbs"] / HBM_PEAK_GBS, 4)
+            e["equivalent_single_step_frac"] = round(e["equivalent_single_step_gbs"] / HBM_PEAK_GBS, 4)
             extra[cfg["name"]] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in e.items()}
         e = run_single(I.DEEP_QUENCH, 300, torch, fsc, kBT=0.0)
         extra[I.DEEP_QUENCH["name"] + "_noise_free"] = {

@@ -346,21 +346,28 @@ int fsc_mfma_probe(const float *host_a, const float *host_b, float *host_c);
 int fsc_autotune(fsc_ctx *ctx);
 int fsc_ens_autotune(fsc_ens *ens);
 
-/* out[0..3] = tile x, tile y, prefetch depth, number of workgroups per step. */
-int fsc_get_tiling(const fsc_ctx *ctx, int *out4);
-int fsc_ens_get_tiling(const fsc_ens *ens, int *out4);
+/* out[0..4] = tile x, tile y, prefetch depth, workgroups per launch, time
+ * steps per launch (1, or 2 for the two-step kernel). */
+int fsc_get_tiling(const fsc_ctx *ctx, int *out5);
+int fsc_ens_get_tiling(const fsc_ens *ens, int *out5);
 
-/* The tile shapes compiled for a lattice kind: writes up to `max` triples
- * (tile x, tile y, prefetch depth) to host out3[3 max] and returns how many
- * exist (the first is the default), or FSC_E_INVAL for an unsupported kind. */
-int fsc_tile_shapes(int D, int stencil, int precision, int *out3, int max);
+/* The tilings compiled for a lattice kind: writes up to `max` quadruples
+ * (tile x, tile y, prefetch depth, steps per launch) to host out4[4 max] and
+ * returns how many exist (the first is the default), or FSC_E_INVAL for an
+ * unsupported kind.  Steps per launch 2 is the temporally blocked kernel of
+ * 2D FP32 lattices: each launch advances two time steps with one read and
+ * one write of the populations, keeping the intermediate state on chip; the
+ * results equal two single steps bit for bit.  Runs then go in pairs of steps,
+ * with single steps where an S(k) sample falls between two steps. */
+int fsc_tile_shapes(int D, int stencil, int precision, int *out4, int max);
 
-/* Fixes the tiling instead of tuning it: one of the compiled shapes, and a
+/* Fixes the tiling instead of tuning it: one of the compiled tilings, and a
  * marching length chosen to give about target_blocks (>= 1) workgroups per
- * step.  Results do not depend on it.  FSC_E_INVAL for a shape that is not
- * compiled for the lattice. */
-int fsc_set_tiling(fsc_ctx *ctx, int tx, int ty, int pf, int64_t target_blocks);
-int fsc_ens_set_tiling(fsc_ens *ens, int tx, int ty, int pf, int64_t target_blocks);
+ * launch.  Results do not depend on it.  FSC_E_INVAL for a tiling that is not
+ * compiled for the lattice, or a two-step tiling on a lattice narrower than
+ * 2R + 2 columns (R = 1 for E4, 2 for E8). */
+int fsc_set_tiling(fsc_ctx *ctx, int tx, int ty, int pf, int steps, int64_t target_blocks);
+int fsc_ens_set_tiling(fsc_ens *ens, int tx, int ty, int pf, int steps, int64_t target_blocks);
 
 /* ----------------------------------------------------------------------- */
 /* Diagnostics.                                                             */

@@ -138,8 +138,8 @@ def lib():
         "fsc_get_tiling": ([vp, C.POINTER(C.c_int)], C.c_int),
         "fsc_ens_get_tiling": ([vp, C.POINTER(C.c_int)], C.c_int),
         "fsc_tile_shapes": ([C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int], C.c_int),
-        "fsc_set_tiling": ([vp, C.c_int, C.c_int, C.c_int, C.c_int64], C.c_int),
-        "fsc_ens_set_tiling": ([vp, C.c_int, C.c_int, C.c_int, C.c_int64], C.c_int),
+        "fsc_set_tiling": ([vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64], C.c_int),
+        "fsc_ens_set_tiling": ([vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64], C.c_int),
         "fsc_copy": ([vp, vp, C.c_int64, vp], C.c_int),
         "fsc_philox": ([u32p, u32p, u32p, C.c_int64], C.c_int),
         "fsc_sur_create": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, vp,
@@ -257,12 +257,12 @@ class Lattice:
 
     @property
     def tiling(self):
-        out = (C.c_int * 4)()
+        out = (C.c_int * 5)()
         self._c(lib().fsc_get_tiling(self._h, out))
-        return dict(tx=out[0], ty=out[1], pf=out[2], blocks=out[3])
+        return dict(tx=out[0], ty=out[1], pf=out[2], blocks=out[3], steps=out[4])
 
-    def set_tiling(self, tx: int, ty: int, pf: int, target_blocks: int = 2048):
-        self._c(lib().fsc_set_tiling(self._h, int(tx), int(ty), int(pf), int(target_blocks)))
+    def set_tiling(self, tx: int, ty: int, pf: int, steps: int = 1, target_blocks: int = 2048):
+        self._c(lib().fsc_set_tiling(self._h, int(tx), int(ty), int(pf), int(steps), int(target_blocks)))
 
     def set_populations(self, f: np.ndarray, step: int = 0):
         f = np.ascontiguousarray(f, dtype=np.float64)
@@ -403,12 +403,13 @@ class Ensemble:
 
     @property
     def tiling(self):
-        out = (C.c_int * 4)()
+        out = (C.c_int * 5)()
         self._c(lib().fsc_ens_get_tiling(self._h, out))
-        return dict(tx=out[0], ty=out[1], pf=out[2], blocks=out[3])
+        return dict(tx=out[0], ty=out[1], pf=out[2], blocks=out[3], steps=out[4])
 
-    def set_tiling(self, tx: int, ty: int, pf: int, target_blocks: int = 2048):
-        self._c(lib().fsc_ens_set_tiling(self._h, int(tx), int(ty), int(pf), int(target_blocks)))
+    def set_tiling(self, tx: int, ty: int, pf: int, steps: int = 1, target_blocks: int = 2048):
+        self._c(lib().fsc_ens_set_tiling(self._h, int(tx), int(ty), int(pf), int(steps),
+                                         int(target_blocks)))
 
     def run(self, n: int, sk_every: int = 0):
         self._c(lib().fsc_ens_run(self._h, int(n), int(sk_every)))
@@ -579,14 +580,15 @@ def field_sk(fields, batch: int, n: int, stream=None):
 
 
 def tile_shapes(D: int, stencil: int, precision: str = "fp32"):
-    """Compiled (tile x, tile y, prefetch depth) shapes of a lattice kind; the first is the default."""
+    """Compiled (tile x, tile y, prefetch depth, steps per launch) tilings of a
+    lattice kind; the first is the default."""
     prec = {"fp32": FSC_FP32_SHIFTED, "fp64": FSC_FP64}[precision] if isinstance(precision, str) \
         else int(precision)
-    out = (C.c_int * 48)()
+    out = (C.c_int * 64)()
     n = lib().fsc_tile_shapes(int(D), int(stencil), prec, out, 16)
     if n < 0:
         raise FscError(n, "unsupported lattice kind")
-    return [(out[3 * i], out[3 * i + 1], out[3 * i + 2]) for i in range(min(n, 16))]
+    return [tuple(out[4 * i:4 * i + 4]) for i in range(min(n, 16))]
 
 
 def linear_sk(p: Params, kvecs) -> np.ndarray:

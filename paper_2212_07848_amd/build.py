@@ -25,6 +25,8 @@ SOURCES = [
     "fsc_step_d2e4_f64.hip",
     "fsc_step_d2e8_f32.hip",
     "fsc_step_d2e8_f64.hip",
+    "fsc_step2_e4.hip",
+    "fsc_step2_e8.hip",
     "fsc_step_d3e4_f32.hip",
     "fsc_step_d3e4_f64.hip",
     "fsc_measure.hip",

@@ -70,6 +70,7 @@ struct Rep {
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     int64_t samples = 0;
+    int flips = 0;  // parity of the number of kernel launches (each swaps the buffers)
 };
 
 }  // namespace
@@ -88,6 +89,7 @@ struct fsc_ens {
     int *d_tile_begin = nullptr;
     uint64_t *d_step = nullptr;
     int64_t step = 0;
+    int cur = 0;  // index of the buffer that holds the current state
     int total_tiles = 0;
     // batched S(k) sample of all replicas: host copy of the device table and its plan
     std::vector<MeasRep> meas;
@@ -419,9 +421,11 @@ void build_desc(fsc_ens *e) {
         const int ns = r.p.D == 3 ? r.p.nz : r.p.ny;
         work += int64_t(tx) * ty * ns;
     }
-    // marching length: enough blocks to fill 256 CUs several times over,
-    // but long marches so that the 2R halo planes stay a small overhead
-    int H = int(std::min<int64_t>(256, std::max<int64_t>(1, work / e->target_blocks)));
+    // marching length: the shortest that gives at most about target_blocks
+    // workgroups (rounding towards fewer blocks, so that a target equal to
+    // the number resident at once leaves no partial second round); long
+    // marches keep the halo planes a small overhead
+    int H = int(std::min<int64_t>(256, std::max<int64_t>(1, (work + e->target_blocks - 1) / e->target_blocks)));
     int tile_begin = 0;
     for (auto &r : e->reps) {
         RepDesc d{};
@@ -517,19 +521,49 @@ StepLaunch make_launch(fsc_ens *e, int parity, uint32_t off) {
     return L;
 }
 
-int enqueue_steps(fsc_ens *e, int parity, int64_t n, int64_t sk_every, int64_t *samples) {
-    for (int64_t k = 0; k < n; ++k) {
-        const StepLaunch L = make_launch(e, (parity + int(k & 1)) & 1, uint32_t(k));
+// Enqueues n steps from buffer `cur`: with a two-step tiling, steps go in
+// pairs except where an S(k) sample falls between them (and a last odd one);
+// those run the single-step kernel of the same tile width, which uses the
+// same tile table.  Returns the parity of the number of launches in *flips.
+bool pair_from(const fsc_ens *e, int64_t k, int64_t n, int64_t sk_every) {
+    return e->tile.steps == 2 && k + 1 < n && !(sk_every > 0 && (k + 1) % sk_every == 0);
+}
+
+// number of kernel launches enqueue_steps makes for n steps
+int64_t count_launches(const fsc_ens *e, int64_t n, int64_t sk_every) {
+    int64_t m = 0;
+    for (int64_t k = 0; k < n; k += pair_from(e, k, n, sk_every) ? 2 : 1) ++m;
+    return m;
+}
+
+int enqueue_steps(fsc_ens *e, int cur, int64_t n, int64_t sk_every, int64_t *samples, int *flips) {
+    int c = cur, launches = 0;
+    for (int64_t k = 0; k < n;) {
+        const bool two = pair_from(e, k, n, sk_every);
+        StepLaunch L = make_launch(e, c, uint32_t(k));
+        if (!two && L.tile.steps == 2) L.tile = TileShape{L.tile.tx, 1, 1};
         HIPCHK(e, launch_step(L, e->stream));
-        if (sk_every > 0 && (k + 1) % sk_every == 0) {
-            const int par = (parity + int((k + 1) & 1)) & 1;
-            int rc = enqueue_measure(e, par, uint32_t(k + 1));
+        c ^= 1;
+        ++launches;
+        k += two ? 2 : 1;
+        if (sk_every > 0 && k % sk_every == 0) {
+            int rc = enqueue_measure(e, c, uint32_t(k));
             if (rc) return rc;
             if (samples) ++*samples;
         }
     }
     HIPCHK(e, launch_step_advance(e->d_step, uint64_t(n), e->stream));
+    if (flips) *flips = launches & 1;
     return FSC_OK;
+}
+
+// Two-step tilings need 2D FP32 lattices at least 2R + 2 columns wide.
+bool two_step_ok(const fsc_ens *e) {
+    if (e->D != 2 || e->precision != FSC_FP32_SHIFTED) return false;
+    const int R = e->stencil == FSC_E8 ? 2 : 1;
+    for (const auto &r : e->reps)
+        if (r.p.nx < 2 * R + 2) return false;
+    return true;
 }
 
 // -------------------------------------------------------------------------
@@ -567,19 +601,22 @@ int ens_autotune(fsc_ens *e) {
             return upload_desc(e);
         }
     }
-    TileShape shapes[8];
-    const int nshape = tile_shapes(e->D, e->stencil, e->precision, shapes, 8);
-    // block counts around one and a few rounds of the ~1.5-2k blocks that
-    // are resident at once (256 CUs x 6-8 blocks of 256 threads)
-    const int64_t targets[] = {768, 1024, 1536, 2048, 3072, 4096, 6144, 8192, 12288, 16384, 24576, 32768, 65536};
+    TileShape shapes[16];
+    const int nshape = tile_shapes(e->D, e->stencil, e->precision, shapes, 16);
+    // block counts of one round of resident workgroups (a multiple of the
+    // 256 CUs: 1-8 per CU, depending on the kernel's LDS and registers) and
+    // of several rounds
+    const int64_t targets[] = {256,  512,  768,  1024, 1280,  1536,  1792, 2048,
+                               2560, 3072, 4096, 6144, 8192, 12288, 16384};
     hipEvent_t a, b;
     HIPCHK(e, hipEventCreate(&a));
     HIPCHK(e, hipEventCreate(&b));
     float best = 1e30f;
     TuneChoice choice{e->tile, e->target_blocks};
-    const int parity = int(e->step & 1);
+    const int parity = e->cur;
     for (int si = 0; si < nshape; ++si)
         for (int64_t tg : targets) {
+            if (shapes[si].steps == 2 && !two_step_ok(e)) continue;
             e->tile = shapes[si];
             e->target_blocks = tg;
             int rc = upload_desc(e);
@@ -592,6 +629,7 @@ int ens_autotune(fsc_ens *e) {
             HIPCHK(e, hipEventSynchronize(b));
             float ms = 0.f;
             HIPCHK(e, hipEventElapsedTime(&ms, a, b));
+            ms /= float(shapes[si].steps);  // per step
             if (ms < best) {
                 best = ms;
                 choice = TuneChoice{shapes[si], tg};
@@ -632,22 +670,28 @@ int ens_run(fsc_ens *e, int64_t nsteps, int64_t sk_every) {
             e->autotune = 0;
         }
     }
-    // whole chunks as graph replays
+    // whole chunks as graph replays; a graph holds the buffer of its first
+    // launch, so a chunk must make an even number of launches (each launch
+    // swaps the buffers)
     int64_t chunk = sk_every > 0 ? sk_every : 64;
-    if (chunk & 1) chunk *= 2;
+    if (count_launches(e, chunk, sk_every) & 1) chunk *= 2;
     int64_t done = 0;
     const int64_t nchunks = nsteps / chunk;
     if (nchunks >= 2) {
-        const int parity = int(e->step & 1);
+        const int parity = e->cur;
         auto key = std::make_pair(parity, std::make_pair(chunk, sk_every));
         auto it = e->graphs.find(key);
         if (it == e->graphs.end()) {
             GraphEntry ge;
             hipGraph_t graph;
             HIPCHK(e, hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
-            int rc = enqueue_steps(e, parity, chunk, sk_every, &ge.samples);
+            int rc = enqueue_steps(e, parity, chunk, sk_every, &ge.samples, &ge.flips);
             hipError_t ec = hipStreamEndCapture(e->stream, &graph);
             if (rc) return rc;
+            if (ge.flips) {
+                (void)hipGraphDestroy(graph);
+                return fail(e, FSC_E_STATE, "graph chunk with an odd number of launches");
+            }
             if (ec != hipSuccess) return fail(e, FSC_E_HIP, std::string("capture: ") + hipGetErrorString(ec));
             ec = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
@@ -662,8 +706,10 @@ int ens_run(fsc_ens *e, int64_t nsteps, int64_t sk_every) {
     const int64_t rest = nsteps - done;
     if (rest > 0) {
         int64_t samples = 0;
-        int rc = enqueue_steps(e, int(e->step & 1), rest, sk_every, &samples);
+        int flips = 0;
+        int rc = enqueue_steps(e, e->cur, rest, sk_every, &samples, &flips);
         if (rc) return rc;
+        e->cur ^= flips;
         for (auto &r : e->reps) r.nsamples += samples;
         e->step += rest;
     }
@@ -704,8 +750,8 @@ int ens_create(const fsc_params *ps, int nrep, void *stream, void *ext_a, void *
     e->D = rp[0].D;
     e->stencil = rp[0].stencil;
     e->precision = rp[0].precision;
-    TileShape shapes[8];
-    tile_shapes(e->D, e->stencil, e->precision, shapes, 8);
+    TileShape shapes[16];
+    tile_shapes(e->D, e->stencil, e->precision, shapes, 16);
     e->tile = shapes[0];
     if (const char *env = std::getenv("FSC_AUTOTUNE")) e->autotune = std::atoi(env) ? -2 : 0;
     e->reps.resize(nrep);
@@ -759,9 +805,10 @@ int rep_index(fsc_ens *e, int replica) {
 }
 
 int ens_set_pop(fsc_ens *e, int ri, const double *host_f, int64_t step) {
+    (void)step;
     Rep &r = e->reps[ri];
     const int nx = r.p.nx, ny = r.p.ny, nz = r.p.nz;
-    const int par = int(step & 1);
+    const int par = e->cur;
     std::vector<unsigned char> raw(r.esz * size_t(r.Q) * size_t(r.N));
     for (int i = 0; i < r.Q; ++i) {
         const int cx = r.c[3 * i], cy = r.c[3 * i + 1], cz = r.c[3 * i + 2];
@@ -786,7 +833,7 @@ int ens_set_pop(fsc_ens *e, int ri, const double *host_f, int64_t step) {
 int ens_get_pop(fsc_ens *e, int ri, double *host_f) {
     Rep &r = e->reps[ri];
     const int nx = r.p.nx, ny = r.p.ny, nz = r.p.nz;
-    const int par = int(e->step & 1);
+    const int par = e->cur;
     std::vector<unsigned char> raw(r.esz * size_t(r.Q) * size_t(r.N));
     HIPCHK(e, hipMemcpyAsync(raw.data(), r.buf[par], raw.size(), hipMemcpyDeviceToHost, e->stream));
     HIPCHK(e, hipStreamSynchronize(e->stream));
@@ -809,7 +856,7 @@ int ens_get_pop(fsc_ens *e, int ri, double *host_f) {
 
 int ens_stats(fsc_ens *e, int ri, double *out8) {
     Rep &r = e->reps[ri];
-    HIPCHK(e, launch_stats(r.geom(), r.p.precision, r.buf[e->step & 1], r.p.rho0, r.d_partials,
+    HIPCHK(e, launch_stats(r.geom(), r.p.precision, r.buf[e->cur], r.p.rho0, r.d_partials,
                            r.d_stats, e->stream));
     HIPCHK(e, hipMemcpyAsync(out8, r.d_stats, sizeof(double) * 8, hipMemcpyDeviceToHost, e->stream));
     HIPCHK(e, hipStreamSynchronize(e->stream));
@@ -863,6 +910,7 @@ int ens_init_uniform(fsc_ens *e) {
         HIPCHK(e, hipMemsetAsync(r.buf[0], 0, bytes, e->stream));
         HIPCHK(e, hipMemsetAsync(r.buf[1], 0, bytes, e->stream));
     }
+    e->cur = 0;
     int rc = set_step_device(e, 0);
     if (rc) return rc;
     return ens_sk_reset(e);
@@ -876,7 +924,7 @@ int ens_density(fsc_ens *e, int ri, double *host_rho) {
         (void)hipGetLastError();
         return fail(e, FSC_E_OOM, "density buffer");
     }
-    hipError_t ec = launch_density_real(r.geom(), r.p.precision, r.buf[e->step & 1], tmp, e->stream);
+    hipError_t ec = launch_density_real(r.geom(), r.p.precision, r.buf[e->cur], tmp, e->stream);
     std::vector<unsigned char> raw(r.esz * size_t(r.N));
     if (ec == hipSuccess) ec = hipMemcpyAsync(raw.data(), tmp, raw.size(), hipMemcpyDeviceToHost, e->stream);
     if (ec == hipSuccess) ec = hipStreamSynchronize(e->stream);
@@ -915,7 +963,7 @@ int ens_save(fsc_ens *e, const char *path) {
     auto put = [&](const void *p, size_t n) { return std::fwrite(p, 1, n, fp.get()) == n; };
     const uint32_t head[4] = {kCkptMagic, kCkptVersion, uint32_t(e->reps.size()), 0};
     bool ok = put(head, sizeof(head)) && put(&e->step, sizeof(e->step));
-    const int par = int(e->step & 1);
+    const int par = e->cur;
     std::vector<unsigned char> raw;
     std::vector<double> acc;
     for (size_t k = 0; ok && k < e->reps.size(); ++k) {
@@ -969,7 +1017,7 @@ int ens_load(fsc_ens *e, const char *path) {
         if (!get(raws[k].data(), nbytes) || !get(accs[k].data(), sizeof(double) * nsk))
             return fail(e, FSC_E_IO, "truncated checkpoint");
     }
-    const int par = int(step & 1);
+    const int par = e->cur;
     for (size_t k = 0; k < n; ++k) {
         Rep &r = e->reps[k];
         HIPCHK(e, hipMemcpyAsync(r.buf[par], raws[k].data(), raws[k].size(), hipMemcpyHostToDevice,
@@ -1091,7 +1139,7 @@ int fsc_measure_sk(fsc_ctx *ctx) {
     if (rc) return rc;
     rc = ensure_measure_plan(e);
     if (rc) return rc;
-    rc = enqueue_measure(e, int(e->step & 1), 0);
+    rc = enqueue_measure(e, e->cur, 0);
     if (rc) return rc;
     r.nsamples += 1;
     return FSC_OK;
@@ -1226,37 +1274,41 @@ int fsc_ens_read_modes(fsc_ens *ens, int replica, double *out, int max_rows, int
 // ---- tiling ---------------------------------------------------------------
 int fsc_autotune(fsc_ctx *ctx) { return ctx ? ens_autotune(ctx->e) : FSC_E_INVAL; }
 int fsc_ens_autotune(fsc_ens *ens) { return ens ? ens_autotune(ens) : FSC_E_INVAL; }
-static int get_tiling(const fsc_ens *e, int *out4) {
-    if (!out4) return FSC_E_INVAL;
-    out4[0] = e->tile.tx;
-    out4[1] = e->tile.ty;
-    out4[2] = e->tile.pf;
-    out4[3] = e->total_tiles;
+static int get_tiling(const fsc_ens *e, int *out5) {
+    if (!out5) return FSC_E_INVAL;
+    out5[0] = e->tile.tx;
+    out5[1] = e->tile.ty;
+    out5[2] = e->tile.pf;
+    out5[3] = e->total_tiles;
+    out5[4] = e->tile.steps;
     return FSC_OK;
 }
-int fsc_get_tiling(const fsc_ctx *ctx, int *out4) { return ctx ? get_tiling(ctx->e, out4) : FSC_E_INVAL; }
-int fsc_ens_get_tiling(const fsc_ens *ens, int *out4) { return ens ? get_tiling(ens, out4) : FSC_E_INVAL; }
+int fsc_get_tiling(const fsc_ctx *ctx, int *out5) { return ctx ? get_tiling(ctx->e, out5) : FSC_E_INVAL; }
+int fsc_ens_get_tiling(const fsc_ens *ens, int *out5) { return ens ? get_tiling(ens, out5) : FSC_E_INVAL; }
 
-int fsc_tile_shapes(int D, int stencil, int precision, int *out3, int max) {
+int fsc_tile_shapes(int D, int stencil, int precision, int *out4, int max) {
     if (!((D == 2 && (stencil == FSC_E4 || stencil == FSC_E8)) || (D == 3 && stencil == FSC_E4)) ||
-        (precision != FSC_FP32_SHIFTED && precision != FSC_FP64) || max < 0 || (max > 0 && !out3))
+        (precision != FSC_FP32_SHIFTED && precision != FSC_FP64) || max < 0 || (max > 0 && !out4))
         return FSC_E_INVAL;
     TileShape t[16];
     const int n = tile_shapes(D, stencil, precision, t, 16);
     for (int i = 0; i < n && i < max; ++i) {
-        out3[3 * i] = t[i].tx;
-        out3[3 * i + 1] = t[i].ty;
-        out3[3 * i + 2] = t[i].pf;
+        out4[4 * i] = t[i].tx;
+        out4[4 * i + 1] = t[i].ty;
+        out4[4 * i + 2] = t[i].pf;
+        out4[4 * i + 3] = t[i].steps;
     }
     return n;
 }
 
-static int set_tiling(fsc_ens *e, int tx, int ty, int pf, int64_t target_blocks) {
+static int set_tiling(fsc_ens *e, int tx, int ty, int pf, int steps, int64_t target_blocks) {
     if (target_blocks < 1) return fail(e, FSC_E_INVAL, "target_blocks < 1");
     TileShape t[16];
     const int n = tile_shapes(e->D, e->stencil, e->precision, t, 16);
     for (int i = 0; i < n; ++i)
-        if (t[i].tx == tx && t[i].ty == ty && t[i].pf == pf) {
+        if (t[i].tx == tx && t[i].ty == ty && t[i].pf == pf && t[i].steps == steps) {
+            if (steps == 2 && !two_step_ok(e))
+                return fail(e, FSC_E_INVAL, "two-step tiling needs sides of at least 2R + 2 columns");
             e->tile = t[i];
             e->target_blocks = target_blocks;
             drop_graphs(e);
@@ -1265,11 +1317,11 @@ static int set_tiling(fsc_ens *e, int tx, int ty, int pf, int64_t target_blocks)
         }
     return fail(e, FSC_E_INVAL, "tile shape not compiled for this lattice (see fsc_tile_shapes)");
 }
-int fsc_set_tiling(fsc_ctx *ctx, int tx, int ty, int pf, int64_t target_blocks) {
-    return ctx ? set_tiling(ctx->e, tx, ty, pf, target_blocks) : FSC_E_INVAL;
+int fsc_set_tiling(fsc_ctx *ctx, int tx, int ty, int pf, int steps, int64_t target_blocks) {
+    return ctx ? set_tiling(ctx->e, tx, ty, pf, steps, target_blocks) : FSC_E_INVAL;
 }
-int fsc_ens_set_tiling(fsc_ens *ens, int tx, int ty, int pf, int64_t target_blocks) {
-    return ens ? set_tiling(ens, tx, ty, pf, target_blocks) : FSC_E_INVAL;
+int fsc_ens_set_tiling(fsc_ens *ens, int tx, int ty, int pf, int steps, int64_t target_blocks) {
+    return ens ? set_tiling(ens, tx, ty, pf, steps, target_blocks) : FSC_E_INVAL;
 }
 
 // ---- coarse-graining and field measurement (surrogate inputs/outputs) ---
@@ -1279,7 +1331,7 @@ int fsc_coarsen(fsc_ctx *ctx, int factor, float *dev_out) {
     Rep &r = e->reps[0];
     if (r.p.D != 2 || factor < 1 || r.p.nx % factor || r.p.ny % factor)
         return fail(e, FSC_E_INVAL, "coarsening needs a 2D lattice with sides divisible by factor");
-    HIPCHK(e, launch_coarsen(r.geom(), r.p.precision, r.buf[e->step & 1], r.p.rho0, factor, dev_out,
+    HIPCHK(e, launch_coarsen(r.geom(), r.p.precision, r.buf[e->cur], r.p.rho0, factor, dev_out,
                              e->stream));
     return FSC_OK;
 }
@@ -1291,7 +1343,7 @@ int fsc_ens_coarsen(fsc_ens *ens, int replica, int factor, float *dev_out) {
     Rep &r = ens->reps[replica];
     if (r.p.D != 2 || factor < 1 || r.p.nx % factor || r.p.ny % factor)
         return fail(ens, FSC_E_INVAL, "coarsening needs a 2D lattice with sides divisible by factor");
-    HIPCHK(ens, launch_coarsen(r.geom(), r.p.precision, r.buf[ens->step & 1], r.p.rho0, factor,
+    HIPCHK(ens, launch_coarsen(r.geom(), r.p.precision, r.buf[ens->cur], r.p.rho0, factor,
                                dev_out, ens->stream));
     return FSC_OK;
 }

@@ -13,7 +13,8 @@ namespace fsc {
 // Tile shape of the fused step kernel: a TX x TY cross-section (TY = 1 in 2D)
 // marching along the slowest axis.
 struct TileShape {
-    int tx, ty, pf;  // cross-section tile and register prefetch depth (planes)
+    int tx, ty, pf;     // cross-section tile and register prefetch depth (planes)
+    int steps = 1;      // time steps per launch: 1, or 2 (two-step kernel, 2D FP32)
 };
 
 // Launch of one step over every replica of an ensemble.
@@ -30,7 +31,10 @@ struct StepLaunch {
     TileShape tile;
 };
 
-// Returns hipErrorInvalidValue when no instantiation matches.
+// One launch of the tile's kernel: one step, or two when L.tile.steps == 2
+// (then the state goes from buf[parity] at step_base + step_off to
+// buf[parity ^ 1] at two steps later).  hipErrorInvalidValue when no
+// instantiation matches.
 hipError_t launch_step(const StepLaunch &L, hipStream_t s);
 // Tile shapes compiled for a lattice/stencil; the first is the default.
 int tile_shapes(int D, int stencil, int precision, TileShape *out, int max);

@@ -1,0 +1,316 @@
+// fsc_step2_kernel.h -- two fused time steps of the fluctuating Shan-Chen
+// lattice Boltzmann equation (Eq. 12 of Lulli et al., arXiv:2212.07848) per
+// pass over HBM, for D2Q9 (temporal blocking).
+//
+// The single-step kernel reads and writes every population once per step.
+// Here a workgroup computes step t -> t+1 ("level 1") on its tile widened by
+// R + 1 columns and rows, keeps f(t+1) in LDS, and immediately computes
+// t+1 -> t+2 ("level 2") on the tile itself, so that each step costs half the
+// HBM traffic.  The per-node arithmetic is the single-step kernel's (same
+// functions, same order), so two steps here equal two single steps bit for
+// bit, and the noise keeps its counter (node, step) keys.
+//
+// Workgroup: TX tile lanes plus one extra wave.  Every thread owns one
+// level-1 node at column offset x1 from the tile origin x0:
+//   tile lanes           x1 = lane (lanes past a ragged edge duplicate the last
+//                        valid column and write nothing to LDS)
+//   extra wave, e < 2R+2 the level-1 edge columns -R-1..-1 and TXe..TXe+R
+//   extra wave, e < 4R+2 psi-only columns -2R-1..-R-2 and TXe+R+1..TXe+2R
+// and at most one level-2 node: tile lanes x2 = x1 (collide and store), extra
+// wave e < 2R the psi(t+1)-only columns -R..-1 and TXe..TXe+R-1.  When the
+// tile spans a whole periodic row (one tile across) the extra wave idles and
+// the tile lanes near either end also write their LDS values at the periodic
+// image columns, so the halo reads stay plain offsets.
+//
+// March of a chunk of H output rows o_0..o_{H-1} (direction alternating by
+// chunk as in the single-step kernel): level 1 runs over the rows
+// l_k = o_{k-R-1}, k = 0..H+2R+1, with the pulled rows of f(t) in a register
+// ring of R+1 rows and psi(t) in an LDS ring of 2R+2 rows (A); f(t+1) goes to
+// an LDS ring of 4 rows (B).  Iteration j, one barrier:
+//   before the barrier: loads of level-1 row l_{j+R}; the noise of both levels;
+//     level 2 pulls f(t+1) of row l_{j-3} from B (rows written at least two
+//     iterations ago) into a register ring of R+1 rows and writes its
+//     psi(t+1) into an LDS ring of 2R+2 rows (C); psi(t) of row l_{j+R} -> A;
+//   after the barrier: level-1 force and collision of row l_j -> B; level-2
+//     force and collision of row l_{j-3-R} -> HBM.
+// The ring sizes make one barrier per iteration sufficient: no slot is
+// rewritten while a slower wave of the previous iteration may still read it.
+#pragma once
+
+#include "fsc_step_kernel.h"
+
+namespace fsc {
+
+template <class ST, typename real, bool NOISE, int TX>
+__global__ void __launch_bounds__(TX + 64)
+    k_step2(const RepDesc *__restrict__ reps, const int *__restrict__ tile_begin, int nrep,
+            int parity, const uint64_t *__restrict__ step_base, uint32_t step_off) {
+    using L = D2Q9;
+    constexpr int Q = 9, R = ST::R, NN = L::NNORM;
+    constexpr int NR = R + 1;                       // register rings (rows)
+    constexpr int SA = 2 * R + 2, SB = 4, SC = 2 * R + 2;
+    constexpr int OA = 2 * R + 1, OB = R + 1, OC = R;  // column of offset 0
+    constexpr int WA = TX + 4 * R + 2, WB = TX + 2 * R + 2, WC = TX + 2 * R;
+    constexpr uint32_t ES = sizeof(real);
+    __shared__ real A[SA][WA];
+    __shared__ real B[SB][Q][WB];
+    __shared__ real Cs[SC][WC];
+
+    // ---- which replica / tile (as in the single-step kernel) ----------------
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    int lo = 0, hi = nrep - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_begin[mid] <= lb) lo = mid;
+        else hi = mid - 1;
+    }
+    const RepDesc &d = reps[lo];
+    const int nx = d.nx, ns = d.ny;
+    const int t = lb - d.tile_begin;
+    const int tix = t % d.tiles_x;
+    const int chunk = t / d.tiles_x;
+    const int s_begin = chunk * d.H;
+    const int s_end = min(s_begin + d.H, ns);
+    const int H = s_end - s_begin;
+    const int x0 = tix * TX;
+    const int TXe = min(TX, nx - x0);
+    const bool full = d.tiles_x == 1;  // TXe == nx: the tile holds whole periodic rows
+
+    const int tid = threadIdx.x;
+    const bool ewave = tid >= TX;
+    const int e = tid - TX;
+    const bool eidle = ewave && full;  // wave-uniform
+
+    // level-1 node: column offset x1, collides (c1), writes to A (wa) and B (wb)
+    int x1 = 0;
+    bool c1 = !ewave, wa = false, wb = false;
+    if (!ewave) {
+        x1 = min(tid, TXe - 1);
+        wa = wb = tid < TXe;
+    } else if (!full && e < 2 * R + 2) {
+        x1 = e < R + 1 ? -R - 1 + e : TXe + (e - R - 1);
+        c1 = wa = wb = true;
+    } else if (!full && e < 4 * R + 2) {
+        const int k = e - 2 * R - 2;
+        x1 = k < R ? -2 * R - 1 + k : TXe + R + 1 + (k - R);
+        wa = true;
+    }
+    // level-2 node: column offset x2, forms psi(t+1) (p2), writes to C (wc);
+    // tile lanes collide and store to HBM
+    int x2 = 0;
+    bool p2 = !ewave, wc = false;
+    if (!ewave) {
+        x2 = x1;
+        wc = tid < TXe;
+    } else if (!full && e < 2 * R) {
+        x2 = e < R ? -R + e : TXe + (e - R);
+        p2 = wc = true;
+    }
+    // periodic images of tile columns near the row ends (whole-row tiles only)
+    const bool mir = full && !ewave && tid < TXe;
+    const int ia_lo = (mir && x1 >= nx - (2 * R + 1)) ? x1 - nx + OA : -1;
+    const int ia_hi = (mir && x1 <= 2 * R) ? x1 + nx + OA : -1;
+    const int ib_lo = (mir && x1 >= nx - (R + 1)) ? x1 - nx + OB : -1;
+    const int ib_hi = (mir && x1 <= R) ? x1 + nx + OB : -1;
+    const int ic_lo = (mir && x2 >= nx - R) ? x2 - nx + OC : -1;
+    const int ic_hi = (mir && x2 <= R - 1) ? x2 + nx + OC : -1;
+
+    const uint64_t buf_bytes = uint64_t(Q) * uint64_t(d.N) * sizeof(real);
+    const rsrc_t src = make_rsrc(d.buf[parity], buf_bytes);
+    const rsrc_t dst = make_rsrc(d.buf[parity ^ 1], buf_bytes);
+    const uint32_t pop_bytes = uint32_t(d.N) * ES;
+    const uint32_t pbytes = uint32_t(nx) * ES;
+
+    constexpr bool F32 = sizeof(real) == 4;
+    const real rho0 = F32 ? real(d.rho0f) : real(d.rho0);
+    const real psi0 = F32 ? real(d.psi0f) : real(d.psi0);
+    const real G = F32 ? real(d.Gf) : real(d.G);
+    const real inv_rho0 = F32 ? real(d.inv_rho0f) : real(1.0 / d.rho0);
+    real lc[4], ac[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        lc[k] = F32 ? real(d.lamcf[k]) : real(d.lamc[k]);
+        ac[k] = F32 ? real(d.ampcf[k]) : real(d.ampc[k]);
+    }
+
+    // ---- pull offsets of the level-1 node (bytes within a row) ---------------
+    const int gx1 = wrap_any(x0 + x1, nx);
+    const int gx2 = wrap_any(x0 + x2, nx);
+    uint32_t xo[3];  // index c_x + 1 -> column x - c_x
+    xo[0] = uint32_t(gx1 + 1 == nx ? 0 : gx1 + 1) * ES;
+    xo[1] = uint32_t(gx1) * ES;
+    xo[2] = uint32_t(gx1 == 0 ? nx - 1 : gx1 - 1) * ES;
+    auto wrap_row = [ns](int v) {
+        while (v < 0) v += ns;
+        while (v >= ns) v -= ns;
+        return v;
+    };
+    auto load_row = [&](int row, real (&out)[Q]) {
+        const int pc = wrap_row(row);
+        const int pp = pc + 1 == ns ? 0 : pc + 1, pm = pc == 0 ? ns - 1 : pc - 1;
+        const uint32_t pb[3] = {uint32_t(pp) * pbytes, uint32_t(pc) * pbytes, uint32_t(pm) * pbytes};
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            out[i] = bload<real>(src, xo[L::c(i, 0) + 1], uint32_t(i) * pop_bytes + pb[L::c(i, 1) + 1]);
+    };
+    auto dpsi_of = [&](const real (&fv)[Q]) {
+        real dn = real(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dn += fv[i];
+        return psi0 * fexpm1(dn * inv_rho0 * fast_rcp(rho0 + dn));
+    };
+
+    const uint64_t step = step_base[0] + step_off;
+    const uint32_t step1 = uint32_t(step), step2 = uint32_t(step + 1);
+
+    // ---- march order ----------------------------------------------------------
+    const int dir = (chunk & 1) ? -1 : 1;
+    const int first = dir > 0 ? s_begin : s_end - 1;       // o_0
+    auto lrow = [&](int k) { return first + dir * (k - R - 1); };  // lattice row of l_k
+    const int H1 = H + 2 * R + 2;                          // level-1 rows
+    const int J = H1 + 2;                                  // iterations
+
+    auto put_a = [&](int k, real v) {  // psi(t) of l_k
+        const int sl = (k + SA) % SA;
+        if (wa) A[sl][x1 + OA] = v;
+        if (ia_lo >= 0) A[sl][ia_lo] = v;
+        if (ia_hi >= 0) A[sl][ia_hi] = v;
+    };
+
+    // ---- prologue: psi(t) of l_{-R} .. l_{R-1}; pulled rows l_0 .. l_{R-1} ----
+    real F[NR][Q];
+    real G2[NR][Q];
+#pragma unroll
+    for (int k = -R; k < R; ++k) {
+        real tm[Q];
+        if (!eidle) load_row(lrow(k), tm);
+        else
+#pragma unroll
+            for (int i = 0; i < Q; ++i) tm[i] = real(0);
+        put_a(k, eidle ? real(0) : dpsi_of(tm));
+        if (k >= 0) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) F[k][i] = tm[i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) G2[k][i] = real(0);
+
+    const uint32_t lane_store = uint32_t(x0 + x2) * ES;  // tile lanes only store
+
+    for (int j0 = 0; j0 < J; j0 += NR) {
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int j = j0 + u;
+            if (j >= J) break;
+            const bool lev1 = j < H1;
+            const bool psi2 = j >= 4 && j <= H1 + 1;
+            const bool lev2 = j >= 2 * R + 4 && j <= H1 + 1;
+            // register-ring slots (constants once the loop over u is unrolled)
+            const int fs_new = (u + R) % NR;                  // row l_{j+R}
+            const int gs_new = ((u - 3) % NR + NR) % NR;      // row l_{j-3}
+            const int gs_use = ((u - 3 - R) % NR + NR) % NR;  // row l_{j-3-R}
+
+            // loads of level-1 row l_{j+R} (consumed by its psi below and by
+            // its collision R iterations later)
+            if (lev1 && !eidle) load_row(lrow(j + R), F[fs_new]);
+            // noise of both levels (independent of memory and LDS)
+            real z1[NN], z2[NN];
+            if constexpr (NOISE) {
+                if (lev1 && !eidle) node_normals<L, real>(uint32_t(gx1 + nx * wrap_row(lrow(j))), step1,
+                                                         d.seed_hi, d.key0, d.key1, z1);
+                if (lev2 && !ewave)
+                    node_normals<L, real>(uint32_t(gx2 + nx * wrap_row(lrow(j - 3 - R))), step2,
+                                          d.seed_hi, d.key0, d.key1, z2);
+            }
+            if constexpr (!NOISE) {
+#pragma unroll
+                for (int k = 0; k < NN; ++k) z1[k] = z2[k] = real(0);
+            }
+            // level 2: pull f(t+1) of l_{j-3} from B, its psi(t+1) -> C.  The
+            // rings are indexed by march position, so lattice row offset dy is
+            // position offset dir * dy.
+            if (psi2 && p2) {
+                const int k = j - 3;
+                const int sb[3] = {(k + dir) & 3, k & 3, (k - dir) & 3};  // c_y + 1 -> row - c_y
+                real(&g2)[Q] = G2[gs_new];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) g2[i] = B[sb[L::c(i, 1) + 1]][i][x2 - L::c(i, 0) + OB];
+                const real v = dpsi_of(g2);
+                const int sl = k % SC;
+                if (wc) Cs[sl][x2 + OC] = v;
+                if (ic_lo >= 0) Cs[sl][ic_lo] = v;
+                if (ic_hi >= 0) Cs[sl][ic_hi] = v;
+            }
+            // psi(t) of l_{j+R} -> A
+            if (lev1) put_a(j + R, eidle ? real(0) : dpsi_of(F[fs_new]));
+            __syncthreads();
+
+            // ---- level 1: row l_j -> B --------------------------------------
+            if (lev1 && c1) {
+                real g[3] = {real(0), real(0), real(0)};
+                const int sc = (j + SA) % SA;
+#pragma unroll
+                for (int a = 0; a < ST::NH; ++a) {
+                    const int ex = ST::e(a, 0), es = dir * ST::e(a, 1);
+                    const real diff = A[(j + es + SA) % SA][x1 + ex + OA] - A[(j - es + SA) % SA][x1 - ex + OA];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int eq = ST::e(a, q);
+                        if (eq != 0) g[q] += real(ST::w(a) * eq) * diff;
+                    }
+                }
+                const real pre = G * (psi0 + A[sc][x1 + OA]);
+                const real Fv[3] = {pre * g[0], pre * g[1], pre * g[2]};
+                real(&fv)[Q] = F[u];
+                collide_d2q9<real, NOISE>(fv, rho0, Fv, lc, ac, z1);
+                const int sl = j & 3;
+                if (wb) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) B[sl][i][x1 + OB] = fv[i];
+                }
+                if (ib_lo >= 0) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) B[sl][i][ib_lo] = fv[i];
+                }
+                if (ib_hi >= 0) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) B[sl][i][ib_hi] = fv[i];
+                }
+            }
+            // ---- level 2: row l_{j-3-R} -> HBM --------------------------------
+            if (lev2 && !ewave) {
+                const int k = j - 3 - R;
+                real g[3] = {real(0), real(0), real(0)};
+#pragma unroll
+                for (int a = 0; a < ST::NH; ++a) {
+                    const int ex = ST::e(a, 0), es = dir * ST::e(a, 1);
+                    const real diff = Cs[(k + es + SC) % SC][x2 + ex + OC] - Cs[(k - es + SC) % SC][x2 - ex + OC];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int eq = ST::e(a, q);
+                        if (eq != 0) g[q] += real(ST::w(a) * eq) * diff;
+                    }
+                }
+                const real pre = G * (psi0 + Cs[k % SC][x2 + OC]);
+                const real Fv[3] = {pre * g[0], pre * g[1], pre * g[2]};
+                real(&fv)[Q] = G2[gs_use];
+                collide_d2q9<real, NOISE>(fv, rho0, Fv, lc, ac, z2);
+                const uint32_t so = uint32_t(wrap_row(lrow(k))) * pbytes + lane_store;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) bstore(dst, so, uint32_t(i) * pop_bytes, fv[i]);
+            }
+        }
+    }
+}
+
+template <class ST, typename real, bool NOISE, int TX>
+inline hipError_t launch_two(const StepLaunch &P, hipStream_t s) {
+    hipLaunchKernelGGL((k_step2<ST, real, NOISE, TX>), dim3(P.total_tiles), dim3(TX + 64), 0, s, P.reps,
+                       P.tile_begin, P.nrep, P.parity, P.step_base, P.step_off);
+    return hipGetLastError();
+}
+
+}  // namespace fsc

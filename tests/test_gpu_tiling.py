@@ -1,6 +1,8 @@
-"""Every compiled tile shape and marching length gives bit-identical
-populations (the per-node arithmetic does not depend on the tiling), on
-lattices with ragged tiles in every direction."""
+"""Every compiled tiling and marching length gives bit-identical populations
+(the per-node arithmetic does not depend on the tiling), on lattices with
+ragged tiles in every direction; the two-step kernel equals two single steps
+bit for bit, also across S(k) samples that split a pair, whole-row tiles,
+narrow lattices and an odd number of steps."""
 import numpy as np
 import pytest
 
@@ -14,6 +16,9 @@ CASES = [
     # D, (nz, ny, nx) or (ny, nx), stencil, precision
     (2, (70, 301), 4, "fp32"),
     (2, (53, 200), 8, "fp32"),
+    (2, (37, 128), 4, "fp32"),   # one whole-row tile of 128 (and of 256)
+    (2, (9, 6), 8, "fp32"),      # narrowest two-step width for E8 (2R + 2)
+    (2, (41, 256), 8, "fp32"),
     (3, (23, 45, 37), 4, "fp32"),
     (2, (40, 77), 8, "fp64"),
     (3, (12, 19, 21), 4, "fp64"),
@@ -37,23 +42,59 @@ def test_all_tilings_are_bit_identical(D, shape, stencil, precision):
         want = ref.get_populations()
     shapes = fsc.tile_shapes(D, stencil, precision)
     assert len(shapes) >= 1
-    for (tx, ty, pf) in shapes:
+    for (tx, ty, pf, steps) in shapes:
         for target in (1, 37, 1 << 20):  # longest march, a ragged one, one plane per block
             with fsc.Lattice(p) as lat:
                 lat.set_populations(f0, 5)
-                lat.set_tiling(tx, ty, pf, target)
+                lat.set_tiling(tx, ty, pf, steps, target)
                 t = lat.tiling
-                assert (t["tx"], t["ty"], t["pf"]) == (tx, ty, pf)
+                assert (t["tx"], t["ty"], t["pf"], t["steps"]) == (tx, ty, pf, steps)
                 lat.step(9)
                 got = lat.get_populations()
-            print(tx, ty, pf, target, t["blocks"], flush=True)
-            assert np.array_equal(got, want), (tx, ty, pf, target)
+            print(tx, ty, pf, steps, target, t["blocks"], flush=True)
+            assert np.array_equal(got, want), (tx, ty, pf, steps, target)
+
+
+@pytest.mark.parametrize("stencil", [4, 8])
+def test_two_step_runs_with_samples_equal_single_steps(stencil):
+    # graph chunks with S(k) samples every 6 steps (pairs) and every 5 steps
+    # (a single step before each sample), plus a remainder
+    p = _params(2, (48, 300), stencil, "fp32")
+    f0 = I.smooth_density_populations(9, (48, 300), 0.9, 0.05, 3, seed=4)
+    two = [s for s in fsc.tile_shapes(2, stencil, "fp32") if s[3] == 2]
+    assert two
+    for every, n in ((6, 61), (5, 47)):
+        with fsc.Lattice(p) as ref:
+            ref.set_populations(f0, 3)
+            ref.set_tiling(128, 1, 1, 1, 64)
+            ref.run(n, every)
+            want = ref.get_populations()
+            s_want, q_want, c_want = ref.read_sk()
+        for (tx, ty, pf, steps) in two:
+            with fsc.Lattice(p) as lat:
+                lat.set_populations(f0, 3)
+                lat.set_tiling(tx, ty, pf, steps, 64)
+                lat.run(n, every)
+                assert np.array_equal(lat.get_populations(), want), (tx, every)
+                s_got, q_got, c_got = lat.read_sk()
+                assert np.array_equal(c_got, c_want)
+                np.testing.assert_allclose(s_got, s_want, rtol=1e-12)
+                np.testing.assert_allclose(q_got, q_want, rtol=1e-12)
+
+
+def test_two_step_is_refused_on_narrow_lattices():
+    p = _params(2, (16, 5), 8, "fp32")  # 5 < 2R + 2 = 6
+    with fsc.Lattice(p) as lat:
+        with pytest.raises(fsc.FscError):
+            lat.set_tiling(128, 1, 0, 2, 100)
 
 
 def test_uncompiled_tiling_is_refused():
     p = _params(2, (32, 32), 4, "fp32")
     with fsc.Lattice(p) as lat:
         with pytest.raises(fsc.FscError):
-            lat.set_tiling(96, 1, 1, 100)
+            lat.set_tiling(96, 1, 1, 1, 100)
         with pytest.raises(fsc.FscError):
-            lat.set_tiling(128, 1, 1, 0)
+            lat.set_tiling(128, 1, 1, 1, 0)
+        with pytest.raises(fsc.FscError):
+            lat.set_tiling(128, 1, 1, 2, 100)  # no two-step kernel with prefetch depth 1
