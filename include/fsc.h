@@ -358,7 +358,9 @@ int fsc_ens_get_tiling(const fsc_ens *ens, int *out5);
  * 2D FP32 lattices: each launch advances two time steps with one read and
  * one write of the populations, keeping the intermediate state on chip; the
  * results equal two single steps bit for bit.  Runs then go in pairs of steps,
- * with single steps where an S(k) sample falls between two steps. */
+ * with single steps where an S(k) sample falls between two steps.  For these
+ * tilings the prefetch field selects the on-chip schedule (0: one barrier per
+ * row; 1: two barriers per row and 3/4 of the LDS). */
 int fsc_tile_shapes(int D, int stencil, int precision, int *out4, int max);
 
 /* Fixes the tiling instead of tuning it: one of the compiled tilings, and a

@@ -421,11 +421,24 @@ void build_desc(fsc_ens *e) {
         const int ns = r.p.D == 3 ? r.p.nz : r.p.ny;
         work += int64_t(tx) * ty * ns;
     }
-    // marching length: the shortest that gives at most about target_blocks
-    // workgroups (rounding towards fewer blocks, so that a target equal to
-    // the number resident at once leaves no partial second round); long
-    // marches keep the halo planes a small overhead
+    // marching length: the shortest that gives at most target_blocks
+    // workgroups (so that a target equal to the number resident at once
+    // leaves no partial second round; each replica's chunks are then evened
+    // out, which can only shorten them); long marches keep the halo planes a
+    // small overhead
+    auto blocks_for = [&](int h) {
+        int64_t n = 0;
+        for (auto &r : e->reps) {
+            const int tx = (r.p.nx + e->tile.tx - 1) / e->tile.tx;
+            const int ty = r.p.D == 3 ? (r.p.ny + e->tile.ty - 1) / e->tile.ty : 1;
+            const int ns = r.p.D == 3 ? r.p.nz : r.p.ny;
+            const int hh = std::min(h, ns);
+            n += int64_t(tx) * ty * ((ns + hh - 1) / hh);
+        }
+        return n;
+    };
     int H = int(std::min<int64_t>(256, std::max<int64_t>(1, (work + e->target_blocks - 1) / e->target_blocks)));
+    while (H < 256 && blocks_for(H) > e->target_blocks) ++H;
     int tile_begin = 0;
     for (auto &r : e->reps) {
         RepDesc d{};
@@ -606,8 +619,8 @@ int ens_autotune(fsc_ens *e) {
     // block counts of one round of resident workgroups (a multiple of the
     // 256 CUs: 1-8 per CU, depending on the kernel's LDS and registers) and
     // of several rounds
-    const int64_t targets[] = {256,  512,  768,  1024, 1280,  1536,  1792, 2048,
-                               2560, 3072, 4096, 6144, 8192, 12288, 16384};
+    const int64_t targets[] = {256,  512,  768,  1024, 1280, 1536, 1792,  2048,  2304,
+                               2560, 3072, 3584, 4096, 4608, 6144, 8192, 12288, 16384};
     hipEvent_t a, b;
     HIPCHK(e, hipEventCreate(&a));
     HIPCHK(e, hipEventCreate(&b));

@@ -4,12 +4,20 @@
 namespace fsc {
 
 hipError_t launch_step2_e8(const StepLaunch &P, hipStream_t s) {
+    // the prefetch field selects the LDS schedule: 0 one barrier per row
+    // (4-row f(t+1) ring), 1 two barriers per row (3-row ring, less LDS)
+    if (P.tile.pf != 0 && P.tile.pf != 1) return hipErrorInvalidValue;
+    const bool two = P.tile.pf == 1;
     if (P.tile.tx == 128)
-        return P.noise ? launch_two<StencilE8_2D, float, true, 128>(P, s)
-                       : launch_two<StencilE8_2D, float, false, 128>(P, s);
+        return P.noise ? (two ? launch_two<StencilE8_2D, float, true, 128, 2>(P, s)
+                              : launch_two<StencilE8_2D, float, true, 128, 1>(P, s))
+                       : (two ? launch_two<StencilE8_2D, float, false, 128, 2>(P, s)
+                              : launch_two<StencilE8_2D, float, false, 128, 1>(P, s));
     if (P.tile.tx == 256)
-        return P.noise ? launch_two<StencilE8_2D, float, true, 256>(P, s)
-                       : launch_two<StencilE8_2D, float, false, 256>(P, s);
+        return P.noise ? (two ? launch_two<StencilE8_2D, float, true, 256, 2>(P, s)
+                              : launch_two<StencilE8_2D, float, true, 256, 1>(P, s))
+                       : (two ? launch_two<StencilE8_2D, float, false, 256, 2>(P, s)
+                              : launch_two<StencilE8_2D, float, false, 256, 1>(P, s));
     return hipErrorInvalidValue;
 }
 

@@ -26,29 +26,34 @@
 // chunk as in the single-step kernel): level 1 runs over the rows
 // l_k = o_{k-R-1}, k = 0..H+2R+1, with the pulled rows of f(t) in a register
 // ring of R+1 rows and psi(t) in an LDS ring of 2R+2 rows (A); f(t+1) goes to
-// an LDS ring of 4 rows (B).  Iteration j, one barrier:
-//   before the barrier: loads of level-1 row l_{j+R}; the noise of both levels;
-//     level 2 pulls f(t+1) of row l_{j-3} from B (rows written at least two
-//     iterations ago) into a register ring of R+1 rows and writes its
-//     psi(t+1) into an LDS ring of 2R+2 rows (C); psi(t) of row l_{j+R} -> A;
-//   after the barrier: level-1 force and collision of row l_j -> B; level-2
-//     force and collision of row l_{j-3-R} -> HBM.
-// The ring sizes make one barrier per iteration sufficient: no slot is
-// rewritten while a slower wave of the previous iteration may still read it.
+// an LDS ring (B).  Two schedules (template BARS):
+//   one barrier per iteration j, B of 4 rows:
+//     before the barrier: loads of level-1 row l_{j+R}; the noise of both
+//       levels; level 2 pulls f(t+1) of row l_{j-3} from B (rows written at
+//       least two iterations ago) into a register ring of R+1 rows and writes
+//       its psi(t+1) into an LDS ring of 2R+2 rows (C); psi(t) of l_{j+R} -> A;
+//     after the barrier: level-1 force and collision of row l_j -> B; level-2
+//       force and collision of row l_{j-3-R} -> HBM;
+//   two barriers per iteration, B of 3 rows (less LDS, so more workgroups
+//     per CU): loads, noise, psi(t) -> A | barrier | level 1 of row l_j -> B |
+//     barrier | level-2 collision of row l_{j-2-R}, then the pull and
+//     psi(t+1) of row l_{j-1}.
+// The ring sizes are the smallest for which no slot is rewritten while a
+// slower wave may still read it.
 #pragma once
 
 #include "fsc_step_kernel.h"
 
 namespace fsc {
 
-template <class ST, typename real, bool NOISE, int TX>
+template <class ST, typename real, bool NOISE, int TX, int BARS>
 __global__ void __launch_bounds__(TX + 64)
     k_step2(const RepDesc *__restrict__ reps, const int *__restrict__ tile_begin, int nrep,
             int parity, const uint64_t *__restrict__ step_base, uint32_t step_off) {
     using L = D2Q9;
     constexpr int Q = 9, R = ST::R, NN = L::NNORM;
     constexpr int NR = R + 1;                       // register rings (rows)
-    constexpr int SA = 2 * R + 2, SB = 4, SC = 2 * R + 2;
+    constexpr int SA = 2 * R + 2, SB = BARS == 1 ? 4 : 3, SC = 2 * R + 2;
     constexpr int OA = 2 * R + 1, OB = R + 1, OC = R;  // column of offset 0
     constexpr int WA = TX + 4 * R + 2, WB = TX + 2 * R + 2, WC = TX + 2 * R;
     constexpr uint32_t ES = sizeof(real);
@@ -168,7 +173,6 @@ __global__ void __launch_bounds__(TX + 64)
     const int first = dir > 0 ? s_begin : s_end - 1;       // o_0
     auto lrow = [&](int k) { return first + dir * (k - R - 1); };  // lattice row of l_k
     const int H1 = H + 2 * R + 2;                          // level-1 rows
-    const int J = H1 + 2;                                  // iterations
 
     auto put_a = [&](int k, real v) {  // psi(t) of l_k
         const int sl = (k + SA) % SA;
@@ -200,18 +204,97 @@ __global__ void __launch_bounds__(TX + 64)
 
     const uint32_t lane_store = uint32_t(x0 + x2) * ES;  // tile lanes only store
 
+    // ---- the three pieces of an iteration ---------------------------------------
+    // level 2: pull f(t+1) of l_k from B into the register ring, psi(t+1) -> C
+    auto psi_stage = [&](int k, int gs) {
+        const int sb[3] = {(k + dir) % SB, k % SB, (k - dir + SB) % SB};  // c_y + 1 -> row - c_y
+        real(&g2)[Q] = G2[gs];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g2[i] = B[sb[L::c(i, 1) + 1]][i][x2 - L::c(i, 0) + OB];
+        const real v = dpsi_of(g2);
+        const int sl = k % SC;
+        if (wc) Cs[sl][x2 + OC] = v;
+        if (ic_lo >= 0) Cs[sl][ic_lo] = v;
+        if (ic_hi >= 0) Cs[sl][ic_hi] = v;
+    };
+    // level 1: force and collision of l_j (pulled populations in F[fs]) -> B
+    auto level1 = [&](int j, int fs, const real (&z)[NN]) {
+        real g[3] = {real(0), real(0), real(0)};
+#pragma unroll
+        for (int a = 0; a < ST::NH; ++a) {
+            const int ex = ST::e(a, 0), es = dir * ST::e(a, 1);
+            const real diff = A[(j + es + SA) % SA][x1 + ex + OA] - A[(j - es + SA) % SA][x1 - ex + OA];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int eq = ST::e(a, q);
+                if (eq != 0) g[q] += real(ST::w(a) * eq) * diff;
+            }
+        }
+        const real pre = G * (psi0 + A[(j + SA) % SA][x1 + OA]);
+        const real Fv[3] = {pre * g[0], pre * g[1], pre * g[2]};
+        real(&fv)[Q] = F[fs];
+        collide_d2q9<real, NOISE>(fv, rho0, Fv, lc, ac, z);
+        const int sl = j % SB;
+        if (wb) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) B[sl][i][x1 + OB] = fv[i];
+        }
+        if (ib_lo >= 0) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) B[sl][i][ib_lo] = fv[i];
+        }
+        if (ib_hi >= 0) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) B[sl][i][ib_hi] = fv[i];
+        }
+    };
+    // level 2: force and collision of l_k (pulled populations in G2[gs]) -> HBM
+    auto level2 = [&](int k, int gs, const real (&z)[NN]) {
+        real g[3] = {real(0), real(0), real(0)};
+#pragma unroll
+        for (int a = 0; a < ST::NH; ++a) {
+            const int ex = ST::e(a, 0), es = dir * ST::e(a, 1);
+            const real diff = Cs[(k + es + SC) % SC][x2 + ex + OC] - Cs[(k - es + SC) % SC][x2 - ex + OC];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int eq = ST::e(a, q);
+                if (eq != 0) g[q] += real(ST::w(a) * eq) * diff;
+            }
+        }
+        const real pre = G * (psi0 + Cs[k % SC][x2 + OC]);
+        const real Fv[3] = {pre * g[0], pre * g[1], pre * g[2]};
+        real(&fv)[Q] = G2[gs];
+        collide_d2q9<real, NOISE>(fv, rho0, Fv, lc, ac, z);
+        const uint32_t so = uint32_t(wrap_row(lrow(k))) * pbytes + lane_store;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) bstore(dst, so, uint32_t(i) * pop_bytes, fv[i]);
+    };
+
+    // Level 2 trails level 1.  Its pull (and psi(t+1)) of iteration j is row
+    // kp = j - LAG: with one barrier per iteration it can only read B rows
+    // written two iterations ago (LAG = 3), with two barriers also the row
+    // written before the second barrier (LAG = 1).  Its collision is row
+    // km = kp - LAG2, whose psi(t+1) stencil reaches km + R: with one barrier
+    // that row is written before the barrier of the same iteration
+    // (LAG2 = R); with two barriers it was written one iteration earlier
+    // (LAG2 = R + 1, so the collision can run before this iteration's pull).
+    constexpr int LAG = BARS == 1 ? 3 : 1;
+    constexpr int LAG2 = BARS == 1 ? R : R + 1;
+    const int J = H + R + LAG + LAG2 + 1;  // iterations: the last one collides km = H + R
     for (int j0 = 0; j0 < J; j0 += NR) {
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
             const int j = j0 + u;
             if (j >= J) break;
+            const int kp = j - LAG;       // psi(t+1) row of this iteration
+            const int km = kp - LAG2;     // level-2 output row of this iteration
             const bool lev1 = j < H1;
-            const bool psi2 = j >= 4 && j <= H1 + 1;
-            const bool lev2 = j >= 2 * R + 4 && j <= H1 + 1;
+            const bool psi2 = kp >= 1 && kp <= H1 - 2;
+            const bool lev2 = km >= R + 1 && km <= H1 - 2 - R;
             // register-ring slots (constants once the loop over u is unrolled)
-            const int fs_new = (u + R) % NR;                  // row l_{j+R}
-            const int gs_new = ((u - 3) % NR + NR) % NR;      // row l_{j-3}
-            const int gs_use = ((u - 3 - R) % NR + NR) % NR;  // row l_{j-3-R}
+            const int fs_new = (u + R) % NR;                     // row l_{j+R}
+            const int gs_new = ((u - LAG) % NR + NR) % NR;       // row l_kp
+            const int gs_use = ((u - LAG - LAG2) % NR + NR) % NR;  // row l_km
 
             // loads of level-1 row l_{j+R} (consumed by its psi below and by
             // its collision R iterations later)
@@ -222,93 +305,37 @@ __global__ void __launch_bounds__(TX + 64)
                 if (lev1 && !eidle) node_normals<L, real>(uint32_t(gx1 + nx * wrap_row(lrow(j))), step1,
                                                          d.seed_hi, d.key0, d.key1, z1);
                 if (lev2 && !ewave)
-                    node_normals<L, real>(uint32_t(gx2 + nx * wrap_row(lrow(j - 3 - R))), step2,
-                                          d.seed_hi, d.key0, d.key1, z2);
+                    node_normals<L, real>(uint32_t(gx2 + nx * wrap_row(lrow(km))), step2, d.seed_hi,
+                                          d.key0, d.key1, z2);
             }
             if constexpr (!NOISE) {
 #pragma unroll
                 for (int k = 0; k < NN; ++k) z1[k] = z2[k] = real(0);
             }
-            // level 2: pull f(t+1) of l_{j-3} from B, its psi(t+1) -> C.  The
-            // rings are indexed by march position, so lattice row offset dy is
-            // position offset dir * dy.
-            if (psi2 && p2) {
-                const int k = j - 3;
-                const int sb[3] = {(k + dir) & 3, k & 3, (k - dir) & 3};  // c_y + 1 -> row - c_y
-                real(&g2)[Q] = G2[gs_new];
-#pragma unroll
-                for (int i = 0; i < Q; ++i) g2[i] = B[sb[L::c(i, 1) + 1]][i][x2 - L::c(i, 0) + OB];
-                const real v = dpsi_of(g2);
-                const int sl = k % SC;
-                if (wc) Cs[sl][x2 + OC] = v;
-                if (ic_lo >= 0) Cs[sl][ic_lo] = v;
-                if (ic_hi >= 0) Cs[sl][ic_hi] = v;
-            }
-            // psi(t) of l_{j+R} -> A
-            if (lev1) put_a(j + R, eidle ? real(0) : dpsi_of(F[fs_new]));
-            __syncthreads();
-
-            // ---- level 1: row l_j -> B --------------------------------------
-            if (lev1 && c1) {
-                real g[3] = {real(0), real(0), real(0)};
-                const int sc = (j + SA) % SA;
-#pragma unroll
-                for (int a = 0; a < ST::NH; ++a) {
-                    const int ex = ST::e(a, 0), es = dir * ST::e(a, 1);
-                    const real diff = A[(j + es + SA) % SA][x1 + ex + OA] - A[(j - es + SA) % SA][x1 - ex + OA];
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const int eq = ST::e(a, q);
-                        if (eq != 0) g[q] += real(ST::w(a) * eq) * diff;
-                    }
-                }
-                const real pre = G * (psi0 + A[sc][x1 + OA]);
-                const real Fv[3] = {pre * g[0], pre * g[1], pre * g[2]};
-                real(&fv)[Q] = F[u];
-                collide_d2q9<real, NOISE>(fv, rho0, Fv, lc, ac, z1);
-                const int sl = j & 3;
-                if (wb) {
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) B[sl][i][x1 + OB] = fv[i];
-                }
-                if (ib_lo >= 0) {
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) B[sl][i][ib_lo] = fv[i];
-                }
-                if (ib_hi >= 0) {
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) B[sl][i][ib_hi] = fv[i];
-                }
-            }
-            // ---- level 2: row l_{j-3-R} -> HBM --------------------------------
-            if (lev2 && !ewave) {
-                const int k = j - 3 - R;
-                real g[3] = {real(0), real(0), real(0)};
-#pragma unroll
-                for (int a = 0; a < ST::NH; ++a) {
-                    const int ex = ST::e(a, 0), es = dir * ST::e(a, 1);
-                    const real diff = Cs[(k + es + SC) % SC][x2 + ex + OC] - Cs[(k - es + SC) % SC][x2 - ex + OC];
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const int eq = ST::e(a, q);
-                        if (eq != 0) g[q] += real(ST::w(a) * eq) * diff;
-                    }
-                }
-                const real pre = G * (psi0 + Cs[k % SC][x2 + OC]);
-                const real Fv[3] = {pre * g[0], pre * g[1], pre * g[2]};
-                real(&fv)[Q] = G2[gs_use];
-                collide_d2q9<real, NOISE>(fv, rho0, Fv, lc, ac, z2);
-                const uint32_t so = uint32_t(wrap_row(lrow(k))) * pbytes + lane_store;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) bstore(dst, so, uint32_t(i) * pop_bytes, fv[i]);
+            if constexpr (BARS == 1) {
+                // B rows kp - 1 .. kp + 1 were written at least two iterations ago
+                if (psi2 && p2) psi_stage(kp, gs_new);
+                if (lev1) put_a(j + R, eidle ? real(0) : dpsi_of(F[fs_new]));
+                __syncthreads();
+                if (lev1 && c1) level1(j, u, z1);
+                if (lev2 && !ewave) level2(km, gs_use, z2);
+            } else {
+                if (lev1) put_a(j + R, eidle ? real(0) : dpsi_of(F[fs_new]));
+                __syncthreads();
+                if (lev1 && c1) level1(j, u, z1);
+                __syncthreads();
+                // the collision frees the ring slot that the pull then refills
+                // (gs_use == gs_new, as kp - km = R + 1)
+                if (lev2 && !ewave) level2(km, gs_use, z2);
+                if (psi2 && p2) psi_stage(kp, gs_new);
             }
         }
     }
 }
 
-template <class ST, typename real, bool NOISE, int TX>
+template <class ST, typename real, bool NOISE, int TX, int BARS>
 inline hipError_t launch_two(const StepLaunch &P, hipStream_t s) {
-    hipLaunchKernelGGL((k_step2<ST, real, NOISE, TX>), dim3(P.total_tiles), dim3(TX + 64), 0, s, P.reps,
+    hipLaunchKernelGGL((k_step2<ST, real, NOISE, TX, BARS>), dim3(P.total_tiles), dim3(TX + 64), 0, s, P.reps,
                        P.tile_begin, P.nrep, P.parity, P.step_base, P.step_off);
     return hipGetLastError();
 }

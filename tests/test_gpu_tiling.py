@@ -97,4 +97,4 @@ def test_uncompiled_tiling_is_refused():
         with pytest.raises(fsc.FscError):
             lat.set_tiling(128, 1, 1, 1, 0)
         with pytest.raises(fsc.FscError):
-            lat.set_tiling(128, 1, 1, 2, 100)  # no two-step kernel with prefetch depth 1
+            lat.set_tiling(128, 1, 2, 2, 100)  # no two-step kernel with schedule 2
