@@ -48,3 +48,22 @@ def test_creation_errors_are_reported_without_touching_the_device():
         fsc.Lattice(fsc.make_params(D=4))
     assert ei.value.code == -1
     assert "D must be" in str(ei.value)
+
+
+def test_tiling_table_is_host_only_and_consistent():
+    # fsc_tile_shapes touches no device: the compiled tilings per lattice kind
+    import paper_2212_07848_amd as fsc
+    for D, st, prec in ((2, 4, "fp32"), (2, 8, "fp32"), (3, 4, "fp32"), (2, 4, "fp64"), (3, 4, "fp64")):
+        shapes = fsc.tile_shapes(D, st, prec)
+        assert shapes and len(set(shapes)) == len(shapes)
+        for tx, ty, pf, steps in shapes:
+            assert tx % 32 == 0 and tx * ty <= 512 and steps in (1, 2)
+            assert (ty == 1) == (D == 2)
+        two = [s for s in shapes if s[3] == 2]
+        # the temporally blocked kernel exists for 2D FP32 only, in both LDS schedules
+        assert bool(two) == (D == 2 and prec == "fp32")
+        if two:
+            assert {s[2] for s in two} == {0, 1} and {s[0] for s in two} == {128, 256}
+        assert shapes[0][3] == 1  # the default is a single-step tiling
+    with pytest.raises(fsc.FscError):
+        fsc.tile_shapes(3, 8, "fp32")
