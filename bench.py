@@ -55,8 +55,8 @@ def bytes_per_lup(D: int, precision: str) -> int:
 def kernel_name(stencil: str, noise: bool, tiling: dict) -> str:
     """Name of the step kernel a tiling launches (as rocprofv3 reports it)."""
     n = "true" if noise else "false"
-    if tiling.get("steps", 1) == 2:
-        return f"k_step2<{stencil}, float, {n}, {tiling['tx']}>"
+    if tiling.get("steps", 1) == 2:  # prefetch field 0/1: one or two barriers per row
+        return f"k_step2<{stencil}, float, {n}, {tiling['tx']}, {tiling['pf'] + 1}>"
     return f"k_step<D2Q9, {stencil}, float, {n}, {tiling['tx']}, {tiling['ty']}, {tiling['pf']}>"
 
 

@@ -636,12 +636,18 @@ int ens_autotune(fsc_ens *e) {
             if (rc) return rc;
             const StepLaunch L = make_launch(e, parity, 0);
             for (int k = 0; k < 2; ++k) HIPCHK(e, launch_step(L, e->stream));
-            HIPCHK(e, hipEventRecord(a, e->stream));
-            for (int k = 0; k < 8; ++k) HIPCHK(e, launch_step(L, e->stream));
-            HIPCHK(e, hipEventRecord(b, e->stream));
-            HIPCHK(e, hipEventSynchronize(b));
-            float ms = 0.f;
-            HIPCHK(e, hipEventElapsedTime(&ms, a, b));
+            // the fastest of three windows of three launches (robust to a
+            // transient slowdown of one window)
+            float ms = 1e30f;
+            for (int w = 0; w < 3; ++w) {
+                HIPCHK(e, hipEventRecord(a, e->stream));
+                for (int k = 0; k < 3; ++k) HIPCHK(e, launch_step(L, e->stream));
+                HIPCHK(e, hipEventRecord(b, e->stream));
+                HIPCHK(e, hipEventSynchronize(b));
+                float t = 0.f;
+                HIPCHK(e, hipEventElapsedTime(&t, a, b));
+                ms = std::min(ms, t);
+            }
             ms /= float(shapes[si].steps);  // per step
             if (ms < best) {
                 best = ms;

@@ -37,6 +37,7 @@ def run_quench(torch, seeds, n=1024, factor=8, stride=256, n_snap=80, seed_base=
     stream = torch.cuda.Stream()
     ens = F.Ensemble(plist, stream=stream)
     ens.init_uniform()
+    ens.autotune()  # outside the timed strides
     m = n // factor
     out = torch.zeros((n_snap + 1, len(seeds), m, m), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()  # the lattice writes on its own stream

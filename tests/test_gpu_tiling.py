@@ -98,3 +98,36 @@ def test_uncompiled_tiling_is_refused():
             lat.set_tiling(128, 1, 1, 1, 0)
         with pytest.raises(fsc.FscError):
             lat.set_tiling(128, 1, 2, 2, 100)  # no two-step kernel with schedule 2
+
+
+@pytest.mark.parametrize("stencil", [4, 8])
+def test_two_step_in_a_mixed_ensemble_equals_single_steps(stencil):
+    # whole-row tiles, several tiles per row, ragged widths and heights in one
+    # launch, uneven parameters per replica, S(k) samples splitting pairs
+    shapes = [(40, 128), (33, 300), (20, 256), (17, 77), (9, 6)]
+    plist = [fsc.make_params(D=2, nx=nx, ny=ny, stencil=stencil, precision="fp32",
+                             T_hat=0.75 + 0.05 * k, rho0=0.6 + 0.2 * k, kBT=1e-4 * (k + 1),
+                             seed=21, replica=k)
+             for k, (ny, nx) in enumerate(shapes)]
+    f0 = [I.smooth_density_populations(9, sh, p.rho0, 0.05, 3, seed=30 + k)
+          for k, (sh, p) in enumerate(zip(shapes, plist))]
+
+    def run(tiling):
+        ens = fsc.Ensemble(plist)
+        ens.init_uniform()
+        for k in range(len(shapes)):
+            ens.set_populations(k, f0[k])
+        ens.set_tiling(*tiling)
+        ens.run(37, 5)
+        out = [ens.get_populations(k) for k in range(len(shapes))]
+        ens.close()
+        return out
+
+    want = run((128, 1, 1, 1, 64))
+    for (tx, ty, pf, steps) in fsc.tile_shapes(2, stencil, "fp32"):
+        if steps != 2:
+            continue
+        for target in (1, 64, 1 << 20):
+            got = run((tx, ty, pf, steps, target))
+            for k in range(len(shapes)):
+                assert np.array_equal(got[k], want[k]), (tx, pf, target, k)
