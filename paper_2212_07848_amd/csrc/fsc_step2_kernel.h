@@ -38,8 +38,8 @@
 //     per CU): loads, noise, psi(t) -> A | barrier | level 1 of row l_j -> B |
 //     barrier | level-2 collision of row l_{j-2-R}, then the pull and
 //     psi(t+1) of row l_{j-1}.
-// The ring sizes are the smallest for which no slot is rewritten while a
-// slower wave may still read it.
+// The ring sizes make sure that no slot is rewritten while a slower wave may
+// still read it (B and C are the smallest that do).
 #pragma once
 
 #include "fsc_step_kernel.h"

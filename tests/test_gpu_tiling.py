@@ -131,3 +131,50 @@ def test_two_step_in_a_mixed_ensemble_equals_single_steps(stencil):
             got = run((tx, ty, pf, steps, target))
             for k in range(len(shapes)):
                 assert np.array_equal(got[k], want[k]), (tx, pf, target, k)
+
+
+@pytest.mark.parametrize("stencil", [4, 8])
+def test_noise_free_two_step_equals_single_steps(stencil):
+    p = fsc.make_params(D=2, nx=300, ny=41, stencil=stencil, precision="fp32", T_hat=0.8,
+                        rho0=0.9, kBT=0.0, seed=13)
+    f0 = I.smooth_density_populations(9, (41, 300), 0.9, 0.05, 3, seed=6)
+    with fsc.Lattice(p) as ref:
+        ref.set_populations(f0, 0)
+        ref.set_tiling(128, 1, 1, 1, 64)
+        ref.step(13)
+        want = ref.get_populations()
+    for (tx, ty, pf, steps) in fsc.tile_shapes(2, stencil, "fp32"):
+        if steps == 2:
+            with fsc.Lattice(p) as lat:
+                lat.set_populations(f0, 0)
+                lat.set_tiling(tx, ty, pf, steps, 64)
+                lat.step(13)
+                assert np.array_equal(lat.get_populations(), want), (tx, pf)
+
+
+def test_two_step_checkpoint_resumes_bit_exactly(tmp_path):
+    # the state sits in either buffer after an odd number of launches; a
+    # checkpoint written there resumes into any tiling
+    plist = [fsc.make_params(D=2, nx=nx, ny=ny, stencil=4, precision="fp32", T_hat=0.8,
+                             rho0=0.7, kBT=1e-4, seed=3, replica=k)
+             for k, (ny, nx) in enumerate([(30, 256), (25, 300)])]
+    path = str(tmp_path / "two.ckpt")
+    a = fsc.Ensemble(plist)
+    a.init_uniform()
+    a.set_tiling(256, 1, 0, 2, 64)
+    a.run(61, 10)
+    a.save(path)
+    a.run(40, 10)
+    b = fsc.Ensemble(plist)
+    b.load(path)
+    b.set_tiling(128, 1, 1, 1, 64)  # resume with single steps
+    b.run(40, 10)
+    c = fsc.Ensemble(plist)
+    c.load(path)
+    c.set_tiling(128, 1, 1, 2, 64)  # and with the other two-step schedule
+    c.run(40, 10)
+    for k in range(2):
+        assert np.array_equal(a.get_populations(k), b.get_populations(k))
+        assert np.array_equal(a.get_populations(k), c.get_populations(k))
+    for e in (a, b, c):
+        e.close()
