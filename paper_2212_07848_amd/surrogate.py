@@ -61,28 +61,29 @@ def run_quench(torch, seeds, n=1024, factor=8, stride=256, n_snap=80, seed_base=
     return out, t_lbm
 
 
-def _batches(torch, snaps, t_first, batch, gen, m):
-    """Random (prev, cur, next, next2) stacks [batch][m][m] from the snapshot
-    tensor [K][R][m][m], with a common random periodic shift and, on every
-    other call, a transpose (the lattice's symmetries)."""
+def _batches(torch, snaps, t_first, batch, gen, m, ahead=2):
+    """Random (prev, cur, next_1, .., next_ahead) stacks [batch][m][m] from the
+    snapshot tensor [K][R][m][m] (next_j is j strides after cur), with a
+    common random periodic shift and, on every other call, a transpose (the
+    lattice's symmetries)."""
     K, R = snaps.shape[:2]
-    ti = torch.randint(t_first, K - 2, (batch,), device="cuda", generator=gen)
+    ti = torch.randint(t_first, K - ahead, (batch,), device="cuda", generator=gen)
     ri = torch.randint(0, R, (batch,), device="cuda", generator=gen)
     sh = torch.randint(0, m, (2,), device="cuda", generator=gen).tolist()
     out = []
-    for dt in (-1, 0, 1, 2):
+    for dt in range(-1, ahead + 1):
         out.append(torch.roll(snaps[ti + dt, ri], shifts=sh, dims=(1, 2)))
     return out
 
 
 def train(torch, snaps, t_first, layers=7, in_ch=2, steps=6000, batch=32, lr=1e-3, push=0.5,
-          seed=0, log=None):
+          push_depth=1, seed=0, log=None):
     """Trains on snapshot pairs (k, k+1), k >= t_first, with the previous
     snapshot as second input channel.  After the first tenth of the steps, a
-    fraction `push` of every batch starts from the network's own one-stride
-    prediction (no gradient through it) and is trained against the snapshot
-    two strides ahead: the network learns to correct the errors its rollouts
-    make."""
+    fraction `push` of every batch starts from the network's own rollout of
+    d = 1..push_depth strides (no gradient through it; the pushed rows are
+    split evenly over d) and is trained against the snapshot d + 1 strides
+    ahead: the network learns to correct the errors its rollouts make."""
     K, R, m, _ = snaps.shape
     mean = 1.0
     in_scale = float((snaps[t_first:] - mean).std().item())
@@ -95,18 +96,26 @@ def train(torch, snaps, t_first, layers=7, in_ch=2, steps=6000, batch=32, lr=1e-
     prev_b, cur_b, tgt_b, pred_b = bufs
     losses = []
     n_push = int(round(push * batch))
+    # rows [edges[d-1], edges[d]) of the batch are pushed d strides
+    edges = [round(n_push * d / push_depth) for d in range(push_depth + 1)]
     for it in range(steps):
-        prev, cur, nxt, nxt2 = _batches(torch, snaps, t_first, batch, gen, m)
+        prev, cur, *nxt = _batches(torch, snaps, t_first, batch, gen, m, ahead=push_depth + 1)
         if it % 2:
-            prev, cur, nxt, nxt2 = (v.transpose(1, 2) for v in (prev, cur, nxt, nxt2))
+            prev, cur = prev.transpose(1, 2), cur.transpose(1, 2)
+            nxt = [v.transpose(1, 2) for v in nxt]
         prev_b.copy_(prev)
         cur_b.copy_(cur)
-        tgt_b.copy_(nxt)
+        tgt_b.copy_(nxt[0])
         if n_push and it >= steps // 10:
-            sur.forward(prev_b[:n_push], cur_b[:n_push], pred_b[:n_push], n_push)
-            prev_b[:n_push].copy_(cur_b[:n_push])
-            cur_b[:n_push].copy_(pred_b[:n_push])
-            tgt_b[:n_push].copy_(nxt2[:n_push])
+            for d in range(1, push_depth + 1):
+                a, b = edges[d - 1], edges[d]
+                if b <= a:
+                    continue
+                for _ in range(d):  # roll rows a..b-1 out d strides
+                    sur.forward(prev_b[a:b], cur_b[a:b], pred_b[a:b], b - a)
+                    prev_b[a:b].copy_(cur_b[a:b])
+                    cur_b[a:b].copy_(pred_b[a:b])
+                tgt_b[a:b].copy_(nxt[d][a:b])
         rate = lr * 0.5 * (1 + math.cos(math.pi * it / steps))
         loss = sur.train_step(prev_b, cur_b, tgt_b, batch, max(rate, 1e-5),
                               want_loss=(it % 100 == 0))
@@ -116,6 +125,7 @@ def train(torch, snaps, t_first, layers=7, in_ch=2, steps=6000, batch=32, lr=1e-
                 log(f"step {it} loss {loss:.4e}")
     return sur, dict(mean=mean, in_scale=in_scale, out_scale=out_scale, losses=losses,
                      layers=layers, in_ch=in_ch, steps=steps, batch=batch, lr=lr, push=push,
+                     push_depth=push_depth,
                      pairs=int((K - 2 - t_first) * R))
 
 
@@ -219,6 +229,7 @@ def main(argv=None):
     ap.add_argument("--t-first", type=int, default=4)
     ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--layers", type=int, nargs="+", default=[7, 5])
+    ap.add_argument("--push-depth", type=int, default=1)
     ap.add_argument("--save", action="store_true", help="store the first model in the package")
     ap.add_argument("--out", default=os.path.join(os.getcwd(), "surrogate_eval.json"))
     a = ap.parse_args(argv)
@@ -231,7 +242,7 @@ def main(argv=None):
     for k, layers in enumerate(a.layers):
         t1 = time.perf_counter()
         sur, meta = train(torch, snaps, a.t_first, layers=layers, steps=a.steps,
-                          log=lambda s: print(s, flush=True))
+                          push_depth=a.push_depth, log=lambda s: print(s, flush=True))
         meta["train_seconds"] = time.perf_counter() - t1
         ev = evaluate(torch, sur, range(a.eval_seeds), n=a.n, snaps=ev_snaps, t_lbm=ev_t)
         meta.update(dict(train_seeds=a.train_seeds, snaps=a.snaps, t_first=a.t_first, n=a.n,
