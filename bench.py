@@ -221,6 +221,74 @@ def summarize_trace(trace_dir: str, log_path: str, out_path: str):
         fh.write("\n".join(lines) + "\n")
 
 
+SUR_TRACE_ARGS = "--steps 40 --warmup 8 --kernel-steps 16 --no-cpu-baseline --no-extra"
+BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak of the part
+
+
+def summarize_surrogate_trace(trace_dir: str, log_path: str, out_path: str):
+    """Markdown summary of the surrogate's kernels in a `rocprofv3
+    --kernel-trace --stats --output-format csv` run of this script: per
+    kernel, the dispatches and mean duration; for the 32 -> 32 matrix-core
+    layer (k_mid) the achieved BF16 rate per launch from the rollout's batch
+    (the bench's held-out seeds, 128^2 pixels each)."""
+    import csv
+    import re
+    from collections import defaultdict
+    bench = None
+    with open(log_path) as fh:
+        for line in fh:
+            if line.startswith('{"metric"'):
+                bench = json.loads(line)
+    per = defaultdict(list)
+    with open(os.path.join(trace_dir, "run_kernel_trace.csv")) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"]
+            m = re.match(r"_ZN3fsc(\d+)(\w+)", name)  # names rocprofv3 leaves mangled
+            if m:
+                ident = m.group(2)[:int(m.group(1))]
+                rest = m.group(2)[int(m.group(1)):]
+                flag = {"ILb0E": "<false>", "ILb1E": "<true>"}.get(rest[:5], "")
+                short = ident + flag
+            elif "fsc::k_" in name:
+                short = name.replace("void ", "").split("(")[0].replace("fsc::", "")
+            else:
+                continue
+            if short.split("<")[0] in ("k_input", "k_first", "k_mid", "k_last", "k_img_part",
+                                       "k_img_total", "k_pred"):
+                per[short].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    lines = ["# Surrogate kernels: rocprofv3 kernel trace of bench.py (rollout part)", "",
+             "Command (repository root as working directory, TMPDIR=/tmp):", "",
+             f"    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
+             f"python3 bench.py {SUR_TRACE_ARGS} > <log>",
+             f"    python3 bench.py --summarize-surrogate-trace <dir> <log> <this file>", ""]
+    batch = None
+    if bench and "surrogate" in bench:
+        su = bench["surrogate"]
+        batch = su["held_out_seeds"]
+        lines += [f"- model: {su['model']}",
+                  f"- rollout of {batch} images of 128^2 pixels: {su['surrogate_s_per_stride'] * 1e3:.3f} ms "
+                  f"per stride against {su['lattice_s_per_stride'] * 1e3:.1f} ms of lattice "
+                  f"(speedup {su['speedup_at_5pct']}x), {su['bf16_tflops_in_rollout']} TFLOP/s "
+                  f"BF16 over the whole pass", ""]
+    lines += ["| kernel | dispatches | mean us | note |", "|---|---|---|---|"]
+    for name, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        mean = sum(v) / len(v)
+        note = ""
+        if name.startswith("k_mid") and batch:
+            flops = 2 * 9 * 32 * 32 * batch * 128 * 128
+            tf = flops / (mean * 1e-9) / 1e12
+            note = (f"{flops / 1e9:.2f} GFLOP per launch: {tf:.1f} TFLOP/s, "
+                    f"{tf / BF16_PEAK_TFLOPS * 100:.1f}% of the BF16 peak")
+        lines.append(f"| `{name}` | {len(v)} | {mean / 1e3:.2f} | {note} |")
+    total = sum(sum(v) / len(v) * (len(v) // max(1, len(per.get("k_pred", [1])))) for v in per.values())
+    lines += ["", f"Kernel time per pass (sum of the means, counting each kernel's launches per "
+              f"pass): {total / 1e3:.1f} us.  Each launch is small (8 images of 128^2), so the "
+              f"rollout is bound by launch latency and the gaps between its kernels, not by the "
+              f"matrix cores."]
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def time_steps(obj, steps: int, stream, torch):
     """Average duration of one fused step launch (HIP events on the library's
     stream), over `steps` launches without measurement."""
@@ -385,9 +453,14 @@ def main():
                     help="write profiles/step_traffic.json from three rocprofv3 counter runs")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "LOG", "OUT_MD"),
                     help="write a markdown summary of a rocprofv3 kernel-trace run")
+    ap.add_argument("--summarize-surrogate-trace", nargs=3, metavar=("TRACE_DIR", "LOG", "OUT_MD"),
+                    help="write a markdown summary of the surrogate kernels of a kernel-trace run")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_surrogate_trace:
+        summarize_surrogate_trace(*args.summarize_surrogate_trace)
         return
     if args.ingest_pmc:
         doc = ingest_pmc(*args.ingest_pmc, os.path.join(ROOT, "profiles", "step_traffic.json"))

@@ -78,10 +78,15 @@ __global__ void __launch_bounds__(256) k_input(const float *__restrict__ cur,
 }
 
 // ---------------------------------------------------------------------------
-// Layer 0 (K -> C) forward, FP32: one thread per pixel.
+// Layer 0 (K -> C) forward, FP32: one thread per pixel.  ZOUT keeps the FP32
+// pre-activations for the backward pass (training); FUSED forms the network
+// input from the fields on the fly (inference: no X buffer, one launch less).
+// The 32 BF16 activations of a pixel go out as four 16-byte stores.
 // ---------------------------------------------------------------------------
-template <int K>
-__global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, int B, int H, int W,
+template <int K, bool ZOUT, bool FUSED>
+__global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, const float *__restrict__ cur,
+                                               const float *__restrict__ prev, float mean, float inv_in,
+                                               float inv_out, int B, int H, int W,
                                                const float *__restrict__ w,
                                                const float *__restrict__ b, float *__restrict__ z,
                                                bf16 *__restrict__ a) {
@@ -94,10 +99,17 @@ __global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, int 
     for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
         for (int kx = 0; kx < 3; ++kx) {
-            const size_t q = size_t((n * H + wrapi(y + ky - 1, H)) * W + wrapi(x + kx - 1, W)) * K;
+            const size_t q = size_t((n * H + wrapi(y + ky - 1, H)) * W + wrapi(x + kx - 1, W));
+            if constexpr (FUSED) {
+                const float c = cur[q];
+                xi[0][ky * 3 + kx] = (c - mean) * inv_in;
+                if constexpr (K == 2) xi[1][ky * 3 + kx] = (c - prev[q]) * inv_out;
+            } else {
 #pragma unroll
-            for (int ci = 0; ci < K; ++ci) xi[ci][ky * 3 + kx] = X[q + ci];
+                for (int ci = 0; ci < K; ++ci) xi[ci][ky * 3 + kx] = X[q * K + ci];
+            }
         }
+    bf16x8 out[SC / 8];
 #pragma unroll
     for (int co = 0; co < SC; ++co) {
         float acc = b[co];
@@ -105,9 +117,12 @@ __global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, int 
         for (int ci = 0; ci < K; ++ci)
 #pragma unroll
             for (int k = 0; k < 9; ++k) acc += w[(co * K + ci) * 9 + k] * xi[ci][k];
-        z[size_t(p) * SC + co] = acc;
-        a[size_t(p) * SC + co] = bf16(silu(acc));
+        if constexpr (ZOUT) z[size_t(p) * SC + co] = acc;
+        out[co / 8][co % 8] = bf16(silu(acc));
     }
+    bf16x8 *ap = reinterpret_cast<bf16x8 *>(a + size_t(p) * SC);
+#pragma unroll
+    for (int c8 = 0; c8 < SC / 8; ++c8) ap[c8] = out[c8];
 }
 
 // ---------------------------------------------------------------------------
@@ -118,7 +133,7 @@ __global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, int 
 //   backward:  out = conv(dZ; W') (W' = tap-flipped transpose: the adjoint)
 //              -> dZ_prev = out * SiLU'(z_prev) (BF16)
 // ---------------------------------------------------------------------------
-template <bool BWD>
+template <bool BWD, bool ZOUT = true>
 __global__ void __launch_bounds__(256) k_mid(const bf16 *__restrict__ ain,
                                              const bf16 *__restrict__ wpk,
                                              const float *__restrict__ bias, int B, int H, int W,
@@ -166,7 +181,7 @@ __global__ void __launch_bounds__(256) k_mid(const bf16 *__restrict__ ain,
                     aout[pix * SC + co] = bf16(v * dsilu(zprev[pix * SC + co]));
                 } else {
                     const float zz = v + bv[nt];
-                    zout[pix * SC + co] = zz;
+                    if (ZOUT) zout[pix * SC + co] = zz;
                     aout[pix * SC + co] = bf16(silu(zz));
                 }
             }
@@ -201,19 +216,33 @@ __global__ void __launch_bounds__(256) k_last(const bf16 *__restrict__ a, int B,
     y[p] = acc;
 }
 
-// per-image sums of a field (one block per image), in FP64
-__global__ void __launch_bounds__(256) k_img_sum(const float *__restrict__ v, int HW,
-                                                 double *__restrict__ out) {
+// Per-image sums of a field in FP64, in a fixed order: stage 1 sums each of
+// IMG_PARTS contiguous segments of an image (one block each, a block-wide tree),
+// stage 2 sums an image's segment sums (one block per image).
+constexpr int IMG_PARTS = 64;
+__global__ void __launch_bounds__(256) k_img_part(const float *__restrict__ v, int HW,
+                                                  double *__restrict__ part) {
     __shared__ double sh[4];
-    const float *row = v + size_t(blockIdx.x) * HW;
+    const int img = blockIdx.x / IMG_PARTS, seg = blockIdx.x % IMG_PARTS;
+    const int len = (HW + IMG_PARTS - 1) / IMG_PARTS;
+    const int lo = seg * len, hi = min(HW, lo + len);
+    const float *row = v + size_t(img) * HW;
     double s = 0.0;
-    for (int i = threadIdx.x; i < HW; i += 256) s += double(row[i]);
+    for (int i = lo + threadIdx.x; i < hi; i += 256) s += double(row[i]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) out[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
+__global__ void __launch_bounds__(64) k_img_total(const double *__restrict__ part,
+                                                  double *__restrict__ out) {
+    double s = part[blockIdx.x * IMG_PARTS + threadIdx.x];  // IMG_PARTS == 64 lanes
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+static_assert(IMG_PARTS == 64, "k_img_total reduces one segment sum per lane");
 
 __global__ void __launch_bounds__(256) k_pred(const float *__restrict__ in,
                                               const float *__restrict__ y,
@@ -552,6 +581,7 @@ struct fsc_sur {
     bf16 *dzA = nullptr, *dzB = nullptr;
     float *y = nullptr, *gbuf = nullptr, *X = nullptr;
     double *ysum = nullptr, *gsum = nullptr, *loss = nullptr;
+    double *part = nullptr;  // [maxB][IMG_PARTS] segment sums
     int64_t adam_t = 0;
     std::string err;
 };
@@ -579,7 +609,7 @@ void sur_free(fsc_sur *s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
     void *ptrs[] = {s->params, s->grads, s->m,    s->v,    s->wf,   s->wb, s->dzA,
-                    s->dzB,    s->y,     s->gbuf, s->ysum, s->gsum, s->loss, s->X};
+                    s->dzB,    s->y,     s->gbuf, s->ysum, s->gsum, s->loss, s->X, s->part};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto p : s->z)
@@ -605,36 +635,60 @@ int check_batch(fsc_sur *s, int batch) {
     return FSC_OK;
 }
 
-// forward pass up to y (and the per-image sums of y)
-int sur_forward_core(fsc_sur *s, const float *prev, const float *cur, int B) {
+int img_sums(fsc_sur *s, const float *v, int B, double *out) {
+    hipLaunchKernelGGL(k_img_part, dim3(unsigned(B * IMG_PARTS)), dim3(256), 0, s->stream, v,
+                       s->H * s->W, s->part);
+    SCHK(s, hipGetLastError());
+    hipLaunchKernelGGL(k_img_total, dim3(unsigned(B)), dim3(64), 0, s->stream, s->part, out);
+    SCHK(s, hipGetLastError());
+    return FSC_OK;
+}
+
+// forward pass up to y (and the per-image sums of y); `train` keeps what the
+// backward pass needs (the FP32 pre-activations and the input X)
+int sur_forward_core(fsc_sur *s, const float *prev, const float *cur, int B, bool train) {
     const int P = B * s->H * s->W;
     const unsigned nb = unsigned((P + 255) / 256);
-    hipLaunchKernelGGL(k_input, dim3(nb), dim3(256), 0, s->stream, cur, prev, P, s->in_ch, s->mean,
-                       1.f / s->in_scale, 1.f / s->out_scale, s->X);
-    SCHK(s, hipGetLastError());
-    if (s->in_ch == 2)
-        hipLaunchKernelGGL(k_first<2>, dim3(nb), dim3(256), 0, s->stream, s->X, B, s->H, s->W,
-                           s->params + s->woff[0], s->params + s->boff[0], s->z[0], s->a[0]);
-    else
-        hipLaunchKernelGGL(k_first<1>, dim3(nb), dim3(256), 0, s->stream, s->X, B, s->H, s->W,
-                           s->params + s->woff[0], s->params + s->boff[0], s->z[0], s->a[0]);
+    const float ii = 1.f / s->in_scale, io = 1.f / s->out_scale;
+    const float *w0 = s->params + s->woff[0], *b0 = s->params + s->boff[0];
+    if (train) {
+        hipLaunchKernelGGL(k_input, dim3(nb), dim3(256), 0, s->stream, cur, prev, P, s->in_ch, s->mean,
+                           ii, io, s->X);
+        SCHK(s, hipGetLastError());
+        if (s->in_ch == 2)
+            hipLaunchKernelGGL((k_first<2, true, false>), dim3(nb), dim3(256), 0, s->stream, s->X, cur,
+                               prev, s->mean, ii, io, B, s->H, s->W, w0, b0, s->z[0], s->a[0]);
+        else
+            hipLaunchKernelGGL((k_first<1, true, false>), dim3(nb), dim3(256), 0, s->stream, s->X, cur,
+                               prev, s->mean, ii, io, B, s->H, s->W, w0, b0, s->z[0], s->a[0]);
+    } else {
+        if (s->in_ch == 2)
+            hipLaunchKernelGGL((k_first<2, false, true>), dim3(nb), dim3(256), 0, s->stream, s->X, cur,
+                               prev, s->mean, ii, io, B, s->H, s->W, w0, b0, s->z[0], s->a[0]);
+        else
+            hipLaunchKernelGGL((k_first<1, false, true>), dim3(nb), dim3(256), 0, s->stream, s->X, cur,
+                               prev, s->mean, ii, io, B, s->H, s->W, w0, b0, s->z[0], s->a[0]);
+    }
     SCHK(s, hipGetLastError());
     const int tiles = P / 16;
     const unsigned mb = unsigned(std::min(2048, std::max(1, tiles / 16)));
     for (int l = 1; l <= nmid(s); ++l) {
         const size_t off = size_t(l - 1) * 9 * SC * SC;
-        hipLaunchKernelGGL(k_mid<false>, dim3(mb), dim3(256), 0, s->stream, s->a[l - 1],
-                           s->wf + off, s->params + s->boff[l], B, s->H, s->W, s->z[l], s->a[l],
-                           nullptr);
+        if (train)
+            hipLaunchKernelGGL((k_mid<false, true>), dim3(mb), dim3(256), 0, s->stream, s->a[l - 1],
+                               s->wf + off, s->params + s->boff[l], B, s->H, s->W, s->z[l], s->a[l],
+                               nullptr);
+        else
+            hipLaunchKernelGGL((k_mid<false, false>), dim3(mb), dim3(256), 0, s->stream, s->a[l - 1],
+                               s->wf + off, s->params + s->boff[l], B, s->H, s->W, s->z[l], s->a[l],
+                               nullptr);
         SCHK(s, hipGetLastError());
     }
     const int last = s->layers - 1;
     hipLaunchKernelGGL(k_last, dim3(nb), dim3(256), 0, s->stream, s->a[last - 1], B, s->H, s->W,
                        s->params + s->woff[last], s->params + s->boff[last], s->y);
     SCHK(s, hipGetLastError());
-    hipLaunchKernelGGL(k_img_sum, dim3(B), dim3(256), 0, s->stream, s->y, s->H * s->W, s->ysum);
-    SCHK(s, hipGetLastError());
-    return FSC_OK;
+    return img_sums(s, s->y, B, s->ysum);
 }
 
 int sur_backward(fsc_sur *s, const float *in, const float *tgt, int B) {
@@ -645,8 +699,10 @@ int sur_backward(fsc_sur *s, const float *in, const float *tgt, int B) {
     hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s->stream, in, tgt, s->y, s->ysum, P, H * W,
                        1.f / s->out_scale, 1.f / float(P), s->gbuf, s->loss);
     SCHK(s, hipGetLastError());
-    hipLaunchKernelGGL(k_img_sum, dim3(B), dim3(256), 0, s->stream, s->gbuf, H * W, s->gsum);
-    SCHK(s, hipGetLastError());
+    {
+        int rc = img_sums(s, s->gbuf, B, s->gsum);
+        if (rc) return rc;
+    }
     const int last = s->layers - 1;
     const int chunk = 2048;
     const unsigned cb = unsigned((P + chunk - 1) / chunk);
@@ -666,7 +722,7 @@ int sur_backward(fsc_sur *s, const float *in, const float *tgt, int B) {
                            W, s->grads + s->woff[l], s->grads + s->boff[l]);
         SCHK(s, hipGetLastError());
         const size_t off = size_t(l - 1) * 9 * SC * SC;
-        hipLaunchKernelGGL(k_mid<true>, dim3(mb), dim3(256), 0, s->stream, dz, s->wb + off,
+        hipLaunchKernelGGL((k_mid<true, true>), dim3(mb), dim3(256), 0, s->stream, dz, s->wb + off,
                            nullptr, B, H, W, nullptr, dzn, s->z[l - 1]);
         SCHK(s, hipGetLastError());
         std::swap(dz, dzn);
@@ -746,6 +802,7 @@ int fsc_sur_create(int layers, int in_ch, int H, int W, int max_batch, uint64_t 
               hipMalloc(&s->gbuf, sizeof(float) * P) == hipSuccess &&
               hipMalloc(&s->X, sizeof(float) * P * in_ch) == hipSuccess &&
               hipMalloc(&s->ysum, sizeof(double) * max_batch) == hipSuccess &&
+              hipMalloc(&s->part, sizeof(double) * IMG_PARTS * max_batch) == hipSuccess &&
               hipMalloc(&s->gsum, sizeof(double) * max_batch) == hipSuccess &&
               hipMalloc(&s->loss, sizeof(double)) == hipSuccess;
     for (int l = 0; ok && l < layers - 1; ++l) {
@@ -820,7 +877,7 @@ int fsc_sur_forward(fsc_sur *s, const float *dev_prev, const float *dev_in, floa
     if (rc) return rc;
     rc = check_batch(s, batch);
     if (rc) return rc;
-    rc = sur_forward_core(s, dev_prev, dev_in, batch);
+    rc = sur_forward_core(s, dev_prev, dev_in, batch, false);
     if (rc) return rc;
     const int P = batch * s->H * s->W;
     hipLaunchKernelGGL(k_pred, dim3(unsigned((P + 255) / 256)), dim3(256), 0, s->stream, dev_in,
@@ -836,7 +893,7 @@ int fsc_sur_grad(fsc_sur *s, const float *dev_prev, const float *dev_in, const f
     if (rc) return rc;
     rc = check_batch(s, batch);
     if (rc) return rc;
-    rc = sur_forward_core(s, dev_prev, dev_in, batch);
+    rc = sur_forward_core(s, dev_prev, dev_in, batch, true);
     if (rc) return rc;
     rc = sur_backward(s, dev_in, dev_target, batch);
     if (rc) return rc;
@@ -857,7 +914,7 @@ int fsc_sur_train_step(fsc_sur *s, const float *dev_prev, const float *dev_in,
     if (rc) return rc;
     rc = check_batch(s, batch);
     if (rc) return rc;
-    rc = sur_forward_core(s, dev_prev, dev_in, batch);
+    rc = sur_forward_core(s, dev_prev, dev_in, batch, true);
     if (rc) return rc;
     rc = sur_backward(s, dev_in, dev_target, batch);
     if (rc) return rc;
