@@ -31,7 +31,8 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int SC = 32;  // hidden channels
+constexpr int SC = 32;          // hidden channels
+constexpr int IMG_PARTS = 64;   // segments per image of the per-image FP64 sums
 
 __device__ __forceinline__ float silu(float z) { return z / (1.f + __expf(-z)); }
 __device__ __forceinline__ float dsilu(float z) {
@@ -190,36 +191,50 @@ __global__ void __launch_bounds__(256) k_mid(const bf16 *__restrict__ ain,
 }
 
 // ---------------------------------------------------------------------------
-// Last layer (C -> 1) forward, FP32 from BF16 activations.
+// Last layer (C -> 1) forward, FP32 from BF16 activations.  Block (image,
+// segment) computes the segment's pixels (the IMG_PARTS segments of
+// k_img_part) and also writes the segment's FP64 sum of y, in the same order
+// k_img_part would.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_last(const bf16 *__restrict__ a, int B, int H, int W,
                                               const float *__restrict__ w, const float *__restrict__ b,
-                                              float *__restrict__ y) {
-    const int P = B * H * W;
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= P) return;
-    const int x = p % W, t = p / W, yy = t % H, n = t / H;
-    float acc = b[0];
+                                              float *__restrict__ y, double *__restrict__ part) {
+    __shared__ double sh[4];
+    const int HW = H * W;
+    const int img = blockIdx.x / IMG_PARTS, seg = blockIdx.x % IMG_PARTS;
+    const int len = (HW + IMG_PARTS - 1) / IMG_PARTS;
+    const int lo = seg * len, hi = min(HW, lo + len);
+    double s = 0.0;
+    for (int i = lo + threadIdx.x; i < hi; i += 256) {
+        const int p = img * HW + i;
+        const int x = p % W, t = p / W, yy = t % H, n = t / H;
+        float acc = b[0];
 #pragma unroll
-    for (int ky = 0; ky < 3; ++ky)
+        for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-            const int q = (n * H + wrapi(yy + ky - 1, H)) * W + wrapi(x + kx - 1, W);
-            const bf16x8 *ap = reinterpret_cast<const bf16x8 *>(a + size_t(q) * SC);
+            for (int kx = 0; kx < 3; ++kx) {
+                const int q = (n * H + wrapi(yy + ky - 1, H)) * W + wrapi(x + kx - 1, W);
+                const bf16x8 *ap = reinterpret_cast<const bf16x8 *>(a + size_t(q) * SC);
 #pragma unroll
-            for (int c8 = 0; c8 < SC / 8; ++c8) {
-                const bf16x8 v = ap[c8];
+                for (int c8 = 0; c8 < SC / 8; ++c8) {
+                    const bf16x8 v = ap[c8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) acc += w[(c8 * 8 + e) * 9 + ky * 3 + kx] * float(v[e]);
+                    for (int e = 0; e < 8; ++e) acc += w[(c8 * 8 + e) * 9 + ky * 3 + kx] * float(v[e]);
+                }
             }
-        }
-    y[p] = acc;
+        y[p] = acc;
+        s += double(acc);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // Per-image sums of a field in FP64, in a fixed order: stage 1 sums each of
 // IMG_PARTS contiguous segments of an image (one block each, a block-wide tree),
 // stage 2 sums an image's segment sums (one block per image).
-constexpr int IMG_PARTS = 64;
 __global__ void __launch_bounds__(256) k_img_part(const float *__restrict__ v, int HW,
                                                   double *__restrict__ part) {
     __shared__ double sh[4];
@@ -244,14 +259,28 @@ __global__ void __launch_bounds__(64) k_img_total(const double *__restrict__ par
 }
 static_assert(IMG_PARTS == 64, "k_img_total reduces one segment sum per lane");
 
+// prediction rho_t + out_scale (y - <y>_image); block (image, segment), the
+// image's mean from its IMG_PARTS segment sums (summed as k_img_total does)
 __global__ void __launch_bounds__(256) k_pred(const float *__restrict__ in,
                                               const float *__restrict__ y,
-                                              const double *__restrict__ ysum, int P, int HW,
+                                              const double *__restrict__ part, int HW,
                                               float out_scale, float *__restrict__ out) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= P) return;
-    const float mean = float(ysum[p / HW] / HW);
-    out[p] = in[p] + out_scale * (y[p] - mean);
+    __shared__ float mean_sh;
+    const int img = blockIdx.x / IMG_PARTS, seg = blockIdx.x % IMG_PARTS;
+    if (threadIdx.x < 64) {
+        double t = part[img * IMG_PARTS + threadIdx.x];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        if (threadIdx.x == 0) mean_sh = float(t / HW);
+    }
+    __syncthreads();
+    const float mean = mean_sh;
+    const int len = (HW + IMG_PARTS - 1) / IMG_PARTS;
+    const int lo = seg * len, hi = min(HW, lo + len);
+    for (int i = lo + threadIdx.x; i < hi; i += 256) {
+        const size_t p = size_t(img) * HW + i;
+        out[p] = in[p] + out_scale * (y[p] - mean);
+    }
 }
 
 // loss terms and dL/dyhat; loss accumulated in FP64
@@ -685,10 +714,14 @@ int sur_forward_core(fsc_sur *s, const float *prev, const float *cur, int B, boo
         SCHK(s, hipGetLastError());
     }
     const int last = s->layers - 1;
-    hipLaunchKernelGGL(k_last, dim3(nb), dim3(256), 0, s->stream, s->a[last - 1], B, s->H, s->W,
-                       s->params + s->woff[last], s->params + s->boff[last], s->y);
+    hipLaunchKernelGGL(k_last, dim3(unsigned(B * IMG_PARTS)), dim3(256), 0, s->stream, s->a[last - 1], B,
+                       s->H, s->W, s->params + s->woff[last], s->params + s->boff[last], s->y, s->part);
     SCHK(s, hipGetLastError());
-    return img_sums(s, s->y, B, s->ysum);
+    if (train) {  // the loss needs the per-image sums of y
+        hipLaunchKernelGGL(k_img_total, dim3(unsigned(B)), dim3(64), 0, s->stream, s->part, s->ysum);
+        SCHK(s, hipGetLastError());
+    }
+    return FSC_OK;
 }
 
 int sur_backward(fsc_sur *s, const float *in, const float *tgt, int B) {
@@ -879,9 +912,8 @@ int fsc_sur_forward(fsc_sur *s, const float *dev_prev, const float *dev_in, floa
     if (rc) return rc;
     rc = sur_forward_core(s, dev_prev, dev_in, batch, false);
     if (rc) return rc;
-    const int P = batch * s->H * s->W;
-    hipLaunchKernelGGL(k_pred, dim3(unsigned((P + 255) / 256)), dim3(256), 0, s->stream, dev_in,
-                       s->y, s->ysum, P, s->H * s->W, s->out_scale, dev_out);
+    hipLaunchKernelGGL(k_pred, dim3(unsigned(batch * IMG_PARTS)), dim3(256), 0, s->stream, dev_in,
+                       s->y, s->part, s->H * s->W, s->out_scale, dev_out);
     SCHK(s, hipGetLastError());
     return FSC_OK;
 }
