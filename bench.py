@@ -247,14 +247,15 @@ def summarize_surrogate_trace(trace_dir: str, log_path: str, out_path: str):
             if m:
                 ident = m.group(2)[:int(m.group(1))]
                 rest = m.group(2)[int(m.group(1)):]
-                flag = {"ILb0E": "<false>", "ILb1E": "<true>"}.get(rest[:5], "")
+                flags = re.findall(r"Lb([01])E", rest[:12])
+                flag = "<" + ", ".join("true" if f == "1" else "false" for f in flags) + ">" if flags else ""
                 short = ident + flag
             elif "fsc::k_" in name:
                 short = name.replace("void ", "").split("(")[0].replace("fsc::", "")
             else:
                 continue
-            if short.split("<")[0] in ("k_input", "k_first", "k_mid", "k_last", "k_img_part",
-                                       "k_img_total", "k_pred"):
+            if short.split("<")[0] in ("k_input", "k_first", "k_mid", "k_mid_lds", "k_last",
+                                       "k_img_part", "k_img_total", "k_pred"):
                 per[short].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     lines = ["# Surrogate kernels: rocprofv3 kernel trace of bench.py (rollout part)", "",
              "Command (repository root as working directory, TMPDIR=/tmp):", "",
@@ -274,7 +275,7 @@ def summarize_surrogate_trace(trace_dir: str, log_path: str, out_path: str):
     for name, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
         mean = sum(v) / len(v)
         note = ""
-        if name.startswith("k_mid") and batch:
+        if name.startswith("k_mid") and batch:  # the generic and the LDS-staged forms
             flops = 2 * 9 * 32 * 32 * batch * 128 * 128
             tf = flops / (mean * 1e-9) / 1e12
             note = (f"{flops / 1e9:.2f} GFLOP per launch: {tf:.1f} TFLOP/s, "

@@ -91,6 +91,11 @@ __global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, cons
                                                const float *__restrict__ w,
                                                const float *__restrict__ b, float *__restrict__ z,
                                                bf16 *__restrict__ a) {
+    // the layer's weights and biases, read by every lane, staged once in LDS
+    __shared__ float ws[SC * K * 9 + SC];
+    for (int i = threadIdx.x; i < SC * K * 9; i += 256) ws[i] = w[i];
+    if (threadIdx.x < SC) ws[SC * K * 9 + threadIdx.x] = b[threadIdx.x];
+    __syncthreads();
     const int P = B * H * W;
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= P) return;
@@ -113,11 +118,11 @@ __global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, cons
     bf16x8 out[SC / 8];
 #pragma unroll
     for (int co = 0; co < SC; ++co) {
-        float acc = b[co];
+        float acc = ws[SC * K * 9 + co];
 #pragma unroll
         for (int ci = 0; ci < K; ++ci)
 #pragma unroll
-            for (int k = 0; k < 9; ++k) acc += w[(co * K + ci) * 9 + k] * xi[ci][k];
+            for (int k = 0; k < 9; ++k) acc += ws[(co * K + ci) * 9 + k] * xi[ci][k];
         if constexpr (ZOUT) z[size_t(p) * SC + co] = acc;
         out[co / 8][co % 8] = bf16(silu(acc));
     }
@@ -190,6 +195,81 @@ __global__ void __launch_bounds__(256) k_mid(const bf16 *__restrict__ ain,
     }
 }
 
+// The same layer with the input staged in LDS: a block computes a tile of
+// MR rows x MW pixels of one image (wave w: row w, MW/16 MFMA tiles), after
+// loading the tile's (MR+2) x (MW+2) input pixels with their 32 channels once
+// (coalesced 16-byte pieces) instead of reading each pixel for each of the
+// 9 taps from L2.  Needs H % MR == 0 and W % MW == 0.
+constexpr int MR = 4, MW = 64;
+template <bool BWD, bool ZOUT>
+__global__ void __launch_bounds__(256) k_mid_lds(const bf16 *__restrict__ ain,
+                                                 const bf16 *__restrict__ wpk,
+                                                 const float *__restrict__ bias, int B, int H, int W,
+                                                 float *__restrict__ zout, bf16 *__restrict__ aout,
+                                                 const float *__restrict__ zprev) {
+    constexpr int LW = MW + 2;
+    __shared__ __attribute__((aligned(16))) bf16 tile_in[(MR + 2) * LW * SC];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int txs = W / MW, tys = H / MR;
+    const int bx = blockIdx.x % txs, t1 = blockIdx.x / txs;
+    const int by = t1 % tys, n = t1 / tys;
+    const int x0 = bx * MW, y0 = by * MR;
+    // stage the input window: pixel (r, c) of the window is image pixel
+    // (y0 - 1 + r, x0 - 1 + c), periodic; 4 pieces of 8 channels per pixel
+    for (int k = threadIdx.x; k < (MR + 2) * LW * 4; k += 256) {
+        const int piece = k & 3, pc = k >> 2;
+        const int r = pc / LW, c = pc % LW;
+        const int yy = wrapi(y0 - 1 + r, H), xx = wrapi(x0 - 1 + c, W);
+        const size_t q = size_t((n * H + yy) * W + xx);
+        *reinterpret_cast<bf16x8 *>(tile_in + pc * SC + piece * 8) =
+            *reinterpret_cast<const bf16x8 *>(ain + q * SC + piece * 8);
+    }
+    bf16x8 bop[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+            bop[t][nt] = *reinterpret_cast<const bf16x8 *>(wpk + (t * SC + nt * 16 + r16) * SC + g * 8);
+    float bv[2] = {0.f, 0.f};
+    if (!BWD) {
+        bv[0] = bias[r16];
+        bv[1] = bias[16 + r16];
+    }
+    __syncthreads();
+    const int y = y0 + wave;
+#pragma unroll
+    for (int tx = 0; tx < MW / 16; ++tx) {
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const int pc = (wave + ky) * LW + tx * 16 + r16 + kx;
+                const bf16x8 aop = *reinterpret_cast<const bf16x8 *>(tile_in + pc * SC + g * 8);
+                acc0 = mfma16(aop, bop[ky * 3 + kx][0], acc0);
+                acc1 = mfma16(aop, bop[ky * 3 + kx][1], acc1);
+            }
+        const size_t p0 = size_t((n * H + y) * W + x0 + tx * 16);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const size_t pix = p0 + 4 * g + r;
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const int co = nt * 16 + r16;
+                const float v = nt ? acc1[r] : acc0[r];
+                if (BWD) {
+                    aout[pix * SC + co] = bf16(v * dsilu(zprev[pix * SC + co]));
+                } else {
+                    const float zz = v + bv[nt];
+                    if (ZOUT) zout[pix * SC + co] = zz;
+                    aout[pix * SC + co] = bf16(silu(zz));
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Last layer (C -> 1) forward, FP32 from BF16 activations.  Block (image,
 // segment) computes the segment's pixels (the IMG_PARTS segments of
@@ -200,6 +280,9 @@ __global__ void __launch_bounds__(256) k_last(const bf16 *__restrict__ a, int B,
                                               const float *__restrict__ w, const float *__restrict__ b,
                                               float *__restrict__ y, double *__restrict__ part) {
     __shared__ double sh[4];
+    __shared__ float ws[SC * 9];  // the layer's weights, staged once
+    for (int i = threadIdx.x; i < SC * 9; i += 256) ws[i] = w[i];
+    __syncthreads();
     const int HW = H * W;
     const int img = blockIdx.x / IMG_PARTS, seg = blockIdx.x % IMG_PARTS;
     const int len = (HW + IMG_PARTS - 1) / IMG_PARTS;
@@ -219,7 +302,7 @@ __global__ void __launch_bounds__(256) k_last(const bf16 *__restrict__ a, int B,
                 for (int c8 = 0; c8 < SC / 8; ++c8) {
                     const bf16x8 v = ap[c8];
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) acc += w[(c8 * 8 + e) * 9 + ky * 3 + kx] * float(v[e]);
+                    for (int e = 0; e < 8; ++e) acc += ws[(c8 * 8 + e) * 9 + ky * 3 + kx] * float(v[e]);
                 }
             }
         y[p] = acc;
@@ -664,6 +747,9 @@ int check_batch(fsc_sur *s, int batch) {
     return FSC_OK;
 }
 
+// the LDS-staged C -> C layer applies when its tiles divide the image
+bool lds_tiles(const fsc_sur *s) { return s->H % MR == 0 && s->W % MW == 0; }
+
 int img_sums(fsc_sur *s, const float *v, int B, double *out) {
     hipLaunchKernelGGL(k_img_part, dim3(unsigned(B * IMG_PARTS)), dim3(256), 0, s->stream, v,
                        s->H * s->W, s->part);
@@ -703,14 +789,23 @@ int sur_forward_core(fsc_sur *s, const float *prev, const float *cur, int B, boo
     const unsigned mb = unsigned(std::min(2048, std::max(1, tiles / 16)));
     for (int l = 1; l <= nmid(s); ++l) {
         const size_t off = size_t(l - 1) * 9 * SC * SC;
-        if (train)
-            hipLaunchKernelGGL((k_mid<false, true>), dim3(mb), dim3(256), 0, s->stream, s->a[l - 1],
-                               s->wf + off, s->params + s->boff[l], B, s->H, s->W, s->z[l], s->a[l],
-                               nullptr);
-        else
-            hipLaunchKernelGGL((k_mid<false, false>), dim3(mb), dim3(256), 0, s->stream, s->a[l - 1],
-                               s->wf + off, s->params + s->boff[l], B, s->H, s->W, s->z[l], s->a[l],
-                               nullptr);
+        const bf16 *ain = s->a[l - 1], *wl = s->wf + off;
+        const float *bl = s->params + s->boff[l];
+        if (lds_tiles(s)) {
+            const dim3 g(unsigned(B * (s->H / MR) * (s->W / MW)));
+            if (train)
+                hipLaunchKernelGGL((k_mid_lds<false, true>), g, dim3(256), 0, s->stream, ain, wl, bl, B,
+                                   s->H, s->W, s->z[l], s->a[l], nullptr);
+            else
+                hipLaunchKernelGGL((k_mid_lds<false, false>), g, dim3(256), 0, s->stream, ain, wl, bl, B,
+                                   s->H, s->W, s->z[l], s->a[l], nullptr);
+        } else if (train) {
+            hipLaunchKernelGGL((k_mid<false, true>), dim3(mb), dim3(256), 0, s->stream, ain, wl, bl, B,
+                               s->H, s->W, s->z[l], s->a[l], nullptr);
+        } else {
+            hipLaunchKernelGGL((k_mid<false, false>), dim3(mb), dim3(256), 0, s->stream, ain, wl, bl, B,
+                               s->H, s->W, s->z[l], s->a[l], nullptr);
+        }
         SCHK(s, hipGetLastError());
     }
     const int last = s->layers - 1;
@@ -755,8 +850,12 @@ int sur_backward(fsc_sur *s, const float *in, const float *tgt, int B) {
                            W, s->grads + s->woff[l], s->grads + s->boff[l]);
         SCHK(s, hipGetLastError());
         const size_t off = size_t(l - 1) * 9 * SC * SC;
-        hipLaunchKernelGGL((k_mid<true, true>), dim3(mb), dim3(256), 0, s->stream, dz, s->wb + off,
-                           nullptr, B, H, W, nullptr, dzn, s->z[l - 1]);
+        if (lds_tiles(s))
+            hipLaunchKernelGGL((k_mid_lds<true, true>), dim3(unsigned(B * (H / MR) * (W / MW))), dim3(256),
+                               0, s->stream, dz, s->wb + off, nullptr, B, H, W, nullptr, dzn, s->z[l - 1]);
+        else
+            hipLaunchKernelGGL((k_mid<true, true>), dim3(mb), dim3(256), 0, s->stream, dz, s->wb + off,
+                               nullptr, B, H, W, nullptr, dzn, s->z[l - 1]);
         SCHK(s, hipGetLastError());
         std::swap(dz, dzn);
     }

@@ -95,10 +95,11 @@ def test_forward_matches_reference(layers, in_ch):
     sur.close()
 
 
-@pytest.mark.parametrize("in_ch", [1, 2])
-def test_gradient_matches_reference(in_ch):
+@pytest.mark.parametrize("in_ch,H,W", [(1, 32, 32), (2, 32, 32), (2, 16, 64)])
+def test_gradient_matches_reference(in_ch, H, W):
+    # 32 x 32 runs the generic C -> C kernels, 16 x 64 the LDS-staged ones
     rng = np.random.default_rng(3)
-    B, H, W, layers = 2, 32, 32, 5
+    B, layers = 2, 5
     p = _net(4, L=layers, in_ch=in_ch).astype(np.float32)
     rho = (1.0 + 0.3 * rng.normal(size=(B, H, W))).astype(np.float32)
     prev = (rho + 0.05 * rng.normal(size=rho.shape)).astype(np.float32) if in_ch == 2 else None
