@@ -32,7 +32,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int SC = 32;          // hidden channels
-constexpr int IMG_PARTS = 64;   // segments per image of the per-image FP64 sums
+constexpr int IMG_PARTS = 256;  // segments per image of the per-image FP64 sums
 
 __device__ __forceinline__ float silu(float z) { return z / (1.f + __expf(-z)); }
 __device__ __forceinline__ float dsilu(float z) {
@@ -96,8 +96,10 @@ __global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, cons
     for (int i = threadIdx.x; i < SC * K * 9; i += 256) ws[i] = w[i];
     if (threadIdx.x < SC) ws[SC * K * 9 + threadIdx.x] = b[threadIdx.x];
     __syncthreads();
+    // four threads per pixel, eight output channels each
     const int P = B * H * W;
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    const int p = gid >> 2, cg = gid & 3;
     if (p >= P) return;
     const int x = p % W, t = p / W, y = t % H, n = t / H;
     float xi[K][9];
@@ -115,20 +117,19 @@ __global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, cons
                 for (int ci = 0; ci < K; ++ci) xi[ci][ky * 3 + kx] = X[q * K + ci];
             }
         }
-    bf16x8 out[SC / 8];
+    bf16x8 out;
 #pragma unroll
-    for (int co = 0; co < SC; ++co) {
+    for (int j = 0; j < 8; ++j) {
+        const int co = cg * 8 + j;
         float acc = ws[SC * K * 9 + co];
 #pragma unroll
         for (int ci = 0; ci < K; ++ci)
 #pragma unroll
             for (int k = 0; k < 9; ++k) acc += ws[(co * K + ci) * 9 + k] * xi[ci][k];
         if constexpr (ZOUT) z[size_t(p) * SC + co] = acc;
-        out[co / 8][co % 8] = bf16(silu(acc));
+        out[j] = bf16(silu(acc));
     }
-    bf16x8 *ap = reinterpret_cast<bf16x8 *>(a + size_t(p) * SC);
-#pragma unroll
-    for (int c8 = 0; c8 < SC / 8; ++c8) ap[c8] = out[c8];
+    *reinterpret_cast<bf16x8 *>(a + size_t(p) * SC + cg * 8) = out;
 }
 
 // ---------------------------------------------------------------------------
@@ -272,9 +273,9 @@ __global__ void __launch_bounds__(256) k_mid_lds(const bf16 *__restrict__ ain,
 
 // ---------------------------------------------------------------------------
 // Last layer (C -> 1) forward, FP32 from BF16 activations.  Block (image,
-// segment) computes the segment's pixels (the IMG_PARTS segments of
-// k_img_part) and also writes the segment's FP64 sum of y, in the same order
-// k_img_part would.
+// segment) computes the segment's pixels, four lanes per pixel (eight
+// channels each, combined by lane shuffles), and writes the segment's FP64 sum
+// of y (a block-wide tree in a fixed order).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_last(const bf16 *__restrict__ a, int B, int H, int W,
                                               const float *__restrict__ w, const float *__restrict__ b,
@@ -287,26 +288,31 @@ __global__ void __launch_bounds__(256) k_last(const bf16 *__restrict__ a, int B,
     const int img = blockIdx.x / IMG_PARTS, seg = blockIdx.x % IMG_PARTS;
     const int len = (HW + IMG_PARTS - 1) / IMG_PARTS;
     const int lo = seg * len, hi = min(HW, lo + len);
+    const int cg = threadIdx.x & 3;
     double s = 0.0;
-    for (int i = lo + threadIdx.x; i < hi; i += 256) {
-        const int p = img * HW + i;
+    for (int i0 = lo; i0 < hi; i0 += 64) {  // 64 pixels per pass of the block
+        const int i = i0 + (threadIdx.x >> 2);
+        const bool on = i < hi;
+        const int pl = on ? i : hi - 1;     // idle lanes repeat a valid pixel
+        const int p = img * HW + pl;
         const int x = p % W, t = p / W, yy = t % H, n = t / H;
-        float acc = b[0];
+        float acc = 0.f;
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
                 const int q = (n * H + wrapi(yy + ky - 1, H)) * W + wrapi(x + kx - 1, W);
-                const bf16x8 *ap = reinterpret_cast<const bf16x8 *>(a + size_t(q) * SC);
+                const bf16x8 v = *reinterpret_cast<const bf16x8 *>(a + size_t(q) * SC + cg * 8);
 #pragma unroll
-                for (int c8 = 0; c8 < SC / 8; ++c8) {
-                    const bf16x8 v = ap[c8];
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) acc += ws[(c8 * 8 + e) * 9 + ky * 3 + kx] * float(v[e]);
-                }
+                for (int e = 0; e < 8; ++e) acc += ws[(cg * 8 + e) * 9 + ky * 3 + kx] * float(v[e]);
             }
-        y[p] = acc;
-        s += double(acc);
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        acc += b[0];
+        if (on && cg == 0) {
+            y[p] = acc;
+            s += double(acc);
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
@@ -333,14 +339,22 @@ __global__ void __launch_bounds__(256) k_img_part(const float *__restrict__ v, i
     __syncthreads();
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
-__global__ void __launch_bounds__(64) k_img_total(const double *__restrict__ part,
-                                                  double *__restrict__ out) {
-    double s = part[blockIdx.x * IMG_PARTS + threadIdx.x];  // IMG_PARTS == 64 lanes
+// sum of an image's IMG_PARTS segment sums by one wave, in a fixed order
+__device__ inline double image_total(const double *__restrict__ part, int img) {
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < IMG_PARTS / 64; ++k) s += part[img * IMG_PARTS + k * 64 + lane];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    return s;
+}
+__global__ void __launch_bounds__(64) k_img_total(const double *__restrict__ part,
+                                                  double *__restrict__ out) {
+    const double s = image_total(part, blockIdx.x);
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
-static_assert(IMG_PARTS == 64, "k_img_total reduces one segment sum per lane");
+static_assert(IMG_PARTS % 64 == 0, "a wave sums the segment sums");
 
 // prediction rho_t + out_scale (y - <y>_image); block (image, segment), the
 // image's mean from its IMG_PARTS segment sums (summed as k_img_total does)
@@ -351,9 +365,7 @@ __global__ void __launch_bounds__(256) k_pred(const float *__restrict__ in,
     __shared__ float mean_sh;
     const int img = blockIdx.x / IMG_PARTS, seg = blockIdx.x % IMG_PARTS;
     if (threadIdx.x < 64) {
-        double t = part[img * IMG_PARTS + threadIdx.x];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        const double t = image_total(part, img);
         if (threadIdx.x == 0) mean_sh = float(t / HW);
     }
     __syncthreads();
@@ -764,6 +776,7 @@ int img_sums(fsc_sur *s, const float *v, int B, double *out) {
 int sur_forward_core(fsc_sur *s, const float *prev, const float *cur, int B, bool train) {
     const int P = B * s->H * s->W;
     const unsigned nb = unsigned((P + 255) / 256);
+    const unsigned nb4 = unsigned((4 * int64_t(P) + 255) / 256);  // k_first: four lanes per pixel
     const float ii = 1.f / s->in_scale, io = 1.f / s->out_scale;
     const float *w0 = s->params + s->woff[0], *b0 = s->params + s->boff[0];
     if (train) {
@@ -771,17 +784,17 @@ int sur_forward_core(fsc_sur *s, const float *prev, const float *cur, int B, boo
                            ii, io, s->X);
         SCHK(s, hipGetLastError());
         if (s->in_ch == 2)
-            hipLaunchKernelGGL((k_first<2, true, false>), dim3(nb), dim3(256), 0, s->stream, s->X, cur,
+            hipLaunchKernelGGL((k_first<2, true, false>), dim3(nb4), dim3(256), 0, s->stream, s->X, cur,
                                prev, s->mean, ii, io, B, s->H, s->W, w0, b0, s->z[0], s->a[0]);
         else
-            hipLaunchKernelGGL((k_first<1, true, false>), dim3(nb), dim3(256), 0, s->stream, s->X, cur,
+            hipLaunchKernelGGL((k_first<1, true, false>), dim3(nb4), dim3(256), 0, s->stream, s->X, cur,
                                prev, s->mean, ii, io, B, s->H, s->W, w0, b0, s->z[0], s->a[0]);
     } else {
         if (s->in_ch == 2)
-            hipLaunchKernelGGL((k_first<2, false, true>), dim3(nb), dim3(256), 0, s->stream, s->X, cur,
+            hipLaunchKernelGGL((k_first<2, false, true>), dim3(nb4), dim3(256), 0, s->stream, s->X, cur,
                                prev, s->mean, ii, io, B, s->H, s->W, w0, b0, s->z[0], s->a[0]);
         else
-            hipLaunchKernelGGL((k_first<1, false, true>), dim3(nb), dim3(256), 0, s->stream, s->X, cur,
+            hipLaunchKernelGGL((k_first<1, false, true>), dim3(nb4), dim3(256), 0, s->stream, s->X, cur,
                                prev, s->mean, ii, io, B, s->H, s->W, w0, b0, s->z[0], s->a[0]);
     }
     SCHK(s, hipGetLastError());
