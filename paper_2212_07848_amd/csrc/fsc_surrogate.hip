@@ -197,11 +197,19 @@ __global__ void __launch_bounds__(256) k_mid(const bf16 *__restrict__ ain,
 }
 
 // The same layer with the input staged in LDS: a block computes a tile of
-// MR rows x MW pixels of one image (wave w: row w, MW/16 MFMA tiles), after
-// loading the tile's (MR+2) x (MW+2) input pixels with their 32 channels once
-// (coalesced 16-byte pieces) instead of reading each pixel for each of the
-// 9 taps from L2.  Needs H % MR == 0 and W % MW == 0.
-constexpr int MR = 4, MW = 64;
+// MR rows x MW pixels of one image (MR MW / 16 MFMA tiles of 16 pixels, dealt
+// to the 4 waves in order), after loading the tile's (MR+2) x (MW+2) input
+// pixels with their 32 channels once (coalesced 16-byte pieces) instead of
+// reading each pixel for each of the 9 taps from L2.  Needs H % MR == 0 and
+// W % MW == 0.  The tile shape is a build-time choice (FSC_SUR_MR, FSC_SUR_MW).
+#ifndef FSC_SUR_MR
+#define FSC_SUR_MR 4
+#endif
+#ifndef FSC_SUR_MW
+#define FSC_SUR_MW 64
+#endif
+constexpr int MR = FSC_SUR_MR, MW = FSC_SUR_MW;
+static_assert(MW % 16 == 0 && (MR * MW / 16) % 4 == 0, "whole MFMA tiles, the same count per wave");
 template <bool BWD, bool ZOUT>
 __global__ void __launch_bounds__(256) k_mid_lds(const bf16 *__restrict__ ain,
                                                  const bf16 *__restrict__ wpk,
@@ -238,15 +246,18 @@ __global__ void __launch_bounds__(256) k_mid_lds(const bf16 *__restrict__ ain,
         bv[1] = bias[16 + r16];
     }
     __syncthreads();
-    const int y = y0 + wave;
+    constexpr int TPW = MR * MW / 64;  // MFMA tiles per wave
 #pragma unroll
-    for (int tx = 0; tx < MW / 16; ++tx) {
+    for (int j = 0; j < TPW; ++j) {
+        const int k = wave * TPW + j;
+        const int row = k / (MW / 16), tx = k % (MW / 16);
+        const int y = y0 + row;
         f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
-                const int pc = (wave + ky) * LW + tx * 16 + r16 + kx;
+                const int pc = (row + ky) * LW + tx * 16 + r16 + kx;
                 const bf16x8 aop = *reinterpret_cast<const bf16x8 *>(tile_in + pc * SC + g * 8);
                 acc0 = mfma16(aop, bop[ky * 3 + kx][0], acc0);
                 acc1 = mfma16(aop, bop[ky * 3 + kx][1], acc1);
