@@ -32,8 +32,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM roofline (FP32 D2Q9 fluct. SC); surrogate speedup at 5% S(k) err"
 HBM_PEAK_GBS = 8000.0
-# one non-packed VALU operation per lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP32 vector issue: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz = 78.6 T
+# operations/s (the published 157.3 TFLOP/s counts an FMA as two).  Integer
+# and transcendental instructions issue at about 1/2 and 1/3.5 of that rate.
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 KERNEL_SOURCES = ["paper_2212_07848_amd/csrc/fsc_step_kernel.h",
                   "paper_2212_07848_amd/csrc/fsc_step2_kernel.h",
                   "paper_2212_07848_amd/csrc/fsc_device.h"]

@@ -13,7 +13,8 @@
 // Workgroup: TX tile lanes plus one extra wave.  Every thread owns one
 // level-1 node at column offset x1 from the tile origin x0:
 //   tile lanes           x1 = lane (lanes past a ragged edge duplicate the last
-//                        valid column and write nothing to LDS)
+//                        valid column and write nothing to LDS; a wave wholly
+//                        past it does no work at all)
 //   extra wave, e < 2R+2 the level-1 edge columns -R-1..-1 and TXe..TXe+R
 //   extra wave, e < 4R+2 psi-only columns -2R-1..-R-2 and TXe+R+1..TXe+2R
 // and at most one level-2 node: tile lanes x2 = x1 (collide and store), extra
@@ -85,10 +86,14 @@ __global__ void __launch_bounds__(TX + 64)
     const bool ewave = tid >= TX;
     const int e = tid - TX;
     const bool eidle = ewave && full;  // wave-uniform
+    // a tile wave wholly past the tile's last column (a tile narrower than TX)
+    // has no node of its own: it only takes part in the barriers
+    const bool tidle = !ewave && (tid & ~63) >= TXe;  // wave-uniform
+    const bool idle = eidle || tidle;
 
     // level-1 node: column offset x1, collides (c1), writes to A (wa) and B (wb)
     int x1 = 0;
-    bool c1 = !ewave, wa = false, wb = false;
+    bool c1 = !ewave && !tidle, wa = false, wb = false;
     if (!ewave) {
         x1 = min(tid, TXe - 1);
         wa = wb = tid < TXe;
@@ -103,7 +108,8 @@ __global__ void __launch_bounds__(TX + 64)
     // level-2 node: column offset x2, forms psi(t+1) (p2), writes to C (wc);
     // tile lanes collide and store to HBM
     int x2 = 0;
-    bool p2 = !ewave, wc = false;
+    bool p2 = !ewave && !tidle, wc = false;
+    const bool st2 = !ewave && !tidle;  // collides and stores a level-2 node
     if (!ewave) {
         x2 = x1;
         wc = tid < TXe;
@@ -187,11 +193,11 @@ __global__ void __launch_bounds__(TX + 64)
 #pragma unroll
     for (int k = -R; k < R; ++k) {
         real tm[Q];
-        if (!eidle) load_row(lrow(k), tm);
+        if (!idle) load_row(lrow(k), tm);
         else
 #pragma unroll
             for (int i = 0; i < Q; ++i) tm[i] = real(0);
-        put_a(k, eidle ? real(0) : dpsi_of(tm));
+        put_a(k, idle ? real(0) : dpsi_of(tm));
         if (k >= 0) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) F[k][i] = tm[i];
@@ -298,13 +304,13 @@ __global__ void __launch_bounds__(TX + 64)
 
             // loads of level-1 row l_{j+R} (consumed by its psi below and by
             // its collision R iterations later)
-            if (lev1 && !eidle) load_row(lrow(j + R), F[fs_new]);
+            if (lev1 && !idle) load_row(lrow(j + R), F[fs_new]);
             // noise of both levels (independent of memory and LDS)
             real z1[NN], z2[NN];
             if constexpr (NOISE) {
-                if (lev1 && !eidle) node_normals<L, real>(uint32_t(gx1 + nx * wrap_row(lrow(j))), step1,
+                if (lev1 && !idle) node_normals<L, real>(uint32_t(gx1 + nx * wrap_row(lrow(j))), step1,
                                                          d.seed_hi, d.key0, d.key1, z1);
-                if (lev2 && !ewave)
+                if (lev2 && st2)
                     node_normals<L, real>(uint32_t(gx2 + nx * wrap_row(lrow(km))), step2, d.seed_hi,
                                           d.key0, d.key1, z2);
             }
@@ -315,18 +321,18 @@ __global__ void __launch_bounds__(TX + 64)
             if constexpr (BARS == 1) {
                 // B rows kp - 1 .. kp + 1 were written at least two iterations ago
                 if (psi2 && p2) psi_stage(kp, gs_new);
-                if (lev1) put_a(j + R, eidle ? real(0) : dpsi_of(F[fs_new]));
+                if (lev1) put_a(j + R, idle ? real(0) : dpsi_of(F[fs_new]));
                 __syncthreads();
                 if (lev1 && c1) level1(j, u, z1);
-                if (lev2 && !ewave) level2(km, gs_use, z2);
+                if (lev2 && st2) level2(km, gs_use, z2);
             } else {
-                if (lev1) put_a(j + R, eidle ? real(0) : dpsi_of(F[fs_new]));
+                if (lev1) put_a(j + R, idle ? real(0) : dpsi_of(F[fs_new]));
                 __syncthreads();
                 if (lev1 && c1) level1(j, u, z1);
                 __syncthreads();
                 // the collision frees the ring slot that the pull then refills
                 // (gs_use == gs_new, as kp - km = R + 1)
-                if (lev2 && !ewave) level2(km, gs_use, z2);
+                if (lev2 && st2) level2(km, gs_use, z2);
                 if (psi2 && p2) psi_stage(kp, gs_new);
             }
         }

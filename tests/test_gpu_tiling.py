@@ -17,6 +17,7 @@ CASES = [
     (2, (70, 301), 4, "fp32"),
     (2, (53, 200), 8, "fp32"),
     (2, (37, 128), 4, "fp32"),   # one whole-row tile of 128 (and of 256)
+    (2, (13, 1100), 4, "fp32"),  # a last tile 76 wide: whole waves of it idle
     (2, (9, 6), 8, "fp32"),      # narrowest two-step width for E8 (2R + 2)
     (2, (41, 256), 8, "fp32"),
     (3, (23, 45, 37), 4, "fp32"),
@@ -104,7 +105,7 @@ def test_uncompiled_tiling_is_refused():
 def test_two_step_in_a_mixed_ensemble_equals_single_steps(stencil):
     # whole-row tiles, several tiles per row, ragged widths and heights in one
     # launch, uneven parameters per replica, S(k) samples splitting pairs
-    shapes = [(40, 128), (33, 300), (20, 256), (17, 77), (9, 6)]
+    shapes = [(40, 128), (33, 300), (20, 256), (17, 77), (9, 6), (11, 1100)]
     plist = [fsc.make_params(D=2, nx=nx, ny=ny, stencil=stencil, precision="fp32",
                              T_hat=0.75 + 0.05 * k, rho0=0.6 + 0.2 * k, kBT=1e-4 * (k + 1),
                              seed=21, replica=k)
