@@ -372,6 +372,65 @@ def test_full_size_one_step_matches_oracle(case):
     assert_pop_close(got, ref, D, c["rho0"], c["precision"])
 
 
+def test_full_size_two_step_launch_matches_oracle():
+    # the 4096^2 E8 quench in the tiling the autotuner picks for it (the launch
+    # bench.py times): one launch of the temporally blocked kernel advances two steps
+    c = I.DEEP_QUENCH
+    shape = (c["ny"], c["nx"])
+    f0 = I.random_populations(9, shape, c["rho0"], 0.1, seed=22)
+    p = _params(2, shape, c["stencil"], c["precision"], T_hat=c["T_hat"], rho0=c["rho0"],
+                kBT=c["kBT"], seed=c["seed"])
+    with fsc.Lattice(p) as lat:
+        lat.set_populations(f0, 4321)
+        lat.autotune()
+        tiling = lat.tiling
+        lat.step(2)
+        got = lat.get_populations()
+        G = lat.G
+    print("tiling", tiling, flush=True)
+    ref = O.step(f0, 2, G=G, kind=c["stencil"], kBT=c["kBT"], seed=c["seed"], t0=4321)
+    del f0
+    assert_pop_close(got, ref, 2, c["rho0"], c["precision"])
+
+
+def test_bench_ensemble_launch_matches_oracle():
+    # the 64-replica ensemble of bench.py (sides 128, 256 and 512) in its
+    # autotuned launch configuration; replicas of every side start from random
+    # states and are compared with the oracle after two steps (one launch of a
+    # two-step tiling), the others from the flat state
+    reps = I.ensemble_replicas(n=64, seed=0, kBT=1e-13)
+    plist = [fsc.make_params(**{k: v for k, v in r.items() if k != "precision"}, precision="fp32")
+             for r in reps]
+    sample = []
+    for side in (128, 256, 512):
+        sample += [k for k, r in enumerate(reps) if r["nx"] == side][:2]
+    ens = fsc.Ensemble(plist)
+    ens.init_uniform()
+    f0 = {}
+    for k in sample:
+        shape = (reps[k]["ny"], reps[k]["nx"])
+        f0[k] = I.random_populations(9, shape, reps[k]["rho0"], 0.05, seed=40 + k)
+        ens.set_populations(k, f0[k])
+    ens.autotune()
+    tiling = ens.tiling
+    ens.run(2, 0)
+    print("tiling", tiling, flush=True)
+    for k in sample:
+        got = ens.get_populations(k)
+        G = O.coupling_from_reduced_temperature(reps[k]["T_hat"])
+        ref = O.step(f0[k], 2, G=G, kind=4, kBT=reps[k]["kBT"], seed=0, replica=k, t0=0)
+        assert_pop_close(got, ref, 2, reps[k]["rho0"], "fp32")
+    # a replica left flat stays flat up to the noise
+    flat = next(k for k in range(len(reps)) if k not in f0)
+    got = ens.get_populations(flat)
+    rf = reps[flat]
+    ref = O.step(O.uniform_state(2, (rf["ny"], rf["nx"]), rf["rho0"]), 2,
+                 G=O.coupling_from_reduced_temperature(rf["T_hat"]), kind=4, kBT=rf["kBT"], seed=0,
+                 replica=flat, t0=0)
+    assert_pop_close(got, ref, 2, rf["rho0"], "fp32")
+    ens.close()
+
+
 # ---------------------------------------------- statistics against theory ----
 @pytest.mark.parametrize("precision,T_hat,rho0,kBT", [("fp32", 0.9, 0.5, 1e-6),
                                                       ("fp32", 0.8, 0.62, 1e-13),
