@@ -117,6 +117,14 @@ int fail(fsc_ens *e, int code, const std::string &msg) {
     return code;
 }
 
+// Waits for the stream when a scope ends whose host buffers may still take
+// part in an enqueued copy (an early return after a failed call).  Declared
+// after those buffers, so that it runs before they are freed.
+struct StreamDrain {
+    hipStream_t s;
+    ~StreamDrain() { (void)hipStreamSynchronize(s); }
+};
+
 #define HIPCHK(ens, expr)                                                            \
     do {                                                                             \
         hipError_t _e = (expr);                                                      \
@@ -226,21 +234,35 @@ int init_rep(Rep &r, const fsc_params &p, void *ext_a, void *ext_b, fsc_ens *e) 
     return FSC_OK;
 }
 
+// Buffers of the S(k) sample: complex field, scratch and twiddle tables.  The
+// set counts as ready only when every part exists, so that a call that failed
+// half way is completed (or fails again) on the next request.
 int ensure_fft(Rep &r, fsc_ens *e) {
-    if (r.cbuf) return FSC_OK;
+    const int sides[3] = {r.p.nx, r.p.ny, r.p.nz};
+    bool ready = r.cbuf && r.ctmp;
+    for (int d = 0; d < r.p.D; ++d) ready = ready && r.tw[d];
+    if (ready) return FSC_OK;
+    for (int d = 0; d < r.p.D; ++d)
+        if (sides[d] > 8192) return fail(e, FSC_E_NOTSUP, "S(k) needs sides <= 8192");
     const size_t csz = 2 * r.esz * size_t(r.N);
-    if (hipMalloc(&r.cbuf, csz) != hipSuccess || hipMalloc(&r.ctmp, csz) != hipSuccess) {
+    if ((!r.cbuf && hipMalloc(&r.cbuf, csz) != hipSuccess) ||
+        (!r.ctmp && hipMalloc(&r.ctmp, csz) != hipSuccess)) {
         (void)hipGetLastError();
         return fail(e, FSC_E_OOM, "FFT buffer allocation failed");
     }
-    const int sides[3] = {r.p.nx, r.p.ny, r.p.nz};
     for (int d = 0; d < r.p.D; ++d) {
-        if (sides[d] > 8192) return fail(e, FSC_E_NOTSUP, "S(k) needs sides <= 8192");
-        if (hipMalloc(&r.tw[d], 2 * r.esz * twiddle_len(sides[d])) != hipSuccess) {
+        if (r.tw[d]) continue;
+        void *tw = nullptr;
+        if (hipMalloc(&tw, 2 * r.esz * twiddle_len(sides[d])) != hipSuccess) {
             (void)hipGetLastError();
             return fail(e, FSC_E_OOM, "twiddle allocation failed");
         }
-        HIPCHK(e, launch_twiddles(r.p.precision, r.tw[d], sides[d], e->stream));
+        const hipError_t ec = launch_twiddles(r.p.precision, tw, sides[d], e->stream);
+        if (ec != hipSuccess) {
+            (void)hipFree(tw);
+            return fail(e, FSC_E_HIP, std::string("twiddles: ") + hipGetErrorString(ec));
+        }
+        r.tw[d] = tw;
     }
     return FSC_OK;
 }
@@ -495,6 +517,7 @@ int upload_desc(fsc_ens *e) {
     }
     std::vector<int> tb(n);
     for (size_t k = 0; k < n; ++k) tb[k] = e->desc[k].tile_begin;
+    StreamDrain drain{e->stream};
     HIPCHK(e, hipMemcpyAsync(e->d_desc, e->desc.data(), sizeof(RepDesc) * n, hipMemcpyHostToDevice,
                              e->stream));
     HIPCHK(e, hipMemcpyAsync(e->d_tile_begin, tb.data(), sizeof(int) * n, hipMemcpyHostToDevice,
@@ -706,7 +729,10 @@ int ens_run(fsc_ens *e, int64_t nsteps, int64_t sk_every) {
             HIPCHK(e, hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
             int rc = enqueue_steps(e, parity, chunk, sk_every, &ge.samples, &ge.flips);
             hipError_t ec = hipStreamEndCapture(e->stream, &graph);
-            if (rc) return rc;
+            if (rc) {
+                if (ec == hipSuccess) (void)hipGraphDestroy(graph);
+                return rc;
+            }
             if (ge.flips) {
                 (void)hipGraphDestroy(graph);
                 return fail(e, FSC_E_STATE, "graph chunk with an odd number of launches");
@@ -901,6 +927,7 @@ int ens_read_sk(fsc_ens *e, int ri, int kind, double *sum, double *sumsq, int64_
     const double *s = kind == FSC_SK_AXIS ? r.d_sk : r.d_sk + 2 * na;
     const double *q = kind == FSC_SK_AXIS ? r.d_sk + na : r.d_sk + 2 * na + r.n_rad;
     std::vector<double> hs(nb), hq(nb);
+    StreamDrain drain{e->stream};
     HIPCHK(e, hipMemcpyAsync(hs.data(), s, sizeof(double) * nb, hipMemcpyDeviceToHost, e->stream));
     HIPCHK(e, hipMemcpyAsync(hq.data(), q, sizeof(double) * nb, hipMemcpyDeviceToHost, e->stream));
     HIPCHK(e, hipStreamSynchronize(e->stream));
@@ -985,6 +1012,7 @@ int ens_save(fsc_ens *e, const char *path) {
     const int par = e->cur;
     std::vector<unsigned char> raw;
     std::vector<double> acc;
+    StreamDrain drain{e->stream};
     for (size_t k = 0; ok && k < e->reps.size(); ++k) {
         Rep &r = e->reps[k];
         const uint64_t nsk = sk_len(r);
@@ -1036,15 +1064,21 @@ int ens_load(fsc_ens *e, const char *path) {
         if (!get(raws[k].data(), nbytes) || !get(accs[k].data(), sizeof(double) * nsk))
             return fail(e, FSC_E_IO, "truncated checkpoint");
     }
+    // the host vectors must outlive the copies: wait for the stream before
+    // returning, also after a failed call
     const int par = e->cur;
-    for (size_t k = 0; k < n; ++k) {
+    hipError_t ec = hipSuccess;
+    for (size_t k = 0; k < n && ec == hipSuccess; ++k) {
         Rep &r = e->reps[k];
-        HIPCHK(e, hipMemcpyAsync(r.buf[par], raws[k].data(), raws[k].size(), hipMemcpyHostToDevice,
-                                 e->stream));
-        HIPCHK(e, hipMemcpyAsync(r.d_sk, accs[k].data(), sizeof(double) * accs[k].size(),
-                                 hipMemcpyHostToDevice, e->stream));
-        r.nsamples = ns[k];
+        ec = hipMemcpyAsync(r.buf[par], raws[k].data(), raws[k].size(), hipMemcpyHostToDevice, e->stream);
+        if (ec == hipSuccess)
+            ec = hipMemcpyAsync(r.d_sk, accs[k].data(), sizeof(double) * accs[k].size(),
+                                hipMemcpyHostToDevice, e->stream);
     }
+    const hipError_t es = hipStreamSynchronize(e->stream);
+    if (ec == hipSuccess) ec = es;
+    if (ec != hipSuccess) return fail(e, FSC_E_HIP, std::string("checkpoint upload: ") + hipGetErrorString(ec));
+    for (size_t k = 0; k < n; ++k) e->reps[k].nsamples = ns[k];
     return set_step_device(e, step);
 }
 

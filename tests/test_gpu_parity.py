@@ -193,6 +193,15 @@ def test_rejects_bad_parameters():
         lat.init_uniform()
         with pytest.raises(fsc.FscError):
             lat.step(-1)
+    # S(k) of a side beyond the FFT limit is refused, again on a second request
+    # (a refusal leaves no half-built sample buffers behind), and steps still run
+    with fsc.Lattice(_params(2, (2, 8200), 4, "fp32")) as lat:
+        lat.init_uniform()
+        for _ in range(2):
+            with pytest.raises(fsc.FscError, match="8192"):
+                lat.measure_sk()
+        lat.step(3)
+        assert lat.stats()["bad"] == 0
 
 
 # -------------------------------------------------------------- S(k) --------
