@@ -59,7 +59,8 @@ def kernel_name(stencil: str, noise: bool, tiling: dict) -> str:
     n = "true" if noise else "false"
     if tiling.get("steps", 1) == 2:  # prefetch field 0/1: one or two barriers per row
         return f"k_step2<{stencil}, float, {n}, {tiling['tx']}, {tiling['pf'] + 1}>"
-    return f"k_step<D2Q9, {stencil}, float, {n}, {tiling['tx']}, {tiling['ty']}, {tiling['pf']}>"
+    # the last argument: buffers below 4 GiB (one buffer resource for all populations)
+    return f"k_step<D2Q9, {stencil}, float, {n}, {tiling['tx']}, {tiling['ty']}, {tiling['pf']}, false>"
 
 
 def grid_threads(tiling: dict) -> int:

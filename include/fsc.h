@@ -101,8 +101,10 @@ typedef struct fsc_ens fsc_ens;
 
 /* Creates a context and allocates its two population buffers (pull
  * streaming ping-pong).  `stream` is a hipStream_t or NULL.  The state is
- * undefined until fsc_init_uniform or fsc_set_populations.  Errors:
- * FSC_E_INVAL (bad parameters), FSC_E_NOTSUP (E8 in 3D), FSC_E_OOM, FSC_E_HIP. */
+ * undefined until fsc_init_uniform or fsc_set_populations.  One population
+ * (nx ny nz values) must stay below 4 GiB: up to about 1000^3 nodes in FP32,
+ * 800^3 in FP64.  Errors: FSC_E_INVAL (bad parameters, lattice too large),
+ * FSC_E_NOTSUP (E8 in 3D), FSC_E_OOM, FSC_E_HIP. */
 int fsc_create(const fsc_params *p, void *stream, fsc_ctx **out);
 
 /* As fsc_create, but uses two caller-owned device buffers of at least
@@ -367,7 +369,8 @@ int fsc_tile_shapes(int D, int stencil, int precision, int *out4, int max);
  * marching length chosen to give about target_blocks (>= 1) workgroups per
  * launch.  Results do not depend on it.  FSC_E_INVAL for a tiling that is not
  * compiled for the lattice, or a two-step tiling on a lattice narrower than
- * 2R + 2 columns (R = 1 for E4, 2 for E8). */
+ * 2R + 2 columns (R = 1 for E4, 2 for E8) or with population buffers of
+ * 4 GiB or more (those run single steps). */
 int fsc_set_tiling(fsc_ctx *ctx, int tx, int ty, int pf, int steps, int64_t target_blocks);
 int fsc_ens_set_tiling(fsc_ens *ens, int tx, int ty, int pf, int steps, int64_t target_blocks);
 

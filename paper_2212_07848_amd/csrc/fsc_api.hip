@@ -67,6 +67,9 @@ struct Rep {
     Geometry geom() const { return Geometry{p.D, p.nx, p.ny, p.nz, N}; }
 };
 
+// a population buffer of 4 GiB or more: beyond one 32-bit buffer resource
+bool wide_buffer(const Rep &r) { return uint64_t(r.esz) * uint64_t(r.Q) * uint64_t(r.N) >= 0xffffffffull; }
+
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     int64_t samples = 0;
@@ -157,9 +160,11 @@ int resolve_params(const fsc_params &in, fsc_params &out, std::string &err) {
         out.T_hat = in.G != 0.0 ? std::exp(2.0) * CS2 / in.G : INFINITY;
     }
     const int64_t N = int64_t(in.nx) * in.ny * in.nz;
-    // kernels address a population buffer with 32-bit byte offsets
+    // the step kernels address one population (N values) with 32-bit byte
+    // offsets; buffers of 4 GiB or more take one buffer resource per population
     const int64_t esz = in.precision == FSC_FP64 ? 8 : 4;
-    if (N * q_of(in.D) * esz >= (int64_t(1) << 32) - 1) return err = "lattice too large", FSC_E_INVAL;
+    if (N * esz >= (int64_t(1) << 32) - 1)
+        return err = "lattice too large (one population must stay below 4 GiB)", FSC_E_INVAL;
     return FSC_OK;
 }
 
@@ -553,6 +558,8 @@ StepLaunch make_launch(fsc_ens *e, int parity, uint32_t off) {
     L.stencil = e->stencil;
     L.precision = e->precision;
     L.noise = e->noise;
+    L.wide = false;
+    for (const auto &r : e->reps) L.wide = L.wide || wide_buffer(r);
     L.tile = e->tile;
     return L;
 }
@@ -594,11 +601,13 @@ int enqueue_steps(fsc_ens *e, int cur, int64_t n, int64_t sk_every, int64_t *sam
 }
 
 // Two-step tilings need 2D FP32 lattices at least 2R + 2 columns wide.
+// the two-step kernel addresses a whole buffer with 32-bit offsets, and needs
+// 2R + 2 columns
 bool two_step_ok(const fsc_ens *e) {
     if (e->D != 2 || e->precision != FSC_FP32_SHIFTED) return false;
     const int R = e->stencil == FSC_E8 ? 2 : 1;
     for (const auto &r : e->reps)
-        if (r.p.nx < 2 * R + 2) return false;
+        if (r.p.nx < 2 * R + 2 || wide_buffer(r)) return false;
     return true;
 }
 
@@ -1361,7 +1370,8 @@ static int set_tiling(fsc_ens *e, int tx, int ty, int pf, int steps, int64_t tar
     for (int i = 0; i < n; ++i)
         if (t[i].tx == tx && t[i].ty == ty && t[i].pf == pf && t[i].steps == steps) {
             if (steps == 2 && !two_step_ok(e))
-                return fail(e, FSC_E_INVAL, "two-step tiling needs sides of at least 2R + 2 columns");
+                return fail(e, FSC_E_INVAL,
+                            "two-step tiling needs sides of at least 2R + 2 columns and buffers below 4 GiB");
             e->tile = t[i];
             e->target_blocks = target_blocks;
             drop_graphs(e);

@@ -28,6 +28,7 @@ struct StepLaunch {
     uint32_t step_off;
     int D, stencil, precision; // selects the instantiation
     bool noise;
+    bool wide;                 // a replica's buffers reach 4 GiB (single-step kernel only)
     TileShape tile;
 };
 

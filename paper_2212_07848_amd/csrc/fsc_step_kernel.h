@@ -300,7 +300,10 @@ __device__ __forceinline__ void collide_d3q19(real (&f)[19], real rho0, const re
 // ---------------------------------------------------------------------------
 // The step kernel.
 // ---------------------------------------------------------------------------
-template <class L, class ST, typename real, bool NOISE, int TX, int TY, int PF = 2>
+// WIDE: the population buffers reach 4 GiB, and each population is addressed
+// through a buffer resource of its own (a separate instantiation, so that the
+// common form keeps its registers).
+template <class L, class ST, typename real, bool NOISE, int TX, int TY, int PF = 2, bool WIDE = false>
 __global__ void __launch_bounds__(TX *TY)
     k_step(const RepDesc *__restrict__ reps, const int *__restrict__ tile_begin, int nrep,
            int parity, const uint64_t *__restrict__ step_base, uint32_t step_off) {
@@ -349,7 +352,15 @@ __global__ void __launch_bounds__(TX *TY)
     const uint64_t buf_bytes = uint64_t(Q) * uint64_t(d.N) * sizeof(real);
     const rsrc_t src = make_rsrc(d.buf[parity], buf_bytes);
     const rsrc_t dst = make_rsrc(d.buf[parity ^ 1], buf_bytes);
-    const uint32_t pop_bytes = uint32_t(d.N) * ES;  // < 2^31 (checked on the host)
+    // one population is below 4 GiB (checked on the host); a buffer of 4 GiB
+    // or more is addressed with one resource per population, so that every
+    // byte offset stays 32-bit
+    const uint32_t pop_bytes = uint32_t(d.N) * ES;
+    constexpr bool wide = WIDE;
+    const uint64_t pop_bytes64 = uint64_t(d.N) * ES;
+    auto pop_rsrc = [&](const void *base, int i) {
+        return make_rsrc(static_cast<const char *>(base) + uint64_t(i) * pop_bytes64, pop_bytes64);
+    };
 
     constexpr bool F32 = sizeof(real) == 4;
     const real rho0 = F32 ? real(d.rho0f) : real(d.rho0);
@@ -429,9 +440,15 @@ __global__ void __launch_bounds__(TX *TY)
         const int pc = wrap_plane(p);
         const int pp = pc + 1 == ns ? 0 : pc + 1, pm = pc == 0 ? ns - 1 : pc - 1;
         const uint32_t pb[3] = {uint32_t(pp) * pbytes, uint32_t(pc) * pbytes, uint32_t(pm) * pbytes};
+        if constexpr (wide) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            out[i] = bload<real>(src, xo[c1(i) + 1][c0(i) + 1], uint32_t(i) * pop_bytes + pb[cm(i) + 1]);
+            for (int i = 0; i < Q; ++i)
+                out[i] = bload<real>(pop_rsrc(d.buf[parity], i), xo[c1(i) + 1][c0(i) + 1], pb[cm(i) + 1]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                out[i] = bload<real>(src, xo[c1(i) + 1][c0(i) + 1], uint32_t(i) * pop_bytes + pb[cm(i) + 1]);
+        }
     };
     auto dpsi_of = [&](const real (&fv)[Q]) {
         real dn = real(0);
@@ -539,17 +556,27 @@ __global__ void __launch_bounds__(TX *TY)
             else collide_d3q19<real, NOISE>(fv, rho0, Fv, lc, ac, z);
 
             const uint32_t so = uint32_t(s) * pbytes + lane_store;
+            if constexpr (wide) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) bstore(dst, so, uint32_t(i) * pop_bytes, fv[i]);
+                for (int i = 0; i < Q; ++i) bstore(pop_rsrc(d.buf[parity ^ 1], i), so, 0u, fv[i]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) bstore(dst, so, uint32_t(i) * pop_bytes, fv[i]);
+            }
         }
     }
 }
 
 template <class L, class ST, typename real, bool NOISE, int TX, int TY, int PF>
 inline hipError_t launch_one(const StepLaunch &P, hipStream_t s) {
-    hipLaunchKernelGGL((k_step<L, ST, real, NOISE, TX, TY, PF>), dim3(P.total_tiles),
-                       dim3(TX * TY), 0, s, P.reps, P.tile_begin, P.nrep, P.parity, P.step_base,
-                       P.step_off);
+    if (P.wide)
+        hipLaunchKernelGGL((k_step<L, ST, real, NOISE, TX, TY, PF, true>), dim3(P.total_tiles),
+                           dim3(TX * TY), 0, s, P.reps, P.tile_begin, P.nrep, P.parity, P.step_base,
+                           P.step_off);
+    else
+        hipLaunchKernelGGL((k_step<L, ST, real, NOISE, TX, TY, PF, false>), dim3(P.total_tiles),
+                           dim3(TX * TY), 0, s, P.reps, P.tile_begin, P.nrep, P.parity, P.step_base,
+                           P.step_off);
     return hipGetLastError();
 }
 
