@@ -471,7 +471,7 @@ def main():
         print(f"{len(doc['entries'])} step-kernel launch shapes, calibration {doc['calibration']}")
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

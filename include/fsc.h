@@ -53,7 +53,7 @@ extern "C" {
 #define FSC_E_OOM (-3)      /* device or host allocation failed */
 #define FSC_E_DIVERGED (-4) /* non-finite or non-positive density detected */
 #define FSC_E_STATE (-5)    /* call not valid in the current state */
-#define FSC_E_NOTSUP (-6)   /* combination not supported by this build */
+#define FSC_E_NOTSUP (-6)   /* combination not supported by the library */
 #define FSC_E_IO (-7)       /* checkpoint file missing, unreadable, truncated or corrupt */
 
 #define FSC_E4 4 /* 2D: |e|^2 in {1,2} (8 neighbours); 3D: {1,2} (18) */

@@ -273,7 +273,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 
 /* ------------------------------------------------------------------------ */
 /* Thermal-noise normals.  The paper fixes only that the noise is Gaussian  */
-/* and uncorrelated in space and time; the generator is this build's        */
+/* and uncorrelated in space and time; the generator is the library's own  */
 /* choice and is stated exactly so that two independent implementations can */
 /* agree on it:                                                             */
 /*   words w_0, w_1, ... : Philox4x32-10 outputs of blocks 0, 1, ..., with   */

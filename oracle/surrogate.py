@@ -2,7 +2,7 @@
 
 The surrogate advances the block-averaged density of a phase-separating run
 by a fixed number of lattice steps.  It is not part of the paper; its
-definition (this build's) is:
+definition (the library's own) is:
 
   x_0    = (rho - mean) / in_scale                          input normalisation
   x_1    = (rho - prev) / out_scale                         last increment (K = 2)
