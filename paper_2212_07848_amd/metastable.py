@@ -150,13 +150,15 @@ def main(argv=None):
     ap.add_argument("--seeds", type=int, default=8)
     ap.add_argument("--d-meta", type=float, default=1.3e-3)
     ap.add_argument("--max-steps", type=int, default=400000)
+    ap.add_argument("--meta-kbt", default="6e-4,5e-4,4e-4,3.5e-4,3e-4,2.5e-4,1e-13",
+                    help="comma-separated k_B theta values of the metastable state")
     ap.add_argument("--out", default=os.path.join(os.getcwd(), "metastable_study.json"))
     a = ap.parse_args(argv)
     sp = state_points(d_meta=a.d_meta)
     say = lambda s: print(s, flush=True)
     uns = run(sp["unstable"], [1e-3, 1e-5, 1e-7, 1e-9, 1e-11, 1e-13], seeds=a.seeds, n=a.n,
               max_steps=4000, check_every=5, log=say)
-    met = run(sp["metastable"], [6e-4, 5e-4, 4e-4, 3.5e-4, 3e-4, 2.5e-4, 1e-13], seeds=a.seeds,
+    met = run(sp["metastable"], [float(v) for v in a.meta_kbt.split(",")], seeds=a.seeds,
               n=a.n, max_steps=a.max_steps, check_every=100, log=say)
     s, k = growth_rate(sp["unstable"], 0.8)
     res = dict(unstable=uns, metastable=met, growth_rate=s, k_fastest=k,
