@@ -177,10 +177,15 @@ def main(argv=None):
     ap.add_argument("--max-steps", type=int, default=80000)
     ap.add_argument("--check-every", type=int, default=2000)
     ap.add_argument("--seeds", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=11, help="noise seed (replica ids 0, 1, ...)")
+    ap.add_argument("--fractions", default=",".join(str(f) for f in DEFAULT_FRACTIONS),
+                    help="comma-separated fractions of the interval between the spinodals")
     ap.add_argument("--out", default=os.path.join(os.getcwd(), "topology_study.json"))
     a = ap.parse_args(argv)
-    res = run(default_densities(), n=a.n, max_steps=a.max_steps, check_every=a.check_every,
-              seeds=a.seeds, log=lambda s: print(s[:200], flush=True))
+    fr = tuple(float(f) for f in a.fractions.split(","))
+    res = run(default_densities(fractions=fr), n=a.n, max_steps=a.max_steps,
+              check_every=a.check_every, seed=a.seed, seeds=a.seeds,
+              log=lambda s: print(s[:200], flush=True))
     with open(a.out, "w") as fh:
         json.dump(res, fh, indent=1)
     for c in res["counts"]:
