@@ -144,6 +144,18 @@ def ingest_pmc(fetch_csv: str, write_csv: str, valu_csv: str, out_path: str):
                             valu_insts_per_launch=int(valu[key]) if key in valu else None))
     for e in entries:
         e["kernel"] = e["kernel"].replace("fsc::", "")
+    # kept: every launch shape (march length) of the ensemble's two-step kernels
+    # (the roofline reads the autotuner's choice among them), and of every other
+    # kernel the shape with the most launches (the one timed; the others are
+    # tuning trials)
+    ens = "k_step2<StencilE4_2D, float, true,"
+    best = {}
+    for e in entries:
+        if not e["kernel"].startswith(ens):
+            if e["kernel"] not in best or e["launches"] > best[e["kernel"]]["launches"]:
+                best[e["kernel"]] = e
+    entries = [e for e in entries if e["kernel"].startswith(ens)] + sorted(best.values(),
+                                                                          key=lambda e: e["kernel"])
     doc = dict(kernel_hash=kernel_hash(),
                commands=[f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch_dir> -o run "
                          f"-- python3 bench.py {PMC_ARGS}",
