@@ -104,7 +104,9 @@ def coupling(T_hat):
 
 def h_axis(k, stencil=4):
     """h(k) of the on-axis sound speed, sum_a w_a e_x sin(k e_x) / (2 tan(k/2)),
-    for the 2D interaction sets (weights normalised to sum w e_x^2 = 1)."""
+    for the interaction sets (weights normalised to sum w e_x^2 = 1).  E4 gives
+    the same h in 2D and 3D: the neighbours with e_x = 1 weigh 1/3 + 2/12 in 2D
+    and 1/6 + 4/12 in 3D, 1/2 either way."""
     if stencil == 4:
         sets = [(1, 1.0 / 3.0 + 2.0 / 12.0)]  # e_x = 1: (1,0) and (1,+-1)
     else:
@@ -173,18 +175,19 @@ def state_points(T_spin=0.8, spin_d=DEFAULT_SPINODAL_D, bin_T=DEFAULT_BINODAL_T)
 
 
 def run(points, n=64, seeds=4, kBT=1e-13, burn=4000, steps=16000, sk_every=50, kfit=6,
-        seed_base=7000, stream=None):
-    """One ensemble of len(points) x seeds replicas of n^2 D2Q9 FP32 lattices
-    (E4, BGK tau = 1).  After `burn` steps the S(k) accumulators are reset;
-    then `steps` steps with a sample every `sk_every`.  Returns the points
-    with the measured axis S(k) (mean over seeds, axes and +-k), the fitted
-    and exact S(0), and the lattice wall time."""
+        seed_base=7000, stream=None, D=2):
+    """One ensemble of len(points) x seeds replicas of n^D FP32 lattices
+    (D2Q9 or D3Q19, E4, BGK tau = 1).  After `burn` steps the S(k)
+    accumulators are reset; then `steps` steps with a sample every
+    `sk_every`.  Returns the points with the measured axis S(k) (mean over
+    seeds, axes and +-k), the fitted and exact S(0), and the lattice wall
+    time."""
     plist = []
     for i, p in enumerate(points):
         for s in range(seeds):
-            plist.append(F.make_params(D=2, nx=n, ny=n, stencil=4, precision="fp32",
-                                       T_hat=p["T_hat"], rho0=p["rho0"], kBT=kBT,
-                                       seed=seed_base + i, replica=s))
+            plist.append(F.make_params(D=D, nx=n, ny=n, nz=n if D == 3 else 1, stencil=4,
+                                       precision="fp32", T_hat=p["T_hat"], rho0=p["rho0"],
+                                       kBT=kBT, seed=seed_base + i, replica=s))
     ens = F.Ensemble(plist, stream=stream)
     ens.init_uniform()
     t0 = time.perf_counter()
@@ -211,7 +214,7 @@ def run(points, n=64, seeds=4, kBT=1e-13, burn=4000, steps=16000, sk_every=50, k
         q.update(k=k.tolist(), S=Sk.tolist(), S_exact=ex.tolist(),
                  S0_fit=float(fit_s0(k[:kfit], Sk[:kfit])),
                  S0_exact=s0_exact(p["rho0"], p["T_hat"], kBT),
-                 samples=int(cnt[0] / (2 * seeds)))
+                 samples=int(cnt[0] / (2 * D * seeds)))
         out.append(q)
     ens.close()
     return out, wall
@@ -243,6 +246,7 @@ def main(argv=None):
     import argparse
 
     ap = argparse.ArgumentParser(description="S(k -> 0) scaling near the spinodal and the critical point")
+    ap.add_argument("--dim", type=int, default=2, choices=(2, 3))
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--seeds", type=int, default=32)
     ap.add_argument("--burn", type=int, default=4000)
@@ -250,9 +254,9 @@ def main(argv=None):
     ap.add_argument("--out", default=os.path.join(os.getcwd(), "scaling_study.json"))
     a = ap.parse_args(argv)
     pts = state_points()
-    res, wall = run(pts, n=a.n, seeds=a.seeds, burn=a.burn, steps=a.steps)
+    res, wall = run(pts, n=a.n, seeds=a.seeds, burn=a.burn, steps=a.steps, D=a.dim)
     ex = exponents(res)
-    doc = dict(n=a.n, seeds=a.seeds, burn=a.burn, steps=a.steps, kBT=1e-13,
+    doc = dict(D=a.dim, n=a.n, seeds=a.seeds, burn=a.burn, steps=a.steps, kBT=1e-13,
                lattice_seconds=wall, exponents=ex, points=res)
     with open(a.out, "w") as fh:
         json.dump(doc, fh, indent=1)

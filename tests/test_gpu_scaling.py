@@ -26,3 +26,15 @@ def test_scaling_study_reduced():
     print(ex, "lattice seconds", wall)
     for key, e in ex.items():
         assert abs(e["measured"] - e["exact_same_points"]) < 0.06, (key, e)
+
+
+def test_scaling_3d_axis_sk_matches_eq16():
+    # D3Q19 (the paper's runs are 3D): the axis S(k) of a few state points
+    # against Eq. 16, whose on-axis form is the same as in 2D for E4
+    pts = SC.state_points(T_spin=0.8, spin_d=(0.1, 0.01), bin_T=(0.9,))
+    res, wall = SC.run(pts, n=24, seeds=8, burn=3000, steps=12000, sk_every=40, D=3)
+    for r in res:
+        S, ex = np.array(r["S"]), np.array(r["S_exact"])
+        print(r["kind"], r["side"], r["d"], np.round(S / ex, 3))
+        assert np.max(np.abs(S / ex - 1)) < 0.1, (r["kind"], r["side"], r["d"])
+        assert abs(r["S0_fit"] / r["S0_exact"] - 1) < 0.1
