@@ -54,13 +54,13 @@ def bytes_per_lup(D: int, precision: str) -> int:
     return 2 * Q * (4 if precision == "fp32" else 8)
 
 
-def kernel_name(stencil: str, noise: bool, tiling: dict) -> str:
+def kernel_name(stencil: str, noise: bool, tiling: dict, lattice: str = "D2Q9") -> str:
     """Name of the step kernel a tiling launches (as rocprofv3 reports it)."""
     n = "true" if noise else "false"
     if tiling.get("steps", 1) == 2:  # prefetch field 0/1: one or two barriers per row
         return f"k_step2<{stencil}, float, {n}, {tiling['tx']}, {tiling['pf'] + 1}>"
     # the last argument: buffers below 4 GiB (one buffer resource for all populations)
-    return f"k_step<D2Q9, {stencil}, float, {n}, {tiling['tx']}, {tiling['ty']}, {tiling['pf']}, false>"
+    return f"k_step<{lattice}, {stencil}, float, {n}, {tiling['tx']}, {tiling['ty']}, {tiling['pf']}, false>"
 
 
 def grid_threads(tiling: dict) -> int:
@@ -68,7 +68,7 @@ def grid_threads(tiling: dict) -> int:
     return tiling["blocks"] * (tiling["tx"] * tiling["ty"] + extra)
 
 
-def counters_from_profile(stencil: str, noise: bool, tiling: dict):
+def counters_from_profile(stencil: str, noise: bool, tiling: dict, lattice: str = "D2Q9"):
     """Counter measurements of the step kernel per launch (HBM bytes:
     FETCH_SIZE + WRITE_SIZE scaled by the counters' reading of a plain copy of
     known size; VALU wave-instructions: SQ_INSTS_VALU) from the committed
@@ -81,7 +81,7 @@ def counters_from_profile(stencil: str, noise: bool, tiling: dict):
         doc = json.load(fh)
     if doc.get("kernel_hash") != kernel_hash():
         return None
-    name = kernel_name(stencil, noise, tiling)
+    name = kernel_name(stencil, noise, tiling, lattice)
     threads = grid_threads(tiling)
     same = [e for e in doc["entries"] if e["kernel"].endswith(name)]
     for e in same:
@@ -353,10 +353,25 @@ def run_single(cfg, steps, torch, fsc, kBT=None):
     lat.close()
     n = cfg["nx"] * cfg["ny"] * cfg["nz"]
     # algorithmic bandwidth: one read and one write of every population per update
-    return dict(mlups=n / t / 1e6,
-                algorithmic_gbs=n * bytes_per_lup(cfg["D"], cfg["precision"]) / t / 1e9,
-                ms_per_step=t * 1e3, tiling=f"{tiling['tx']}x{tiling['ty']}/pf{tiling['pf']}"
-                                              f"/{tiling['blocks']}blk/{tiling['steps']}step")
+    out = dict(mlups=n / t / 1e6,
+               algorithmic_gbs=n * bytes_per_lup(cfg["D"], cfg["precision"]) / t / 1e9,
+               ms_per_step=t * 1e3, tiling=f"{tiling['tx']}x{tiling['ty']}/pf{tiling['pf']}"
+                                             f"/{tiling['blocks']}blk/{tiling['steps']}step")
+    # counter figures of the same kernel from the committed summary, if present
+    stencil = {(2, 4): "StencilE4_2D", (2, 8): "StencilE8_2D", (3, 4): "StencilE4_3D"}[
+        (cfg["D"], cfg["stencil"])]
+    noise = (cfg["kBT"] if kBT is None else kBT) > 0
+    cnt = counters_from_profile(stencil, noise, tiling, "D2Q9" if cfg["D"] == 2 else "D3Q19")
+    if cnt and cfg["precision"] == "fp32":
+        entry, note = cnt
+        t_launch = t * tiling.get("steps", 1)
+        lups = n * tiling.get("steps", 1)
+        out["measured_bytes_per_lup"] = entry["bytes_per_launch"] / lups
+        out["measured_hbm_gbs"] = entry["bytes_per_launch"] / t_launch / 1e9
+        if entry.get("valu_insts_per_launch"):
+            out["valu_issue_frac"] = entry["valu_insts_per_launch"] * 64 / t_launch / 1e12 / VALU_PEAK_TOPS
+        out["counters"] = note
+    return out
 
 
 def copy_ceiling(torch, fsc, nbytes=1 << 30, reps=20):
