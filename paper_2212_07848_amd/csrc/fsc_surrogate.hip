@@ -1,7 +1,7 @@
 // fsc_surrogate.hip -- learned coarse-grained surrogate of the phase-separating
 // lattice: a small periodic convolutional network that maps the block-averaged
 // density at time t to the one at t + k lattice steps.  Not part of the paper:
-// it is the inference/training path next to the lattice, judged against the
+// it is the inference/training path next to the lattice, assessed against the
 // lattice's own S(k, t) and L(t).
 //
 // Network (C = 32 hidden channels, L layers, K = 1 or 2 input channels):
