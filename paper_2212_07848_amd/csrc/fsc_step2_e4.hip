@@ -13,6 +13,11 @@ hipError_t launch_step2_e4(const StepLaunch &P, hipStream_t s) {
                               : launch_two<StencilE4_2D, float, true, 128, 1>(P, s))
                        : (two ? launch_two<StencilE4_2D, float, false, 128, 2>(P, s)
                               : launch_two<StencilE4_2D, float, false, 128, 1>(P, s));
+    if (P.tile.tx == 192)
+        return P.noise ? (two ? launch_two<StencilE4_2D, float, true, 192, 2>(P, s)
+                              : launch_two<StencilE4_2D, float, true, 192, 1>(P, s))
+                       : (two ? launch_two<StencilE4_2D, float, false, 192, 2>(P, s)
+                              : launch_two<StencilE4_2D, float, false, 192, 1>(P, s));
     if (P.tile.tx == 256)
         return P.noise ? (two ? launch_two<StencilE4_2D, float, true, 256, 2>(P, s)
                               : launch_two<StencilE4_2D, float, true, 256, 1>(P, s))

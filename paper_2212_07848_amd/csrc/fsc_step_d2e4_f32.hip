@@ -19,6 +19,10 @@ hipError_t launch_step_d2e4_f32(const StepLaunch &P, hipStream_t s) {
     if (P.tile.tx == 256 && P.tile.ty == 1 && P.tile.pf == 1)
         return P.noise ? launch_one<D2Q9, StencilE4_2D, float, true, 256, 1, 1>(P, s)
                        : launch_one<D2Q9, StencilE4_2D, float, false, 256, 1, 1>(P, s);
+    // the single steps of a run on the 192-wide two-step tiling
+    if (P.tile.tx == 192 && P.tile.ty == 1 && P.tile.pf == 1)
+        return P.noise ? launch_one<D2Q9, StencilE4_2D, float, true, 192, 1, 1>(P, s)
+                       : launch_one<D2Q9, StencilE4_2D, float, false, 192, 1, 1>(P, s);
     return hipErrorInvalidValue;
 }
 

@@ -63,7 +63,7 @@ def test_tiling_table_is_host_only_and_consistent():
         # the temporally blocked kernel exists for 2D FP32 only, in both LDS schedules
         assert bool(two) == (D == 2 and prec == "fp32")
         if two:
-            assert {s[2] for s in two} == {0, 1} and {s[0] for s in two} == {128, 256}
+            assert {s[2] for s in two} == {0, 1} and {s[0] for s in two} == {128, 192, 256}
         assert shapes[0][3] == 1  # the default is a single-step tiling
     with pytest.raises(fsc.FscError):
         fsc.tile_shapes(3, 8, "fp32")
