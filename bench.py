@@ -472,7 +472,8 @@ def run_surrogate(torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
+    # the ensemble workload's own length: 20 000 steps per replica (about 2 s)
+    ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=400)
     ap.add_argument("--kernel-steps", type=int, default=1000)
     ap.add_argument("--replicas", type=int, default=64)
