@@ -21,6 +21,15 @@ batch of (yhat - (target - rho) / out_scale)^2.
 
 Parameters are one flat float vector, per layer: weights [C_out][C_in][3][3]
 then biases [C_out].
+
+With bf16=True, forward and loss_and_grad round to bfloat16 (round to nearest,
+ties to even, of the FP32 value) exactly the operands the library keeps in
+that format, and nothing else: the weights of the C -> C layers; the hidden
+activations a_l = SiLU(z_l); and, in the backward pass, the pre-activation
+gradients of the hidden layers.  The first and last layers' weights, the
+pre-activations z, the input channels and all sums stay in (here) FP64.  The
+result differs from the library only by its FP32 sums and SiLU, and by the
+rare BF16 rounding that those move across a rounding boundary.
 """
 from __future__ import annotations
 
@@ -81,6 +90,30 @@ def conv3x3_weight_grad(g: np.ndarray, x: np.ndarray):
     return dW, g.sum(axis=(0, 2, 3))
 
 
+def bf16_round(x):
+    """bfloat16 value nearest to float32(x), ties to even, as float64.
+
+    bfloat16 keeps the sign, the 8 exponent bits and the top 7 mantissa bits
+    of an IEEE float32.  Rounding adds 0x7FFF plus the lowest kept bit to the
+    32-bit pattern and truncates to the top 16 bits: below half an ulp rounds
+    down, above rounds up, an exact half rounds to the even pattern; a carry
+    out of the mantissa moves to the next binade and past the largest finite
+    value to infinity.  NaN stays NaN (quiet); infinities and zeros keep their
+    sign; float32 subnormals round on the same bit grid."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    lsb = (b >> np.uint64(16)) & np.uint64(1)
+    r = ((b + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) & np.uint64(0xFFFF)
+    nan = np.isnan(f)
+    r = np.where(nan, ((b >> np.uint64(16)) | np.uint64(0x0040)) & np.uint64(0xFFFF), r)
+    return (r.astype(np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)
+
+
+def bf16_bits(x):
+    """16-bit pattern of bf16_round(x)."""
+    return (bf16_round(x).astype(np.float32).view(np.uint32) >> np.uint32(16)).astype(np.uint16)
+
+
 def silu(z):
     return z / (1.0 + np.exp(-z))
 
@@ -98,11 +131,20 @@ def network_input(rho, prev, mean, in_scale, out_scale):
     return np.stack(chans, axis=1)
 
 
-def forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=False, prev=None):
-    """rho (and prev for two-channel networks): [B, H, W] -> prediction [B, H, W]
-    (and the intermediates)."""
-    in_ch = 1 if prev is None else 2
+def _layers(params, channels, layers, in_ch, bf16):
     P = unpack(np.asarray(params, dtype=np.float64), channels, layers, in_ch)
+    if bf16:
+        # the C -> C layers' weights feed the matrix cores in bfloat16
+        P = [(bf16_round(W) if 0 < l < layers - 1 else W, b) for l, (W, b) in enumerate(P)]
+    return P
+
+
+def forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=False, prev=None,
+            bf16=False):
+    """rho (and prev for two-channel networks): [B, H, W] -> prediction [B, H, W]
+    (and the intermediates).  bf16: round as the library does (module text)."""
+    in_ch = 1 if prev is None else 2
+    P = _layers(params, channels, layers, in_ch, bf16)
     x = network_input(rho, prev, mean, in_scale, out_scale)
     zs, acts = [], [x]
     a = x
@@ -111,6 +153,8 @@ def forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=False
         if l < layers - 1:
             zs.append(z)
             a = silu(z)
+            if bf16:
+                a = bf16_round(a)
             acts.append(a)
         else:
             y = z[:, 0]
@@ -121,9 +165,11 @@ def forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=False
     return pred
 
 
-def loss_and_grad(params, rho, target, channels, layers, mean, in_scale, out_scale, prev=None):
+def loss_and_grad(params, rho, target, channels, layers, mean, in_scale, out_scale, prev=None,
+                  bf16=False):
     rho = np.asarray(rho, dtype=np.float64)
-    _, c = forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=True, prev=prev)
+    _, c = forward(params, rho, channels, layers, mean, in_scale, out_scale, keep=True, prev=prev,
+                   bf16=bf16)
     r = (np.asarray(target, dtype=np.float64) - rho) / out_scale
     e = c["yhat"] - r
     M = e.size
@@ -139,6 +185,9 @@ def loss_and_grad(params, rho, target, channels, layers, mean, in_scale, out_sca
         grads.append((dW, db))
         if l > 0:
             delta = conv3x3_input_grad(delta, W) * dsilu(c["zs"][l - 1])
+            if bf16:
+                # hidden pre-activation gradients are kept in bfloat16
+                delta = bf16_round(delta)
     grads.reverse()
     flat = np.concatenate([np.concatenate([dW.ravel(), db]) for dW, db in grads])
     return loss, flat
