@@ -55,6 +55,7 @@ extern "C" {
 #define FSC_E_STATE (-5)    /* call not valid in the current state */
 #define FSC_E_NOTSUP (-6)   /* combination not supported by the library */
 #define FSC_E_IO (-7)       /* checkpoint file missing, unreadable, truncated or corrupt */
+#define FSC_E_RANGE (-8)    /* input larger than a fixed-size library buffer allows */
 
 #define FSC_E4 4 /* 2D: |e|^2 in {1,2} (8 neighbours); 3D: {1,2} (18) */
 #define FSC_E8 8 /* 2D only: |e|^2 in {1,2,4,5,8} (24 neighbours, 5x5 block) */
@@ -329,6 +330,21 @@ int fsc_ens_coarsen(fsc_ens *ens, int replica, int factor, float *dev_out);
 int fsc_field_nbins(int n, int *nbins);
 int fsc_field_sk(const float *dev_fields, int batch, int ny, int nx, void *stream,
                  double *host_shell_mean, double *host_L, int nbins);
+
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it): the
+ * same computation and results as fsc_field_sk, with every work area (complex
+ * FFT lines, twiddles, FP64 accumulators, counter) in a fixed-size scratch
+ * array that the library holds in device memory, about 16 MiB per device for
+ * the life of the process.  It calls no hipMalloc or hipFree.  Fields up to
+ * 1024 x 1024 (ny = nx <= 1024); larger ones return FSC_E_RANGE before any
+ * device work.  All calls on one device share that device's scratch, and each
+ * call re-initialises what it reads: calls that overlap in time on one device
+ * (other host threads, or other streams) race and give wrong results, so the
+ * caller serialises them.  Synchronous on `stream` (NULL: the current
+ * device's default stream); the scratch of the stream's device is used. */
+int fsc_field_sk_noalloc(const float *dev_fields, int batch, int ny, int nx, void *stream,
+                         double *host_shell_mean, double *host_L, int nbins);
 
 /* Matrix-core layout check: C = A (16x32) B (32x16) through one BF16 MFMA
  * with the operand placement the surrogate kernels use (host row-major). */

@@ -22,7 +22,8 @@ FSC_FP32_SHIFTED, FSC_FP64 = 0, 1
 FSC_SK_AXIS, FSC_SK_RADIAL = 0, 1
 
 ERRORS = {0: "ok", -1: "invalid argument", -2: "HIP runtime error", -3: "out of memory",
-          -4: "diverged", -5: "invalid state", -6: "not supported", -7: "file error"}
+          -4: "diverged", -5: "invalid state", -6: "not supported", -7: "file error",
+          -8: "input exceeds the fixed-size scratch"}
 
 # Every symbol include/fsc.h declares.
 EXPORTS = [
@@ -42,7 +43,7 @@ EXPORTS = [
     "fsc_sur_create", "fsc_sur_destroy", "fsc_sur_last_error", "fsc_sur_nparams",
     "fsc_sur_set_params", "fsc_sur_get_params", "fsc_sur_set_norm", "fsc_sur_forward",
     "fsc_sur_grad", "fsc_sur_train_step", "fsc_coarsen", "fsc_ens_coarsen", "fsc_field_nbins",
-    "fsc_field_sk", "fsc_mfma_probe",
+    "fsc_field_sk", "fsc_field_sk_noalloc", "fsc_mfma_probe",
 ]
 
 
@@ -158,6 +159,7 @@ def lib():
         "fsc_ens_coarsen": ([vp, C.c_int, C.c_int, vp], C.c_int),
         "fsc_field_nbins": ([C.c_int, C.POINTER(C.c_int)], C.c_int),
         "fsc_field_sk": ([vp, C.c_int, C.c_int, C.c_int, vp, dp, dp, C.c_int], C.c_int),
+        "fsc_field_sk_noalloc": ([vp, C.c_int, C.c_int, C.c_int, vp, dp, dp, C.c_int], C.c_int),
         "fsc_mfma_probe": ([fp, fp, fp], C.c_int),
         "fsc_normals": ([C.c_int, C.c_int, C.c_uint64, C.c_uint32, i64p, i64p, C.c_int64, dp],
                         C.c_int),
@@ -567,15 +569,19 @@ class Surrogate:
         return loss.value if want_loss else None
 
 
-def field_sk(fields, batch: int, n: int, stream=None):
-    """Radial shell means of S(k) and L for device float fields [batch][n][n]."""
+def field_sk(fields, batch: int, n: int, stream=None, noalloc: bool = False):
+    """Radial shell means of S(k) and L for device float fields [batch][n][n].
+
+    noalloc=True calls fsc_field_sk_noalloc (fixed-size library scratch, no
+    device allocation; sides up to 1024)."""
     nb = C.c_int()
     _check(lib().fsc_field_nbins(n, C.byref(nb)))
     shells = np.zeros((batch, nb.value))
     L = np.zeros(batch)
     ptr = C.c_void_p(fields.data_ptr() if hasattr(fields, "data_ptr") else int(fields))
-    _check(lib().fsc_field_sk(ptr, batch, n, n, _stream_handle(_torch_stream_or(stream)),
-                              _dp(shells), _dp(L), nb.value))
+    fn = lib().fsc_field_sk_noalloc if noalloc else lib().fsc_field_sk
+    _check(fn(ptr, batch, n, n, _stream_handle(_torch_stream_or(stream)), _dp(shells), _dp(L),
+              nb.value))
     return shells, L
 
 

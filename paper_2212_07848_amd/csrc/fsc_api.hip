@@ -1108,6 +1108,7 @@ const char *fsc_strerror(int code) {
     case FSC_E_STATE: return "invalid state";
     case FSC_E_NOTSUP: return "not supported";
     case FSC_E_IO: return "file error";
+    case FSC_E_RANGE: return "input larger than the fixed-size scratch allows";
     default: return "unknown error";
     }
 }
@@ -1411,31 +1412,150 @@ int fsc_ens_coarsen(fsc_ens *ens, int replica, int factor, float *dev_out) {
     return FSC_OK;
 }
 
-int fsc_field_sk(const float *dev_fields, int batch, int ny, int nx, void *stream,
-                 double *host_shell_mean, double *host_L, int nbins) {
-    if (!dev_fields || batch < 1 || nx < 2 || ny < 2 || nx != ny || nx > 8192) return FSC_E_INVAL;
-    const hipStream_t st = static_cast<hipStream_t>(stream);
-    auto round_sqrt = [](int64_t m) {
-        int64_t b = int64_t(std::sqrt(double(m)));
-        while (b * b > m) --b;
-        while ((b + 1) * (b + 1) <= m) ++b;
-        if (m - b * b > b) ++b;
-        return int(b);
-    };
-    const int L = nx;
-    const int nrad = round_sqrt(2 * int64_t(L / 2) * (L / 2)) + 1;
-    if (nbins != nrad) return FSC_E_INVAL;
-    std::vector<int64_t> modes(nrad, 0);
+namespace {
+
+// Shell index round(sqrt(m)) of a squared mode number, in integer arithmetic.
+int round_sqrt_shell(int64_t m) {
+    int64_t b = int64_t(std::sqrt(double(m)));
+    while (b * b > m) --b;
+    while ((b + 1) * (b + 1) <= m) ++b;
+    if (m - b * b > b) ++b;
+    return int(b);
+}
+
+// Mode count of each radial shell of an L x L box (k = 0 excluded).
+void field_shell_modes(int L, int nrad, int64_t *modes) {
+    for (int k = 0; k < nrad; ++k) modes[k] = 0;
     for (int y = 0; y < L; ++y)
         for (int x = 0; x < L; ++x) {
             const int64_t mx = x <= L / 2 ? x : x - L, my = y <= L / 2 ? y : y - L;
-            if (mx || my) modes[round_sqrt(mx * mx + my * my)] += 1;
+            if (mx || my) modes[round_sqrt_shell(mx * mx + my * my)] += 1;
         }
-    const int64_t N = int64_t(nx) * ny;
+}
+
+// Device work areas of one field S(k): two complex lines of N points, the
+// twiddles, the FP64 bin accumulators and the series counter.
+struct FieldWork {
+    void *ca, *cb, *tw;
+    double *acc;
+    int *cnt;
+};
+
+size_t field_acc_len(int L, int nrad) {
+    return 2 * size_t(2 * (L / 2 + 1)) + 2 * size_t(nrad) + 2 + size_t(2 + nrad);
+}
+
+// S(k) of `batch` fields [batch][L][L] (float) on stream st, one field after
+// the other through the work areas w: density to complex, FFT along x then
+// y, radial binning with the first moment, then the shell sums and the moment
+// pair are copied to the host.  Shared by fsc_field_sk (which allocates w per
+// call) and fsc_field_sk_noalloc (which uses the library's static scratch).
+hipError_t field_sk_batches(const float *dev_fields, int batch, int L, hipStream_t st,
+                            const FieldWork &w, const int64_t *modes, int nrad,
+                            double *host_shell_mean, double *host_L) {
+    const int64_t N = int64_t(L) * L;
+    const int na = L / 2 + 1;
+    const size_t nacc = field_acc_len(L, nrad);
+    hipError_t ec = launch_twiddles(0, w.tw, L, st);
+    const Geometry g{2, L, L, 1, N};
+    for (int b = 0; b < batch && ec == hipSuccess; ++b) {
+        // the accumulators and the series counter start at zero for every field
+        ec = launch_zero_words(w.acc, int64_t(2 * nacc), st);
+        if (ec == hipSuccess) ec = launch_zero_words(w.cnt, 1, st);
+        if (ec == hipSuccess) ec = launch_field_cplx(dev_fields + size_t(b) * N, int(N), w.ca, st);
+        if (ec == hipSuccess) ec = launch_fft_axis(0, w.ca, w.cb, w.tw, L, L, 1, st);
+        if (ec == hipSuccess) ec = launch_fft_axis(0, w.cb, w.ca, w.tw, L, L, 1, st);
+        BinTargets t;
+        t.axis_sum = w.acc;
+        t.axis_sq = w.acc + 2 * na;
+        t.rad_sum = w.acc + 4 * na;
+        t.rad_sq = w.acc + 4 * na + nrad;
+        t.n_axis = na;
+        t.n_rad = nrad;
+        t.mom = w.acc + 4 * na + 2 * nrad;
+        t.series = w.acc + 4 * na + 2 * nrad + 2;
+        t.series_n = w.cnt;
+        t.series_cap = 1;
+        if (ec == hipSuccess) ec = launch_bin(g, 0, w.ca, t, st);
+        double mom[2] = {0.0, 0.0};
+        double *shell = host_shell_mean ? host_shell_mean + size_t(b) * nrad : nullptr;
+        if (ec == hipSuccess && shell)
+            ec = hipMemcpyAsync(shell, t.rad_sum, sizeof(double) * nrad, hipMemcpyDeviceToHost, st);
+        if (ec == hipSuccess)
+            ec = hipMemcpyAsync(mom, t.mom, sizeof(mom), hipMemcpyDeviceToHost, st);
+        if (ec == hipSuccess) ec = hipStreamSynchronize(st);
+        if (ec != hipSuccess) break;
+        if (shell)
+            for (int k = 0; k < nrad; ++k) shell[k] = modes[k] ? shell[k] / double(modes[k]) : 0.0;
+        if (host_L) host_L[b] = mom[1] > 0.0 ? 2.0 * M_PI * mom[0] / mom[1] : 0.0;
+    }
+    return ec;
+}
+
+// ---- fixed-size scratch of the allocation-free field S(k) ----------------
+// Sized for fields up to FIELD_STATIC_MAX_SIDE^2: two complex work lines of
+// 8 B per point, the twiddles, the accumulators and the counter, each at a
+// 256-byte boundary.  Every device the library runs on holds one copy for the
+// life of the process.
+constexpr int FIELD_STATIC_MAX_SIDE = 1024;
+constexpr int FIELD_STATIC_MAX_NRAD = 726;  // round(sqrt(2) * 512) + 1
+constexpr size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+constexpr size_t FS_CPLX = 8 * size_t(FIELD_STATIC_MAX_SIDE) * FIELD_STATIC_MAX_SIDE;
+constexpr size_t FS_TW = align256(8 * size_t(FIELD_STATIC_MAX_SIDE));
+constexpr size_t FS_ACC = align256(8 * (2 * size_t(2 * (FIELD_STATIC_MAX_SIDE / 2 + 1)) +
+                                        2 * size_t(FIELD_STATIC_MAX_NRAD) + 2 +
+                                        size_t(2 + FIELD_STATIC_MAX_NRAD)));
+constexpr size_t FS_BYTES = 2 * FS_CPLX + FS_TW + FS_ACC + 256;
+
+__device__ __align__(256) unsigned char scratch[FS_BYTES];
+
+constexpr int FS_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[FS_MAX_DEVICES] = {};
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current (the array's host-side name is not a device address).
+hipError_t scratch_on(int dev, void **out) {
+    if (dev < 0 || dev >= FS_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int prev = -1;
+        hipError_t ec = hipGetDevice(&prev);
+        if (ec != hipSuccess) return ec;
+        if (prev != dev && (ec = hipSetDevice(dev)) != hipSuccess) return ec;
+        void *ptr = nullptr;
+        ec = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (prev != dev) (void)hipSetDevice(prev);
+        if (ec != hipSuccess) return ec;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+int field_args(const float *dev_fields, int batch, int ny, int nx, int nbins, int *nrad) {
+    if (!dev_fields || batch < 1 || nx < 2 || ny < 2 || nx != ny || nx > 8192) return FSC_E_INVAL;
+    *nrad = round_sqrt_shell(2 * int64_t(nx / 2) * (nx / 2)) + 1;
+    return nbins == *nrad ? FSC_OK : FSC_E_INVAL;
+}
+
+}  // namespace
+
+int fsc_field_sk(const float *dev_fields, int batch, int ny, int nx, void *stream,
+                 double *host_shell_mean, double *host_L, int nbins) {
+    int nrad = 0;
+    int rc = field_args(dev_fields, batch, ny, nx, nbins, &nrad);
+    if (rc) return rc;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int L = nx;
+    std::vector<int64_t> modes(nrad, 0);
+    field_shell_modes(L, nrad, modes.data());
+    const int64_t N = int64_t(L) * L;
     void *ca = nullptr, *cb = nullptr, *tw = nullptr;
     double *acc = nullptr;
     int *cnt = nullptr;
-    const size_t nacc = 2 * size_t(2 * (L / 2 + 1)) + 2 * size_t(nrad) + 2 + size_t(2 + nrad);
+    const size_t nacc = field_acc_len(L, nrad);
     if (hipMalloc(&ca, 8 * N) != hipSuccess || hipMalloc(&cb, 8 * N) != hipSuccess ||
         hipMalloc(&tw, 8 * twiddle_len(L)) != hipSuccess ||
         hipMalloc(&acc, sizeof(double) * nacc) != hipSuccess ||
@@ -1445,40 +1565,32 @@ int fsc_field_sk(const float *dev_fields, int batch, int ny, int nx, void *strea
             if (p) (void)hipFree(p);
         return FSC_E_OOM;
     }
-    hipError_t ec = launch_twiddles(0, tw, L, st);
-    std::vector<double> host(nacc);
-    const Geometry g{2, nx, ny, 1, N};
-    const int na = L / 2 + 1;
-    for (int b = 0; b < batch && ec == hipSuccess; ++b) {
-        ec = hipMemsetAsync(acc, 0, sizeof(double) * nacc, st);
-        if (ec == hipSuccess) ec = hipMemsetAsync(cnt, 0, sizeof(int), st);
-        if (ec == hipSuccess) ec = launch_field_cplx(dev_fields + size_t(b) * N, int(N), ca, st);
-        if (ec == hipSuccess) ec = launch_fft_axis(0, ca, cb, tw, nx, ny, 1, st);
-        if (ec == hipSuccess) ec = launch_fft_axis(0, cb, ca, tw, ny, nx, 1, st);
-        BinTargets t;
-        t.axis_sum = acc;
-        t.axis_sq = acc + 2 * na;
-        t.rad_sum = acc + 4 * na;
-        t.rad_sq = acc + 4 * na + nrad;
-        t.n_axis = na;
-        t.n_rad = nrad;
-        t.mom = acc + 4 * na + 2 * nrad;
-        t.series = acc + 4 * na + 2 * nrad + 2;
-        t.series_n = cnt;
-        t.series_cap = 1;
-        if (ec == hipSuccess) ec = launch_bin(g, 0, ca, t, st);
-        if (ec == hipSuccess)
-            ec = hipMemcpyAsync(host.data(), acc, sizeof(double) * nacc, hipMemcpyDeviceToHost, st);
-        if (ec == hipSuccess) ec = hipStreamSynchronize(st);
-        if (ec != hipSuccess) break;
-        const double *rs = host.data() + 4 * na;
-        const double *mom = host.data() + 4 * na + 2 * nrad;
-        for (int k = 0; k < nrad; ++k)
-            if (host_shell_mean)
-                host_shell_mean[size_t(b) * nrad + k] = modes[k] ? rs[k] / double(modes[k]) : 0.0;
-        if (host_L) host_L[b] = mom[1] > 0.0 ? 2.0 * M_PI * mom[0] / mom[1] : 0.0;
-    }
+    const FieldWork w{ca, cb, tw, acc, cnt};
+    hipError_t ec = field_sk_batches(dev_fields, batch, L, st, w, modes.data(), nrad,
+                                     host_shell_mean, host_L);
     for (void *p : {ca, cb, tw, (void *)acc, (void *)cnt}) (void)hipFree(p);
+    return ec == hipSuccess ? FSC_OK : FSC_E_HIP;
+}
+
+int fsc_field_sk_noalloc(const float *dev_fields, int batch, int ny, int nx, void *stream,
+                         double *host_shell_mean, double *host_L, int nbins) {
+    int nrad = 0;
+    int rc = field_args(dev_fields, batch, ny, nx, nbins, &nrad);
+    if (rc) return rc;
+    if (nx > FIELD_STATIC_MAX_SIDE) return FSC_E_RANGE;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = -1;
+    hipError_t ec = st ? hipStreamGetDevice(st, &dev) : hipGetDevice(&dev);
+    if (ec != hipSuccess) return FSC_E_HIP;
+    void *base = nullptr;
+    if (scratch_on(dev, &base) != hipSuccess) return FSC_E_HIP;
+    unsigned char *p = static_cast<unsigned char *>(base);
+    const FieldWork w{p, p + FS_CPLX, p + 2 * FS_CPLX,
+                      reinterpret_cast<double *>(p + 2 * FS_CPLX + FS_TW),
+                      reinterpret_cast<int *>(p + 2 * FS_CPLX + FS_TW + FS_ACC)};
+    int64_t modes[FIELD_STATIC_MAX_NRAD];
+    field_shell_modes(nx, nrad, modes);
+    ec = field_sk_batches(dev_fields, batch, nx, st, w, modes, nrad, host_shell_mean, host_L);
     return ec == hipSuccess ? FSC_OK : FSC_E_HIP;
 }
 

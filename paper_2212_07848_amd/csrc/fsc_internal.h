@@ -122,6 +122,8 @@ hipError_t launch_coarsen(const Geometry &g, int precision, const void *buf, dou
                           float *out, hipStream_t s);
 // Real field -> interleaved complex float.
 hipError_t launch_field_cplx(const float *f, int n, void *c, hipStream_t s);
+// Zeroes `words` 32-bit words of device memory with a fill kernel.
+hipError_t launch_zero_words(void *p, int64_t words, hipStream_t s);
 
 // Plain copy of `bytes` (multiple of 16) bytes.
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);

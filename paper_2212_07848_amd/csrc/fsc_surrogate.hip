@@ -695,6 +695,20 @@ hipError_t launch_field_cplx(const float *f, int n, void *c, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Clears `words` 32-bit words (a fill kernel rather than a memset node, so the
+// clearing can also sit inside a caller's captured graph).
+__global__ void k_zero_words(uint32_t *p, int64_t words) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < words) p[i] = 0u;
+}
+
+hipError_t launch_zero_words(void *p, int64_t words, hipStream_t s) {
+    if (words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_words, dim3(unsigned((words + 255) / 256)), dim3(256), 0, s,
+                       static_cast<uint32_t *>(p), words);
+    return hipGetLastError();
+}
+
 }  // namespace fsc
 
 // ===========================================================================
