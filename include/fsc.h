@@ -126,17 +126,24 @@ int fsc_get_params(const fsc_ctx *ctx, fsc_params *out);
 int fsc_init_uniform(fsc_ctx *ctx);
 
 /* Sets the streamed populations f (host, double, layout above) as the state
- * at time step `step` (0 <= step < 2^32).  Clears nothing else. */
+ * of Eq. (12) at time step `step` (0 <= step < 2^32).  Clears nothing else.
+ * Values are stored as deviations f_i - w_i rho0 in the context's precision
+ * (rounded to float for FSC_FP32_SHIFTED); they are not checked (a
+ * non-finite or non-positive density shows in fsc_stats). */
 int fsc_set_populations(fsc_ctx *ctx, const double *host_f, int64_t step);
 
-/* Reads the streamed populations of the current state into host_f and the
- * current time step into *step (may be NULL). */
+/* Reads the streamed populations of the current state of Eq. (12) into
+ * host_f (w_i rho0 + the stored deviation, in double) and the current time
+ * step into *step (may be NULL).  Synchronises the stream. */
 int fsc_get_populations(fsc_ctx *ctx, double *host_f, int64_t *step);
 
-/* Advances the state by nsteps >= 0 time steps of Eq. (12), one fused kernel
- * launch per step.  The noise of step t at node s uses counter (s, t, block,
- * seed >> 32) and key (seed & 0xffffffff, replica).  Fails with FSC_E_INVAL
- * if the step count would pass 2^32. */
+/* Advances the state by nsteps >= 0 time steps of Eq. (12) with the force of
+ * Eq. (1) and the moment-space noise described after Eq. (16): one fused
+ * kernel launch per step, or per pair of steps where the tiling in use is the
+ * two-step kernel (2D FP32; bit-identical results, see fsc_tile_shapes).  The
+ * noise of step t at node s uses counter (s, t, block, seed >> 32) and key
+ * (seed & 0xffffffff, replica) (fsc_normals).  Enqueued on the context's
+ * stream.  Fails with FSC_E_INVAL if the step count would pass 2^32. */
 int fsc_step(fsc_ctx *ctx, int64_t nsteps);
 
 /* Advances nsteps and accumulates one S(k) sample after every `sk_every`
@@ -151,14 +158,25 @@ int fsc_get_step(const fsc_ctx *ctx, int64_t *step);
 int fsc_save(fsc_ctx *ctx, const char *path);
 int fsc_load(fsc_ctx *ctx, const char *path);
 
-/* Density n(x) = sum_i f_i of the current state, host double [nz][ny][nx]. */
+/* Density n(x) = sum_i f_i of the current state (the field whose
+ * fluctuations the paper's S(k) measures), host double [nz][ny][nx].
+ * fsc_read_density is the same call under the name of the problem
+ * statement's "measure rho".  Synchronises the stream. */
 int fsc_density(fsc_ctx *ctx, double *host_rho);
+int fsc_read_density(fsc_ctx *ctx, double *host_rho);
 
-/* FP64 reductions of the current state: out[0] = sum n, out[1..3] = sum j
- * (x, y, z; z = 0 in 2D), out[4] = min n, out[5] = max n, out[6] = number of
- * nodes with a non-finite or non-positive density, out[7] = node count.
- * Returns FSC_E_DIVERGED (after filling out) when out[6] > 0. */
+/* FP64 reductions of the current state, the quantities the collision
+ * conserves (mass exactly, momentum up to the force, whose lattice sum
+ * vanishes; the paper's protocol relies on the exact mass conservation):
+ * out[0] = sum n, out[1..3] = sum j (x, y, z; z = 0 in 2D), out[4] = min n,
+ * out[5] = max n over nodes with a number as density (NaN nodes are skipped),
+ * out[6] = number of nodes with a non-finite or non-positive density,
+ * out[7] = node count.  Returns FSC_E_DIVERGED (after filling out) when
+ * out[6] > 0.  Synchronises the stream. */
 int fsc_stats(fsc_ctx *ctx, double *out8);
+/* The conserved sums alone: *mass = sum n, mom[0..D-1] = sum j.  Errors as
+ * fsc_stats (FSC_E_DIVERGED after filling them). */
+int fsc_conserved(fsc_ctx *ctx, double *mass, double *mom);
 
 /* Structure factor.  One sample adds, for every wave vector k != 0 of the
  * lattice (k_d = 2 pi m_d / n_d), P(k) = |sum_x n(x) e^{-i k.x}|^2 / N to the
@@ -170,6 +188,10 @@ int fsc_stats(fsc_ctx *ctx, double *out8);
  *                 else 0; shell b collects the modes with round(|m|) = b,
  *                 decided in exact integer arithmetic.
  * Mean S(k) of a bin = sum / count. */
+/* One sample fills both bin kinds from one FFT of the density; the kind is
+ * chosen when reading (fsc_read_sk's `kind` plays the role of a measurement
+ * mode).  S(k) is the quantity compared with Eq. (16); the sample is
+ * enqueued on the context's stream. */
 int fsc_sk_reset(fsc_ctx *ctx);
 int fsc_measure_sk(fsc_ctx *ctx);
 int fsc_sk_nbins(const fsc_ctx *ctx, int kind, int *nbins);
@@ -318,6 +340,36 @@ int fsc_sur_grad(fsc_sur *s, const float *dev_prev, const float *dev_in, const f
 int fsc_sur_train_step(fsc_sur *s, const float *dev_prev, const float *dev_in,
                        const float *dev_target, int batch, float lr, double *loss);
 
+/* Rollout: `passes` forward passes in a row, traj [passes + 1][batch][H][W]
+ * with traj[0] the start (set by the caller) and traj[k + 1] the prediction
+ * from (traj[k - 1], traj[k]) (dev_prev in place of traj[-1]; ignored for
+ * in_ch = 1).  The passes are captured once per (dev_prev, dev_traj, batch,
+ * passes) into a hipGraph and replayed, so the launches of a rollout run
+ * back to back; the replay is ordered after earlier and before later work
+ * on the surrogate's stream.  Results equal `passes` calls of
+ * fsc_sur_forward. */
+int fsc_sur_rollout(fsc_sur *s, const float *dev_prev, float *dev_traj, int batch, int passes);
+
+/* Training batch from a device snapshot stack S [K][R][H][W] (float; H, W
+ * the surrogate's): image b (b < batch <= min(64, max_batch)) is
+ *   out[b][y][x] = S[t[b] + dt][r[b]][(Y - sy) mod H][(X - sx) mod W],
+ * (Y, X) = (x, y) if `transpose` (needs H == W), else (y, x): a periodic
+ * shift and a transpose, symmetries of the periodic square lattice.  host_t,
+ * host_r: batch indices (host int arrays); every t[b] + dt in [0, K), r[b]
+ * in [0, R), else FSC_E_INVAL.  Enqueued on the surrogate's stream. */
+int fsc_sur_gather(fsc_sur *s, const float *dev_snaps, int K, int R, const int *host_t,
+                   const int *host_r, int batch, int dt, int sy, int sx, int transpose,
+                   float *dev_out);
+
+/* Data scales of a snapshot stack S [K][per_snap] (float, device), in FP64:
+ * *host_in_std = sample standard deviation (n - 1) of S[t_first..K-1], and
+ * *host_out_std = that of the increments S[k+1] - S[k], k = t_first..K-2
+ * (the network's input and output scales).  `centre` is subtracted before
+ * squaring (any value near the mean; it does not change the result beyond
+ * rounding).  Synchronous on `stream` (NULL: the default stream). */
+int fsc_stack_scales(const float *dev_snaps, int K, int64_t per_snap, int t_first, double centre,
+                     double *host_in_std, double *host_out_std, void *stream);
+
 /* Block-averaged density of the current state over factor x factor blocks
  * into dev_out[(ny/factor) x (nx/factor)] (2D lattices, sides divisible by
  * factor); enqueued on the lattice's stream. */
@@ -410,9 +462,18 @@ int fsc_philox(const uint32_t *host_ctr, const uint32_t *host_key, uint32_t *hos
 
 /* The Q-D-1 standard normals the step kernel draws for each (node, step)
  * pair (host arrays node[n], step[n]; out[n][Q-D-1] as double), computed in
- * the given precision (FSC_FP32_SHIFTED: float, FSC_FP64: double):
- *   u(r) = (floor(r/2^9) + 1/2) / 2^23; pairs sqrt(-2 ln u_a) (cos, sin)(2 pi u_b)
- *   from (r0, r1), (r2, r3) of blocks 0, 1, ... .  Synchronous. */
+ * the given precision (FSC_FP32_SHIFTED: float, FSC_FP64: double).  The
+ * paper fixes only that the noise is Gaussian and uncorrelated in space and
+ * time; the generator is this library's: words w_0, w_1, .. are Philox4x32-10
+ * outputs of blocks 0, 1, .. (one block for D2Q9, three for D3Q19) with key
+ * (seed & 0xffffffff, replica) and counter (node, step, block, seed >> 32).
+ * Pair k uses the radius uniform u_a = (floor(w_k / 2^9) + 1/2) / 2^23 and a
+ * 16-bit angle uniform u_b = (h_k + 1/2) / 2^16:
+ *   D2Q9 : h_0 = high half of w_3, h_1 = low half of w_3,
+ *          h_2 = (low byte of w_0) * 256 + low byte of w_1;
+ *   D3Q19: h_k = the k-th 16-bit half of w_8 .. w_11, high half first;
+ * (z_2k, z_2k+1) = sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b); normal m goes
+ * to the m-th non-conserved moment.  Synchronous. */
 int fsc_normals(int D, int precision, uint64_t seed, uint32_t replica, const int64_t *host_node,
                 const int64_t *host_step, int64_t n, double *host_out);
 

@@ -8,10 +8,10 @@ buffers=(tensor_a, tensor_b))``).
 from ._lib import (FSC_E4, FSC_E8, FSC_FP32_SHIFTED, FSC_FP64, FSC_SK_AXIS, FSC_SK_RADIAL,
                    EXPORTS, Ensemble, FscError, Lattice, Params, Surrogate, device_copy,
                    field_sk, lib, linear_corr, linear_sk, linear_sk_radial, make_params, mfma_probe,
-                   normals, philox, tile_shapes)
+                   normals, philox, stack_scales, tile_shapes)
 
 __all__ = ["FSC_E4", "FSC_E8", "FSC_FP32_SHIFTED", "FSC_FP64", "FSC_SK_AXIS", "FSC_SK_RADIAL",
            "EXPORTS", "Ensemble", "FscError", "Lattice", "Params", "Surrogate", "device_copy",
            "field_sk", "lib", "linear_corr", "linear_sk", "linear_sk_radial", "make_params", "mfma_probe",
-           "tile_shapes",
+           "tile_shapes", "stack_scales",
            "normals", "philox"]

@@ -29,7 +29,8 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "HIP runtime error", -3: "out of 
 EXPORTS = [
     "fsc_create", "fsc_create_external", "fsc_destroy", "fsc_last_error", "fsc_strerror",
     "fsc_get_params", "fsc_init_uniform", "fsc_set_populations", "fsc_get_populations",
-    "fsc_step", "fsc_run", "fsc_get_step", "fsc_save", "fsc_load", "fsc_density", "fsc_stats", "fsc_sk_reset",
+    "fsc_step", "fsc_run", "fsc_get_step", "fsc_save", "fsc_load", "fsc_density",
+    "fsc_read_density", "fsc_stats", "fsc_conserved", "fsc_sk_reset",
     "fsc_measure_sk", "fsc_sk_nbins", "fsc_read_sk", "fsc_series_enable", "fsc_read_series",
     "fsc_ens_create", "fsc_ens_destroy", "fsc_ens_last_error", "fsc_ens_init_uniform",
     "fsc_ens_run", "fsc_ens_get_step", "fsc_ens_get_populations", "fsc_ens_set_populations",
@@ -42,7 +43,8 @@ EXPORTS = [
     "fsc_linear_corr",
     "fsc_sur_create", "fsc_sur_destroy", "fsc_sur_last_error", "fsc_sur_nparams",
     "fsc_sur_set_params", "fsc_sur_get_params", "fsc_sur_set_norm", "fsc_sur_forward",
-    "fsc_sur_grad", "fsc_sur_train_step", "fsc_coarsen", "fsc_ens_coarsen", "fsc_field_nbins",
+    "fsc_sur_grad", "fsc_sur_train_step", "fsc_sur_rollout", "fsc_sur_gather",
+    "fsc_stack_scales", "fsc_coarsen", "fsc_ens_coarsen", "fsc_field_nbins",
     "fsc_field_sk", "fsc_field_sk_noalloc", "fsc_mfma_probe",
 ]
 
@@ -105,6 +107,8 @@ def lib():
         "fsc_ens_load": ([vp, C.c_char_p], C.c_int),
         "fsc_density": ([vp, dp], C.c_int),
         "fsc_stats": ([vp, dp], C.c_int),
+        "fsc_read_density": ([vp, dp], C.c_int),
+        "fsc_conserved": ([vp, dp, dp], C.c_int),
         "fsc_sk_reset": ([vp], C.c_int),
         "fsc_measure_sk": ([vp], C.c_int),
         "fsc_sk_nbins": ([vp, C.c_int, C.POINTER(C.c_int)], C.c_int),
@@ -155,6 +159,10 @@ def lib():
         "fsc_sur_forward": ([vp, vp, vp, vp, C.c_int], C.c_int),
         "fsc_sur_grad": ([vp, vp, vp, vp, C.c_int, fp, dp], C.c_int),
         "fsc_sur_train_step": ([vp, vp, vp, vp, C.c_int, C.c_float, dp], C.c_int),
+        "fsc_sur_rollout": ([vp, vp, vp, C.c_int, C.c_int], C.c_int),
+        "fsc_sur_gather": ([vp, vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                            C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp], C.c_int),
+        "fsc_stack_scales": ([vp, C.c_int, C.c_int64, C.c_int, C.c_double, dp, dp, vp], C.c_int),
         "fsc_coarsen": ([vp, C.c_int, vp], C.c_int),
         "fsc_ens_coarsen": ([vp, C.c_int, C.c_int, vp], C.c_int),
         "fsc_field_nbins": ([C.c_int, C.POINTER(C.c_int)], C.c_int),
@@ -293,6 +301,15 @@ class Lattice:
         n = np.empty(self.shape)
         self._c(lib().fsc_density(self._h, _dp(n)))
         return n
+
+    def conserved(self, allow_diverged: bool = False):
+        """(mass, momentum[D]) of the current state (fsc_conserved)."""
+        mass = C.c_double()
+        mom = np.zeros(3)
+        rc = lib().fsc_conserved(self._h, C.byref(mass), _dp(mom))
+        if rc != 0 and not (allow_diverged and rc == -4):
+            self._c(rc)
+        return mass.value, mom[:self.D].copy()
 
     def stats(self, allow_diverged: bool = False):
         out = np.empty(8)
@@ -567,6 +584,35 @@ class Surrogate:
                                          int(batch), float(lr),
                                          C.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
+
+    def rollout(self, prev, traj, batch: int, passes: int):
+        """`passes` forward passes replayed from a captured graph: traj
+        [passes + 1][batch][H][W] with traj[0] the start (see fsc_sur_rollout)."""
+        self._c(lib().fsc_sur_rollout(self._h, self._ptr(prev), self._ptr(traj), int(batch),
+                                      int(passes)))
+
+    def gather(self, snaps, t_idx, r_idx, dt: int, shift, transpose: bool, out):
+        """Batch of snapshot images with a periodic shift and an optional
+        transpose (see fsc_sur_gather); snaps is a device tensor [K][R][H][W]."""
+        t = np.ascontiguousarray(t_idx, dtype=np.int32)
+        r = np.ascontiguousarray(r_idx, dtype=np.int32)
+        K, R = int(snaps.shape[0]), int(snaps.shape[1])
+        ip = C.POINTER(C.c_int)
+        self._c(lib().fsc_sur_gather(self._h, self._ptr(snaps), K, R, t.ctypes.data_as(ip),
+                                     r.ctypes.data_as(ip), int(t.size), int(dt), int(shift[0]),
+                                     int(shift[1]), int(bool(transpose)), self._ptr(out)))
+
+
+def stack_scales(snaps, t_first: int, centre: float = 1.0, stream=None):
+    """(input std, increment std) of a device snapshot stack [K][...] in FP64
+    (see fsc_stack_scales)."""
+    K = int(snaps.shape[0])
+    per = int(np.prod(snaps.shape[1:]))
+    a, b = C.c_double(), C.c_double()
+    ptr = C.c_void_p(snaps.data_ptr())
+    _check(lib().fsc_stack_scales(ptr, K, per, int(t_first), float(centre), C.byref(a), C.byref(b),
+                                  _stream_handle(_torch_stream_or(stream))))
+    return a.value, b.value
 
 
 def field_sk(fields, batch: int, n: int, stream=None, noalloc: bool = False):

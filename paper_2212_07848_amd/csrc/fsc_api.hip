@@ -1184,9 +1184,21 @@ int fsc_density(fsc_ctx *ctx, double *host_rho) {
     return ens_density(ctx->e, 0, host_rho);
 }
 
+int fsc_read_density(fsc_ctx *ctx, double *host_rho) { return fsc_density(ctx, host_rho); }
+
 int fsc_stats(fsc_ctx *ctx, double *out8) {
     if (!ctx || !out8) return FSC_E_INVAL;
     return ens_stats(ctx->e, 0, out8);
+}
+
+int fsc_conserved(fsc_ctx *ctx, double *mass, double *mom) {
+    if (!ctx || !mass || !mom) return FSC_E_INVAL;
+    double out[8];
+    const int rc = ens_stats(ctx->e, 0, out);
+    if (rc != FSC_OK && rc != FSC_E_DIVERGED) return rc;
+    *mass = out[0];
+    for (int d = 0; d < ctx->e->reps[0].p.D; ++d) mom[d] = out[1 + d];
+    return rc;
 }
 
 int fsc_sk_reset(fsc_ctx *ctx) {

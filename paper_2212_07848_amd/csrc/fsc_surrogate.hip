@@ -19,7 +19,9 @@
 // Activations are NHWC: pixel p = (n H + y) W + x, channel fastest.
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/fsc.h"
@@ -695,6 +697,66 @@ hipError_t launch_field_cplx(const float *f, int n, void *c, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Training batches from a snapshot stack S[K][R][H][W]: image b of the batch
+// is snapshot t_b + dt of run r_b, moved by a periodic shift and optionally
+// transposed (symmetries of the periodic square lattice):
+//   out[b][y][x] = S[t_b + dt][r_b][(Y - sy) mod H][(X - sx) mod W],
+//   (Y, X) = (x, y) if transposed, else (y, x).
+// ---------------------------------------------------------------------------
+constexpr int GATHER_MAX = 64;
+struct GatherIdx {
+    int t[GATHER_MAX], r[GATHER_MAX];
+};
+
+__global__ void __launch_bounds__(256) k_gather(const float *__restrict__ snaps, int R, int H,
+                                                int W, GatherIdx idx, int dt, int sy, int sx,
+                                                int transpose, float *__restrict__ out) {
+    const int b = blockIdx.y;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= H * W) return;
+    const int x = k % W, y = k / W;
+    const int Y = transpose ? x : y, X = transpose ? y : x;
+    int ys = (Y - sy) % H, xs = (X - sx) % W;
+    ys += ys < 0 ? H : 0;
+    xs += xs < 0 ? W : 0;
+    const size_t img = size_t(idx.t[b] + dt) * R + idx.r[b];
+    out[size_t(b) * H * W + k] = snaps[img * H * W + size_t(ys) * W + xs];
+}
+
+// Partial FP64 sums over a snapshot stack for the data scales: per block,
+// sum (x - c) and (x - c)^2 over snapshots t_first.. K-1 and sum d, d^2 of the
+// increments d = S[k+1] - S[k], k >= t_first (c: a centre close to the mean).
+__global__ void __launch_bounds__(256) k_stack_moments(const float *__restrict__ S, int K,
+                                                       int64_t per, int t_first, double c,
+                                                       double *__restrict__ part) {
+    __shared__ double sh[4][4];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t n = int64_t(K - t_first) * per;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        const int64_t j = int64_t(t_first) * per + i;
+        const double v = double(S[j]) - c;
+        acc[0] += v;
+        acc[1] += v * v;
+        if (j + per < int64_t(K) * per) {
+            const double d = double(S[j + per]) - double(S[j]);
+            acc[2] += d;
+            acc[3] += d * d;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][q] = acc[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        part[blockIdx.x * 4 + q] = sh[0][q] + sh[1][q] + sh[2][q] + sh[3][q];
+    }
+}
+
 // Clears `words` 32-bit words (a fill kernel rather than a memset node, so the
 // clearing can also sit inside a caller's captured graph).
 __global__ void k_zero_words(uint32_t *p, int64_t words) {
@@ -732,6 +794,11 @@ struct fsc_sur {
     double *ysum = nullptr, *gsum = nullptr, *loss = nullptr;
     double *part = nullptr;  // [maxB][IMG_PARTS] segment sums
     int64_t adam_t = 0;
+    // captured rollouts: (prev, traj, batch, passes) -> graph, replayed on a
+    // stream of the surrogate's own that is ordered after and before `stream`
+    hipStream_t cap_stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::map<std::tuple<const float *, float *, int, int>, hipGraphExec_t> rollouts;
     std::string err;
 };
 
@@ -765,6 +832,13 @@ void sur_free(fsc_sur *s) {
         if (p) (void)hipFree(p);
     for (auto p : s->a)
         if (p) (void)hipFree(p);
+    for (auto &kv : s->rollouts) (void)hipGraphExecDestroy(kv.second);
+    if (s->cap_stream) {
+        (void)hipStreamSynchronize(s->cap_stream);
+        (void)hipStreamDestroy(s->cap_stream);
+    }
+    if (s->ev_in) (void)hipEventDestroy(s->ev_in);
+    if (s->ev_out) (void)hipEventDestroy(s->ev_out);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -1103,6 +1177,115 @@ int fsc_sur_train_step(fsc_sur *s, const float *dev_prev, const float *dev_in,
         SCHK(s, hipStreamSynchronize(s->stream));
         *loss = l / double(batch * s->H * s->W);
     }
+    return FSC_OK;
+}
+
+int fsc_sur_rollout(fsc_sur *s, const float *dev_prev, float *dev_traj, int batch, int passes) {
+    if (!s || !dev_traj || passes < 1) return FSC_E_INVAL;
+    int rc = check_batch(s, batch);
+    if (rc) return rc;
+    if (s->in_ch == 2 && !dev_prev)
+        return sur_fail(s, FSC_E_INVAL, "missing input field (two-channel networks need prev)");
+    if (!s->cap_stream) {
+        SCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+        SCHK(s, hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
+        SCHK(s, hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
+    }
+    const size_t img = size_t(batch) * s->H * s->W;
+    auto key = std::make_tuple(dev_prev, dev_traj, batch, passes);
+    auto it = s->rollouts.find(key);
+    if (it == s->rollouts.end()) {
+        // capture the passes on the private stream: the forward kernels use
+        // no memset nodes, only launches
+        hipStream_t user = s->stream;
+        s->stream = s->cap_stream;
+        hipGraph_t graph = nullptr;
+        hipError_t ec = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+        int frc = FSC_OK;
+        if (ec == hipSuccess) {
+            for (int k = 0; k < passes && frc == FSC_OK; ++k) {
+                const float *prev = k == 0 ? dev_prev : dev_traj + (k - 1) * img;
+                frc = sur_forward_core(s, prev, dev_traj + k * img, batch, false);
+                if (frc == FSC_OK) {
+                    hipLaunchKernelGGL(k_pred, dim3(unsigned(batch * IMG_PARTS)), dim3(256), 0,
+                                       s->stream, dev_traj + k * img, s->y, s->part, s->H * s->W,
+                                       s->out_scale, dev_traj + (k + 1) * img);
+                    if (hipGetLastError() != hipSuccess) frc = FSC_E_HIP;
+                }
+            }
+            hipError_t ee = hipStreamEndCapture(s->cap_stream, &graph);
+            if (ec == hipSuccess) ec = ee;
+        }
+        s->stream = user;
+        if (frc != FSC_OK || ec != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return frc != FSC_OK ? frc : sur_fail(s, FSC_E_HIP, std::string("rollout capture: ") +
+                                                                      hipGetErrorString(ec));
+        }
+        hipGraphExec_t exec = nullptr;
+        ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ec != hipSuccess)
+            return sur_fail(s, FSC_E_HIP, std::string("rollout instantiate: ") + hipGetErrorString(ec));
+        it = s->rollouts.emplace(key, exec).first;
+    }
+    // ordered after the caller's stream and before its later work
+    SCHK(s, hipEventRecord(s->ev_in, s->stream));
+    SCHK(s, hipStreamWaitEvent(s->cap_stream, s->ev_in, 0));
+    SCHK(s, hipGraphLaunch(it->second, s->cap_stream));
+    SCHK(s, hipEventRecord(s->ev_out, s->cap_stream));
+    SCHK(s, hipStreamWaitEvent(s->stream, s->ev_out, 0));
+    return FSC_OK;
+}
+
+int fsc_sur_gather(fsc_sur *s, const float *dev_snaps, int K, int R, const int *host_t,
+                   const int *host_r, int batch, int dt, int sy, int sx, int transpose,
+                   float *dev_out) {
+    if (!s || !dev_snaps || !host_t || !host_r || !dev_out || K < 1 || R < 1) return FSC_E_INVAL;
+    if (batch < 1 || batch > GATHER_MAX || batch > s->maxB)
+        return sur_fail(s, FSC_E_INVAL, "gather batch out of range");
+    if (transpose && s->H != s->W) return sur_fail(s, FSC_E_INVAL, "transpose needs H == W");
+    GatherIdx idx{};
+    for (int b = 0; b < batch; ++b) {
+        if (host_t[b] + dt < 0 || host_t[b] + dt >= K || host_r[b] < 0 || host_r[b] >= R)
+            return sur_fail(s, FSC_E_INVAL, "gather index out of the snapshot stack");
+        idx.t[b] = host_t[b];
+        idx.r[b] = host_r[b];
+    }
+    const int HW = s->H * s->W;
+    const dim3 g(unsigned((HW + 255) / 256), unsigned(batch));
+    hipLaunchKernelGGL(k_gather, g, dim3(256), 0, s->stream, dev_snaps, R, s->H, s->W, idx, dt,
+                       ((sy % s->H) + s->H) % s->H, ((sx % s->W) + s->W) % s->W, transpose ? 1 : 0,
+                       dev_out);
+    SCHK(s, hipGetLastError());
+    return FSC_OK;
+}
+
+int fsc_stack_scales(const float *dev_snaps, int K, int64_t per_snap, int t_first, double centre,
+                     double *host_in_std, double *host_out_std, void *stream) {
+    if (!dev_snaps || K < 2 || per_snap < 1 || t_first < 0 || t_first > K - 2 || !host_in_std ||
+        !host_out_std)
+        return FSC_E_INVAL;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nb = 1024;
+    double *part = nullptr;
+    if (hipMalloc(&part, sizeof(double) * 4 * nb) != hipSuccess) return FSC_E_OOM;
+    hipLaunchKernelGGL(k_stack_moments, dim3(nb), dim3(256), 0, st, dev_snaps, K, per_snap, t_first,
+                       centre, part);
+    std::vector<double> h(4 * nb);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), part, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(part);
+    if (e != hipSuccess) return FSC_E_HIP;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < nb; ++b)
+        for (int q = 0; q < 4; ++q) a[q] += h[4 * b + q];
+    const double n = double(K - t_first) * double(per_snap);
+    const double nd = double(K - 1 - t_first) * double(per_snap);
+    *host_in_std = std::sqrt((a[1] - a[0] * a[0] / n) / (n - 1.0));
+    *host_out_std = std::sqrt((a[3] - a[2] * a[2] / nd) / (nd - 1.0));
     return FSC_OK;
 }
 

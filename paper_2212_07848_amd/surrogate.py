@@ -23,7 +23,9 @@ import numpy as np
 from . import _lib as F
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-MODEL_PATH = os.path.join(HERE, "surrogate_model.npz")
+MODEL_PATH = os.path.join(HERE, "surrogate_model.npz")  # 9 layers, two input channels
+# the network the workload names: 5 layers (1 -> 32 -> 32 -> 32 -> 32 -> 1)
+MODEL_5X1_PATH = os.path.join(HERE, "surrogate_model_5layer_1ch.npz")
 
 QUENCH = dict(D=2, stencil=8, precision="fp32", T_hat=0.7, rho0=1.0, kBT=1e-4)
 
@@ -61,51 +63,48 @@ def run_quench(torch, seeds, n=1024, factor=8, stride=256, n_snap=80, seed_base=
     return out, t_lbm
 
 
-def _batches(torch, snaps, t_first, batch, gen, m, ahead=2):
-    """Random (prev, cur, next_1, .., next_ahead) stacks [batch][m][m] from the
-    snapshot tensor [K][R][m][m] (next_j is j strides after cur), with a
-    common random periodic shift and, on every other call, a transpose (the
-    lattice's symmetries)."""
-    K, R = snaps.shape[:2]
-    ti = torch.randint(t_first, K - ahead, (batch,), device="cuda", generator=gen)
-    ri = torch.randint(0, R, (batch,), device="cuda", generator=gen)
-    sh = torch.randint(0, m, (2,), device="cuda", generator=gen).tolist()
-    out = []
-    for dt in range(-1, ahead + 1):
-        out.append(torch.roll(snaps[ti + dt, ri], shifts=sh, dims=(1, 2)))
-    return out
+def _draw_batch(rng, K, R, t_first, batch, m, ahead):
+    """Random batch indices (snapshot t, run r), a common periodic shift and
+    the transpose flag: the lattice's symmetries augment the data."""
+    t = rng.integers(t_first, K - ahead, size=batch)
+    r = rng.integers(0, R, size=batch)
+    shift = (int(rng.integers(0, m)), int(rng.integers(0, m)))
+    return t, r, shift
 
 
 def train(torch, snaps, t_first, layers=7, in_ch=2, steps=6000, batch=32, lr=1e-3, push=0.5,
           push_depth=1, seed=0, log=None):
     """Trains on snapshot pairs (k, k+1), k >= t_first, with the previous
-    snapshot as second input channel.  After the first tenth of the steps, a
-    fraction `push` of every batch starts from the network's own rollout of
-    d = 1..push_depth strides (no gradient through it; the pushed rows are
-    split evenly over d) and is trained against the snapshot d + 1 strides
-    ahead: the network learns to correct the errors its rollouts make."""
+    snapshot as second input channel (in_ch = 2).  After the first tenth of the
+    steps, a fraction `push` of every batch starts from the network's own
+    rollout of d = 1..push_depth strides (no gradient through it; the pushed
+    rows are split evenly over d) and is trained against the snapshot d + 1
+    strides ahead: the network learns to correct the errors its rollouts
+    make.  Batches are gathered by the library (fsc_sur_gather) with random
+    periodic shifts and, every other step, a transpose; the input and output
+    scales come from the library's FP64 moments of the stack."""
     K, R, m, _ = snaps.shape
     mean = 1.0
-    in_scale = float((snaps[t_first:] - mean).std().item())
-    out_scale = float((snaps[t_first + 1:] - snaps[t_first:-1]).std().item())
+    in_scale, out_scale = F.stack_scales(snaps[t_first:], 0, centre=mean)
     sur = F.Surrogate(layers, m, m, batch, seed=seed, in_ch=in_ch)
     sur.set_norm(mean, in_scale, out_scale)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
+    rng = np.random.default_rng(seed)
     bufs = [torch.empty((batch, m, m), dtype=torch.float32, device="cuda") for _ in range(4)]
     prev_b, cur_b, tgt_b, pred_b = bufs
+    nxt_b = [torch.empty((batch, m, m), dtype=torch.float32, device="cuda")
+             for _ in range(push_depth + 1)]
     losses = []
     n_push = int(round(push * batch))
     # rows [edges[d-1], edges[d]) of the batch are pushed d strides
     edges = [round(n_push * d / push_depth) for d in range(push_depth + 1)]
     for it in range(steps):
-        prev, cur, *nxt = _batches(torch, snaps, t_first, batch, gen, m, ahead=push_depth + 1)
-        if it % 2:
-            prev, cur = prev.transpose(1, 2), cur.transpose(1, 2)
-            nxt = [v.transpose(1, 2) for v in nxt]
-        prev_b.copy_(prev)
-        cur_b.copy_(cur)
-        tgt_b.copy_(nxt[0])
+        t, r, shift = _draw_batch(rng, K, R, t_first, batch, m, push_depth + 1)
+        tr = bool(it % 2)
+        sur.gather(snaps, t, r, -1, shift, tr, prev_b)
+        sur.gather(snaps, t, r, 0, shift, tr, cur_b)
+        for d in range(push_depth + 1):
+            sur.gather(snaps, t, r, d + 1, shift, tr, nxt_b[d])
+        tgt_b.copy_(nxt_b[0])
         if n_push and it >= steps // 10:
             for d in range(1, push_depth + 1):
                 a, b = edges[d - 1], edges[d]
@@ -115,7 +114,7 @@ def train(torch, snaps, t_first, layers=7, in_ch=2, steps=6000, batch=32, lr=1e-
                     sur.forward(prev_b[a:b], cur_b[a:b], pred_b[a:b], b - a)
                     prev_b[a:b].copy_(cur_b[a:b])
                     cur_b[a:b].copy_(pred_b[a:b])
-                tgt_b[a:b].copy_(nxt[d][a:b])
+                tgt_b[a:b].copy_(nxt_b[d][a:b])
         rate = lr * 0.5 * (1 + math.cos(math.pi * it / steps))
         loss = sur.train_step(prev_b, cur_b, tgt_b, batch, max(rate, 1e-5),
                               want_loss=(it % 100 == 0))
@@ -129,19 +128,25 @@ def train(torch, snaps, t_first, layers=7, in_ch=2, steps=6000, batch=32, lr=1e-
                      pairs=int((K - 2 - t_first) * R))
 
 
-def rollout(torch, sur, prev, start, n_out, batch):
-    """Applies the surrogate n_out times from (prev, start) [batch][m][m];
-    returns [n_out + 1][batch][m][m] and the wall time of the passes."""
+def rollout(torch, sur, prev, start, n_out, batch, reps=3):
+    """Applies the surrogate n_out times from (prev, start) [batch][m][m]
+    (one captured graph of the n_out passes, fsc_sur_rollout); returns
+    [n_out + 1][batch][m][m] and the wall time of the passes (the fastest of
+    `reps` replays after a first one that captures the graph)."""
     m = start.shape[-1]
     traj = torch.zeros((n_out + 1, batch, m, m), dtype=torch.float32, device="cuda")
     traj[0].copy_(start)
     prev = prev.contiguous()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(n_out):
-        sur.forward(prev if k == 0 else traj[k - 1], traj[k], traj[k + 1], batch)
-    torch.cuda.synchronize()
-    return traj, time.perf_counter() - t0
+    sur.rollout(prev, traj, batch, n_out)  # capture
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sur.rollout(prev, traj, batch, n_out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return traj, best
 
 
 def sk_error(torch, a, b, m, kmax_shell):
@@ -185,10 +190,16 @@ def evaluate(torch, sur, seeds, n=1024, factor=8, stride=256, t0_snaps=(4, 8, 16
             pers, _, _ = sk_error(torch, snaps[t0], snaps[t0 + k], m, kmax)
             rows.append(dict(t=(t0 + k) * stride, sk_rel_err=err, persistence_err=pers,
                              L_surrogate=L_sur * factor, L_lbm=L_lbm * factor))
-        lbm_s = t_lbm * n_out / n_snap  # lattice time for the same n_out strides
-        starts.append(dict(t0=t0 * stride, rows=rows, horizon_5pct=horizon(rows),
+        per = t_lbm / n_snap  # lattice seconds per stride
+        lbm_s = per * n_out  # lattice time for the same n_out strides
+        h = horizon(rows)
+        # reaching t0 + h strides: the lattice alone, against the lattice to t0
+        # (the warm-up the rollout starts from) plus h surrogate strides
+        with_warm = (t0 + h) * per / (t0 * per + t_sur * h / n_out) if h else None
+        starts.append(dict(t0=t0 * stride, rows=rows, horizon_5pct=h,
                            persistence_horizon_5pct=horizon(rows, key="persistence_err"),
-                           lbm_seconds=lbm_s, surrogate_seconds=t_sur, speedup=lbm_s / t_sur))
+                           lbm_seconds=lbm_s, surrogate_seconds=t_sur, speedup=lbm_s / t_sur,
+                           speedup_with_warmup=with_warm, warmup_lattice_seconds=t0 * per))
     return dict(starts=starts, seeds=list(seeds), n=n, stride=stride, n_out=n_out)
 
 
@@ -223,14 +234,18 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser(description="train and evaluate the coarse-grained surrogate")
     ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--train-seeds", type=int, default=128)
-    ap.add_argument("--eval-seeds", type=int, default=8)
+    ap.add_argument("--train-seeds", type=int, default=200)
+    ap.add_argument("--eval-seeds", type=int, default=16)
     ap.add_argument("--snaps", type=int, default=40)
     ap.add_argument("--t-first", type=int, default=4)
-    ap.add_argument("--steps", type=int, default=6000)
-    ap.add_argument("--layers", type=int, nargs="+", default=[7, 5])
-    ap.add_argument("--push-depth", type=int, default=1)
-    ap.add_argument("--save", action="store_true", help="store the first model in the package")
+    ap.add_argument("--steps", type=int, default=12000)
+    ap.add_argument("--models", nargs="+", default=["9:2", "5:1"],
+                    help="networks to train, as layers:input_channels")
+    ap.add_argument("--push-depth", type=int, default=2)
+    ap.add_argument("--save", action="store_true",
+                    help="store 9:2 as the package model and 5:1 as the five-layer model")
+    ap.add_argument("--save-dir", default=None,
+                    help="with --save: directory for the model files (default: the package)")
     ap.add_argument("--out", default=os.path.join(os.getcwd(), "surrogate_eval.json"))
     a = ap.parse_args(argv)
     t0 = time.perf_counter()
@@ -239,17 +254,22 @@ def main(argv=None):
           flush=True)
     ev_snaps, ev_t = run_quench(torch, range(a.eval_seeds), n=a.n, n_snap=40, seed_base=1000)
     results = []
-    for k, layers in enumerate(a.layers):
+    for spec in a.models:
+        layers, in_ch = (int(v) for v in spec.split(":"))
         t1 = time.perf_counter()
-        sur, meta = train(torch, snaps, a.t_first, layers=layers, steps=a.steps,
+        sur, meta = train(torch, snaps, a.t_first, layers=layers, in_ch=in_ch, steps=a.steps,
                           push_depth=a.push_depth, log=lambda s: print(s, flush=True))
         meta["train_seconds"] = time.perf_counter() - t1
         ev = evaluate(torch, sur, range(a.eval_seeds), n=a.n, snaps=ev_snaps, t_lbm=ev_t)
         meta.update(dict(train_seeds=a.train_seeds, snaps=a.snaps, t_first=a.t_first, n=a.n,
                          eval=ev, summary=summary(ev)))
-        print(json.dumps(dict(layers=layers, summary=meta["summary"])), flush=True)
-        if a.save and k == 0:
-            save_model(sur, meta)
+        print(json.dumps(dict(layers=layers, in_ch=in_ch, summary=meta["summary"])), flush=True)
+        dest = {"9:2": MODEL_PATH, "5:1": MODEL_5X1_PATH}.get(spec)
+        if a.save and dest:
+            if a.save_dir:
+                os.makedirs(a.save_dir, exist_ok=True)
+                dest = os.path.join(a.save_dir, os.path.basename(dest))
+            save_model(sur, meta, dest)
         results.append(meta)
         sur.close()
     with open(a.out, "w") as fh:

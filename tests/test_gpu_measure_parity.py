@@ -15,6 +15,8 @@ a millionth of the mean bin; reductions 1e-6 (FP32) / 1e-12 (FP64) of the
 total mass; the noise increment within 1e-3 of the oracle's, relative to its
 largest element.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -123,6 +125,14 @@ def test_stats_match_oracle_sums(D, shape, precision):
     with fsc.Lattice(_p(shape, precision, T_hat=0.9, rho0=rho0, kBT=0.0, replica=0)) as lat:
         lat.set_populations(f, 5)
         st = lat.stats()
+        # the boundary's names for the same reductions and the density read
+        m2, p2 = lat.conserved()
+        assert m2 == st["mass"] and np.array_equal(p2, st["mom"])
+        rho_a = lat.density()
+        rho_b = np.empty(shape)
+        assert fsc.lib().fsc_read_density(
+            lat._h, rho_b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
+        assert np.array_equal(rho_a, rho_b)
     mass, mom = O.conserved(f)
     rho = O.density(f)
     tol = 1e-6 if precision == "fp32" else 1e-12

@@ -185,3 +185,63 @@ def test_trained_model_beats_persistence_on_held_out_seeds():
         assert abs(r["L_surrogate"] / r["L_lbm"] - 1) < 0.03
     assert st["speedup"] > 10
     sur.close()
+
+
+def test_rollout_graph_equals_repeated_forward_passes():
+    # fsc_sur_rollout replays a captured graph of the passes: bit-identical to
+    # calling fsc_sur_forward pass by pass, twice in a row (the second replay
+    # reuses the graph)
+    rng = np.random.default_rng(12)
+    B, H, W, layers, passes = 3, 32, 64, 5, 4
+    p = _net(8, L=layers, in_ch=2).astype(np.float32)
+    sur = fsc.Surrogate(layers, H, W, B, seed=0, in_ch=2)
+    sur.set_params(p)
+    sur.set_norm(1.0, 0.3, 0.05)
+    rho = (1.0 + 0.3 * rng.normal(size=(B, H, W))).astype(np.float32)
+    prev = (rho + 0.05 * rng.normal(size=rho.shape)).astype(np.float32)
+    dprev = _dev(prev)
+    ref = torch.zeros((passes + 1, B, H, W), dtype=torch.float32, device="cuda")
+    ref[0].copy_(_dev(rho))
+    for k in range(passes):
+        sur.forward(dprev if k == 0 else ref[k - 1], ref[k], ref[k + 1], B)
+    traj = torch.zeros_like(ref)
+    traj[0].copy_(_dev(rho))
+    for _ in range(2):
+        sur.rollout(dprev, traj, B, passes)
+        torch.cuda.synchronize()
+        assert torch.equal(traj, ref)
+    sur.close()
+
+
+def test_gather_is_the_shifted_and_transposed_snapshot():
+    rng = np.random.default_rng(13)
+    K, R, m, batch = 7, 5, 64, 9
+    snaps = rng.normal(size=(K, R, m, m)).astype(np.float32)
+    d = _dev(snaps)
+    sur = fsc.Surrogate(3, m, m, 16, seed=0, in_ch=2)
+    out = torch.zeros((batch, m, m), dtype=torch.float32, device="cuda")
+    for dt, shift, tr in ((0, (3, 61), False), (-1, (0, 5), True), (2, (63, 0), True)):
+        t = rng.integers(1, K - 2, size=batch)
+        r = rng.integers(0, R, size=batch)
+        sur.gather(d, t, r, dt, shift, tr, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        for b in range(batch):
+            want = np.roll(snaps[t[b] + dt, r[b]], shift=shift, axis=(0, 1))
+            if tr:
+                want = want.T
+            assert np.array_equal(got[b], want)
+    with pytest.raises(fsc.FscError):
+        sur.gather(d, [K - 1], [0], 1, (0, 0), False, out)  # past the stack
+    sur.close()
+
+
+def test_stack_scales_match_fp64_moments():
+    rng = np.random.default_rng(14)
+    K, R, m, t_first = 9, 3, 32, 2
+    snaps = (1.0 + 0.2 * rng.normal(size=(K, R, m, m))).astype(np.float32)
+    a, b = fsc.stack_scales(_dev(snaps), t_first)
+    x = snaps[t_first:].astype(np.float64)
+    dx = (snaps[t_first + 1:].astype(np.float64) - snaps[t_first:-1].astype(np.float64))
+    assert a == pytest.approx(x.std(ddof=1), rel=1e-12)
+    assert b == pytest.approx(dx.std(ddof=1), rel=1e-12)
