@@ -47,16 +47,62 @@ def _newest_header() -> float:
     return max(os.path.getmtime(h) for h in hs)
 
 
+# The fused step kernels must not spill vector registers or use scratch: a
+# spill to scratch memory costs them a large part of their speed, and the
+# FP64 D3Q19 form once gave wrong values next to the register limit.  Their
+# translation units are compiled with the compiler's resource report, which is
+# checked here; SGPR spills (to vector-register lanes) are logged.
+STEP_SOURCES = [s for s in SOURCES if s.startswith("fsc_step") and s != "fsc_step.hip"]
+
+
+def resource_report(stderr: str):
+    """Per kernel: VGPRs, AGPRs, scratch bytes per lane, VGPR and SGPR spills,
+    from the -Rpass-analysis=kernel-resource-usage remarks."""
+    keys = {"VGPRs": "vgpr", "AGPRs": "agpr", "ScratchSize [bytes/lane]": "scratch",
+            "VGPRs Spill": "vgpr_spill", "SGPRs Spill": "sgpr_spill",
+            "Occupancy [waves/SIMD]": "waves"}
+    rows, cur = [], None
+    for line in stderr.splitlines():
+        if "remark:" not in line:
+            continue
+        body = line.split("remark:", 1)[1].strip()
+        if body.startswith("Function Name:"):
+            cur = {"name": body.split(":", 1)[1].split()[0]}
+            rows.append(cur)
+            continue
+        if cur is None or ":" not in body:
+            continue
+        k, v = body.split(":", 1)
+        v = v.split("[-Rpass")[0].strip()
+        if k.strip() in keys and v.isdigit():
+            cur[keys[k.strip()]] = int(v)
+    return rows
+
+
 def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     if incremental and os.path.exists(obj):
         t = os.path.getmtime(obj)
         if t > os.path.getmtime(os.path.join(CSRC, src)) and t > _newest_header():
             return obj
-    cmd = [HIPCC, "-c", *CFLAGS, os.path.join(CSRC, src), "-o", obj]
+    check = src in STEP_SOURCES
+    extra = ["-Rpass-analysis=kernel-resource-usage"] if check else []
+    cmd = [HIPCC, "-c", *CFLAGS, *extra, os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if check:
+        rows = resource_report(r.stderr)
+        bad = [k for k in rows if k.get("scratch", 0) > 0 or k.get("vgpr_spill", 0) > 0]
+        with open(os.path.join(BUILD, os.path.splitext(src)[0] + ".resources.txt"), "w") as fh:
+            for k in rows:
+                fh.write(" ".join(f"{a}={k[a]}" for a in ("vgpr", "agpr", "scratch", "vgpr_spill",
+                                                          "sgpr_spill", "waves") if a in k)
+                         + f" {k['name']}\n")
+        if bad:
+            os.remove(obj)
+            raise RuntimeError(f"{src}: step kernels with scratch or VGPR spills: "
+                               + ", ".join(k["name"] for k in bad))
     return obj
 
 
@@ -74,6 +120,15 @@ def build(verbose: bool = False, jobs: int | None = None, incremental: bool = Fa
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB} from {len(objs)} objects")
+        worst = 0
+        for src in STEP_SOURCES:
+            path = os.path.join(BUILD, os.path.splitext(src)[0] + ".resources.txt")
+            if os.path.exists(path):
+                for line in open(path):
+                    worst = max([worst] + [int(t.split("=")[1]) for t in line.split()
+                                           if t.startswith("sgpr_spill=")])
+        print(f"step kernels: no scratch, no VGPR spills; largest SGPR spill count {worst} "
+              f"(per-kernel report in {BUILD}/*.resources.txt)")
     return LIB
 
 

@@ -420,6 +420,13 @@ __global__ void __launch_bounds__(TX *TY)
     uint32_t xo_r[3][3];
     make_offsets(has_ring ? wrap_any(x0 - R + rex, nx) : 0,
                  (D == 3 && has_ring) ? wrap_any(y0 - RY + rey, ny) : 0, xo_r);
+    // Which lanes load the ring plane.  FP32: the lanes with a ring node.
+    // FP64: every lane (the others load node (0, 0), an in-range offset, and
+    // discard it), so that the ring registers are never written under a
+    // partial execution mask -- the FP64 kernels run close to the register
+    // limit, where the FP64 D3Q19 form with prefetch once gave wrong values
+    // in lanes without a ring node.
+    const bool ring_load = sizeof(real) == 8 || has_ring;
 
     const uint32_t pbytes = uint32_t(plane) * ES;
     auto cm = [](int i) { return L::c(i, D - 1); };
@@ -488,7 +495,7 @@ __global__ void __launch_bounds__(TX *TY)
     for (int k = -R; k < R; ++k) {
         real tm[Q];
         load_plane(first + dir * k, xo_m, tm);
-        if (has_ring) load_plane(first + dir * k, xo_r, RG);
+        if (ring_load) load_plane(first + dir * k, xo_r, RG);
         put_psi(first + dir * k, tm, RG);
         if (k >= 0) {
 #pragma unroll
@@ -496,7 +503,7 @@ __global__ void __launch_bounds__(TX *TY)
         }
     }
     // prefetch: ring plane first + dir R, main planes first + dir (R + q), q < PF
-    if (RING_PF && has_ring) load_plane(first + dir * R, xo_r, RG);
+    if (RING_PF && ring_load) load_plane(first + dir * R, xo_r, RG);
 #pragma unroll
     for (int q = 0; q < PF; ++q)
         if (q < len) load_plane(first + dir * (R + q), xo_m, F[R + q]);
@@ -523,10 +530,10 @@ __global__ void __launch_bounds__(TX *TY)
             // plane s + dir R has arrived: its dpsi goes to LDS
             // PF = 0: plane s + dir R is loaded here, right before its dpsi is needed
             if constexpr (PF == 0) load_plane(s + dir * R, xo_m, F[(j + R) % NSLOT]);
-            if (!RING_PF && has_ring) load_plane(s + dir * R, xo_r, RG);
+            if (!RING_PF && ring_load) load_plane(s + dir * R, xo_r, RG);
             put_psi(s + dir * R, F[(j + R) % NSLOT], RG);
             // prefetch: ring plane s + dir (R + 1), main plane s + dir (R + PF)
-            if (RING_PF && has_ring && m + 1 < len) load_plane(s + dir * (R + 1), xo_r, RG);
+            if (RING_PF && ring_load && m + 1 < len) load_plane(s + dir * (R + 1), xo_r, RG);
             if (PF > 0 && m + PF < len) load_plane(s + dir * (R + PF), xo_m, F[(j + R + PF) % NSLOT]);
             __syncthreads();
 

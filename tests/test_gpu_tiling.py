@@ -21,8 +21,10 @@ CASES = [
     (2, (9, 6), 8, "fp32"),      # narrowest two-step width for E8 (2R + 2)
     (2, (41, 256), 8, "fp32"),
     (3, (23, 45, 37), 4, "fp32"),
+    (3, (2, 3, 5), 4, "fp32"),   # thinner than the halo in every direction: all wraps
     (2, (40, 77), 8, "fp64"),
     (3, (12, 19, 21), 4, "fp64"),
+    (3, (9, 17, 40), 4, "fp64"),  # ragged in x (32 + 8) and y (8 + 8 + 1)
 ]
 
 
