@@ -76,3 +76,33 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stdout
+
+
+def test_kernel_view_prices_a_launch_by_its_nodes():
+    # one launch reads and writes every population of every node once, also
+    # when it advances two steps: 72 B per node for D2Q9, 152 B for D3Q19
+    q = dict(D=2, nx=4096, ny=4096, nz=1, stencil=8, precision="fp32")
+    two = dict(tx=192, ty=1, pf=0, blocks=1012, steps=2)
+    kv = bench.kernel_view(q, two, t_step=200e-6)
+    assert kv["kernel"] == "k_step2<StencilE8_2D, float, true, 192, 1>"
+    assert kv["nodes_per_launch"] == 4096 * 4096 and kv["lups_per_launch"] == 2 * 4096 * 4096
+    assert kv["algorithmic_bytes_per_launch"] == 72 * 4096 * 4096
+    assert kv["avg_launch_us"] == pytest.approx(400.0)
+    assert kv["hbm_gbs"] == pytest.approx(72 * 4096 * 4096 / 400e-6 / 1e9)
+    c4 = dict(D=3, nx=256, ny=256, nz=256, stencil=4, precision="fp32")
+    one = dict(tx=64, ty=4, pf=0, blocks=512, steps=1)
+    kv3 = bench.kernel_view(c4, one, t_step=565e-6)
+    assert kv3["kernel"] == "k_step<D3Q19, StencilE4_3D, float, true, 64, 4, 0, false>"
+    assert kv3["algorithmic_bytes_per_launch"] == 152 * 256 ** 3
+
+
+def test_bench_defaults_time_the_whole_workload():
+    # the default run is the deep quench's 50 000 steps in periods of 500
+    # lattice steps, each ending in its S(k,t)/L(t) sample
+    import fsc_inputs as I
+    assert I.DEEP_QUENCH["sk_every"] == 500 and I.DEEP_QUENCH["steps"] == 50000
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    assert 'ap.add_argument("--steps", type=int, default=100)' in src
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--kernel-steps", "3"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "kernel-steps" in r.stdout
