@@ -148,18 +148,23 @@ def ingest_pmc(fetch_csv: str, write_csv: str, valu_csv: str, out_path: str):
                             valu_insts_per_launch=int(valu[key]) if key in valu else None))
     for e in entries:
         e["kernel"] = e["kernel"].replace("fsc::", "")
-    # kept: every launch shape (march length) of the two-step kernels with noise
-    # (the headline quench and the ensemble; the roofline reads the autotuner's
-    # choice among them), and of every other kernel the shape with the most
-    # launches (the one timed; the others are tuning trials)
-    fams = ("k_step2<StencilE4_2D, float, true,", "k_step2<StencilE8_2D, float, true,")
+    # kept: of every kernel the launch shape with the most launches (the one
+    # timed; the others are tuning trials), and of the two-step kernels with
+    # noise also the shapes near the tuned march lengths (within a factor 2
+    # of the timed one), where another box's autotuner may land
     best = {}
     for e in entries:
-        if not e["kernel"].startswith(fams):
-            if e["kernel"] not in best or e["launches"] > best[e["kernel"]]["launches"]:
-                best[e["kernel"]] = e
-    entries = [e for e in entries if e["kernel"].startswith(fams)] + sorted(best.values(),
-                                                                           key=lambda e: e["kernel"])
+        if e["kernel"] not in best or e["launches"] > best[e["kernel"]]["launches"]:
+            best[e["kernel"]] = e
+    fams = ("k_step2<StencilE4_2D, float, true,", "k_step2<StencilE8_2D, float, true,")
+    keep = set(id(e) for e in best.values())
+    for e in entries:
+        b = best[e["kernel"]]
+        if e["kernel"].startswith(fams) and b["launches"] > 11 and \
+                0.5 <= e["grid_threads"] / b["grid_threads"] <= 2.0:
+            keep.add(id(e))
+    entries = sorted((e for e in entries if id(e) in keep),
+                     key=lambda e: (e["kernel"], e["grid_threads"]))
     doc = dict(kernel_hash=kernel_hash(),
                commands=[f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch_dir> -o run "
                          f"-- python3 bench.py {PMC_ARGS}",
