@@ -54,6 +54,39 @@ __device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// Epilogue of a C -> C layer tile computed as D = W (32 channels) x A (16
+// pixels): lane l holds channels nt*16 + 4 (l/16) + r, r = 0..3, of pixel
+// l % 16 in acc[nt], so each lane writes four consecutive channels of its
+// pixel (8-byte BF16 and 16-byte FP32 stores, NHWC).
+//   forward:  z = acc + bias (kept if ZOUT), a = bf16(SiLU(z))
+//   backward: a = bf16(acc SiLU'(z_prev))
+template <bool BWD, bool ZOUT>
+__device__ __forceinline__ void mid_epilogue(const f32x4 (&acc)[2], size_t pix, int g,
+                                             const f32x4 (&bv)[2], float *__restrict__ zout,
+                                             bf16 *__restrict__ aout,
+                                             const float *__restrict__ zprev) {
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const size_t o = pix * SC + nt * 16 + 4 * g;
+        bf16x4 out;
+        if (BWD) {
+            const f32x4 zp = *reinterpret_cast<const f32x4 *>(zprev + o);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[r] = bf16(acc[nt][r] * dsilu(zp[r]));
+        } else {
+            f32x4 zz;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) zz[r] = acc[nt][r] + bv[nt][r];
+            if (ZOUT) *reinterpret_cast<f32x4 *>(zout + o) = zz;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[r] = bf16(silu(zz[r]));
+        }
+        *reinterpret_cast<bf16x4 *>(aout + o) = out;
+    }
+}
+
 __global__ void k_mfma_probe(const float *A, const float *B, float *Cm) {
     const int l = threadIdx.x, r16 = l & 15, g = l >> 4;
     bf16x8 a, b;
@@ -136,8 +169,11 @@ __global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, cons
 
 // ---------------------------------------------------------------------------
 // C -> C layer on the matrix cores.  A wave computes 16 consecutive pixels of
-// one image row for all 32 output channels: 9 taps x 2 column tiles of
-// 16x16x32 MFMA, with the packed weights held in registers.
+// one image row for all 32 output channels: 9 taps x 2 tiles of 16x16x32
+// MFMA, with the packed weights held in registers.  The weights are the A
+// operand (16 output channels by 32 input channels) and the activations the B
+// operand (32 input channels by 16 pixels), so that each lane's results are
+// four consecutive channels of one pixel (mid_epilogue).
 //   forward:   out = conv(a_in; W) + bias -> z (FP32), SiLU(z) (BF16)
 //   backward:  out = conv(dZ; W') (W' = tap-flipped transpose: the adjoint)
 //              -> dZ_prev = out * SiLU'(z_prev) (BF16)
@@ -158,16 +194,16 @@ __global__ void __launch_bounds__(256) k_mid(const bf16 *__restrict__ ain,
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
             bop[t][nt] = *reinterpret_cast<const bf16x8 *>(wpk + (t * SC + nt * 16 + r16) * SC + g * 8);
-    float bv[2] = {0.f, 0.f};
+    f32x4 bv[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
     if (!BWD) {
-        bv[0] = bias[r16];
-        bv[1] = bias[16 + r16];
+        bv[0] = *reinterpret_cast<const f32x4 *>(bias + 4 * g);
+        bv[1] = *reinterpret_cast<const f32x4 *>(bias + 16 + 4 * g);
     }
     const int tiles = (B * H * W) / 16;
     for (int tile = wave; tile < tiles; tile += nwaves) {
         const int p0 = tile * 16;
         const int x0 = p0 % W, t2 = p0 / W, y = t2 % H, n = t2 / H;
-        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky) {
             const int rowbase = (n * H + wrapi(y + ky - 1, H)) * W;
@@ -175,26 +211,11 @@ __global__ void __launch_bounds__(256) k_mid(const bf16 *__restrict__ ain,
             for (int kx = 0; kx < 3; ++kx) {
                 const int q = rowbase + wrapi(x0 + r16 + kx - 1, W);
                 const bf16x8 aop = *reinterpret_cast<const bf16x8 *>(ain + size_t(q) * SC + g * 8);
-                acc0 = mfma16(aop, bop[ky * 3 + kx][0], acc0);
-                acc1 = mfma16(aop, bop[ky * 3 + kx][1], acc1);
+                acc[0] = mfma16(bop[ky * 3 + kx][0], aop, acc[0]);
+                acc[1] = mfma16(bop[ky * 3 + kx][1], aop, acc[1]);
             }
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const size_t pix = size_t(p0 + 4 * g + r);
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                const int co = nt * 16 + r16;
-                const float v = nt ? acc1[r] : acc0[r];
-                if (BWD) {
-                    aout[pix * SC + co] = bf16(v * dsilu(zprev[pix * SC + co]));
-                } else {
-                    const float zz = v + bv[nt];
-                    if (ZOUT) zout[pix * SC + co] = zz;
-                    aout[pix * SC + co] = bf16(silu(zz));
-                }
-            }
-        }
+        mid_epilogue<BWD, ZOUT>(acc, size_t(p0 + r16), g, bv, zout, aout, zprev);
     }
 }
 
@@ -242,10 +263,10 @@ __global__ void __launch_bounds__(256) k_mid_lds(const bf16 *__restrict__ ain,
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
             bop[t][nt] = *reinterpret_cast<const bf16x8 *>(wpk + (t * SC + nt * 16 + r16) * SC + g * 8);
-    float bv[2] = {0.f, 0.f};
+    f32x4 bv[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
     if (!BWD) {
-        bv[0] = bias[r16];
-        bv[1] = bias[16 + r16];
+        bv[0] = *reinterpret_cast<const f32x4 *>(bias + 4 * g);
+        bv[1] = *reinterpret_cast<const f32x4 *>(bias + 16 + 4 * g);
     }
     __syncthreads();
     constexpr int TPW = MR * MW / 64;  // MFMA tiles per wave
@@ -254,33 +275,18 @@ __global__ void __launch_bounds__(256) k_mid_lds(const bf16 *__restrict__ ain,
         const int k = wave * TPW + j;
         const int row = k / (MW / 16), tx = k % (MW / 16);
         const int y = y0 + row;
-        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
                 const int pc = (row + ky) * LW + tx * 16 + r16 + kx;
                 const bf16x8 aop = *reinterpret_cast<const bf16x8 *>(tile_in + pc * SC + g * 8);
-                acc0 = mfma16(aop, bop[ky * 3 + kx][0], acc0);
-                acc1 = mfma16(aop, bop[ky * 3 + kx][1], acc1);
+                acc[0] = mfma16(bop[ky * 3 + kx][0], aop, acc[0]);
+                acc[1] = mfma16(bop[ky * 3 + kx][1], aop, acc[1]);
             }
         const size_t p0 = size_t((n * H + y) * W + x0 + tx * 16);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const size_t pix = p0 + 4 * g + r;
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                const int co = nt * 16 + r16;
-                const float v = nt ? acc1[r] : acc0[r];
-                if (BWD) {
-                    aout[pix * SC + co] = bf16(v * dsilu(zprev[pix * SC + co]));
-                } else {
-                    const float zz = v + bv[nt];
-                    if (ZOUT) zout[pix * SC + co] = zz;
-                    aout[pix * SC + co] = bf16(silu(zz));
-                }
-            }
-        }
+        mid_epilogue<BWD, ZOUT>(acc, p0 + r16, g, bv, zout, aout, zprev);
     }
 }
 

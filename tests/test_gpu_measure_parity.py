@@ -246,3 +246,51 @@ def test_noise_increment_at_metastable_kbt_3d(start):
         # in 1e4 of the noise at 1e-13 (the CPU emulation of that rounding
         # gives 2e-4 max, 1e-4 rms)
         assert err <= 2e-3 and rms <= 1e-3
+
+
+# --------------------------------------------------- the small workload -----
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_small_workload_sk_series_matches_oracle_and_linear_theory(precision):
+    # 64^2 D2Q9 E4, T_hat 0.9, n0 0.5, kBT 1e-4, seed 0: 1000 steps with an axis
+    # S(k) sample every 10 steps, as configured.  The accumulated bins equal the
+    # oracle's own trajectory sampled alike (the run is stable, so the two
+    # trajectories stay within the population tolerance), and the sample mean
+    # of each axis mode agrees with the exact linear expectation at the sampled
+    # times (Eq. 16 in the limit) within its statistical error.
+    from oracle import theory as T
+    c = I.SMALL_PARITY
+    L, every, steps = c["nx"], c["sk_every"], c["steps"]
+    p = _p((c["ny"], c["nx"]), precision, T_hat=c["T_hat"], rho0=c["rho0"], kBT=c["kBT"],
+           replica=0, seed=c["seed"])
+    with fsc.Lattice(p) as lat:
+        lat.init_uniform()
+        lat.run(steps, every)
+        s, q, cnt = lat.read_sk(fsc.FSC_SK_AXIS)
+        G = lat.G
+    f = O.uniform_state(2, (c["ny"], c["nx"]), c["rho0"])
+    ref_s = np.zeros_like(s)
+    ref_c = np.zeros_like(cnt)
+    for k in range(steps // every):
+        f = O.step(f, every, G=G, kind=c["stencil"], kBT=c["kBT"], seed=c["seed"], t0=k * every)
+        a_sum, _, a_cnt = O.sk_sample(O.density(f))["axis"]
+        ref_s[:, : a_sum.shape[1]] += a_sum
+        ref_c[:, : a_cnt.shape[1]] += a_cnt
+    assert np.array_equal(cnt, ref_c)
+    # the populations agree to 1e-11 (FP64) / 1e-5 (FP32) relative; P(k) of a
+    # fluctuation field carries twice that relative error, more on low bins
+    rtol = 1e-8 if precision == "fp64" else 5e-3
+    nz = ref_s > 0
+    assert np.all(np.abs(s[nz] - ref_s[nz]) <= rtol * ref_s[nz] + 1e-6 * ref_s[nz].mean())
+    times = every * np.arange(1, steps // every + 1)
+    z = []
+    for m in range(1, L // 2):
+        k = 2 * np.pi * m / L
+        th = T.sk_linear_times([k, 0.0], times, D=2, kind=4, n0=c["rho0"], G=G,
+                               kBT=c["kBT"]).mean()
+        mean = s[:, m].sum() / cnt[:, m].sum()
+        # 4 modes per sample (+-m on two axes), correlated over a few samples
+        err = th / np.sqrt(cnt[:, m].sum() / 4.0)
+        z.append((mean - th) / err)
+    z = np.array(z)
+    print(precision, "z-scores", np.round(z, 2))
+    assert np.abs(z).max() < 5.0 and np.mean(z ** 2) < 4.0
