@@ -12,9 +12,11 @@
 // alone does not determine.
 // conv = 3x3 cross-correlation with circular padding.  The C -> C layers run
 // as implicit GEMMs on v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32
-// accumulation), forward, backward-data and backward-weight; the 1 -> C and
-// C -> 1 layers and the reductions are FP32 vector code.  Parameters are FP32
-// masters updated by Adam; BF16 copies feed the matrix cores.
+// accumulation), forward, backward-data and backward-weight.  The C -> 1
+// forward runs on the matrix cores too, with its FP32 weights split exactly
+// into three BF16 parts; the 1 -> C layer, the other C -> 1 passes and the
+// reductions are FP32 vector code.  Parameters are FP32 masters updated by
+// Adam; BF16 copies feed the matrix cores.
 //
 // Activations are NHWC: pixel p = (n H + y) W + x, channel fastest.
 #include <cmath>
@@ -36,9 +38,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int SC = 32;          // hidden channels
 constexpr int IMG_PARTS = 256;  // segments per image of the per-image FP64 sums
 
-__device__ __forceinline__ float silu(float z) { return z / (1.f + __expf(-z)); }
+// SiLU and its derivative from the hardware exp2 and reciprocal (about one
+// ulp each).  Their results are rounded to bfloat16 (2^-8 relative) or feed
+// FP32 sums, so a correctly rounded exp and division would change nothing
+// but the cost, which in the matrix-core layers is the epilogue's.
+__device__ __forceinline__ float sigmoid(float z) {
+    return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-1.44269504088896341f * z));
+}
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 __device__ __forceinline__ float dsilu(float z) {
-    const float s = 1.f / (1.f + __expf(-z));
+    const float s = sigmoid(z);
     return s * (1.f + z * (1.f - s));
 }
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
@@ -56,35 +65,39 @@ __device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
+// Output channel of row m (0..15) of the A operand in MFMA tile nt (0, 1) of a
+// C -> C layer: rows 4j .. 4j + 3 of tile nt hold channels 8j + 4nt .. 8j +
+// 4nt + 3.  The result rows 4 (l/16) + r of lane l are then channels
+// 8 (l/16) + 4nt + r: over both tiles, the eight consecutive channels
+// 8 (l/16) .. 8 (l/16) + 7 of pixel l % 16, and one 16-byte store per lane
+// writes whole 64-byte pixel records (a wave's store covers 1 KB).
+__device__ __forceinline__ int mid_row_channel(int nt, int m) { return 8 * (m >> 2) + 4 * nt + (m & 3); }
+
 // Epilogue of a C -> C layer tile computed as D = W (32 channels) x A (16
-// pixels): lane l holds channels nt*16 + 4 (l/16) + r, r = 0..3, of pixel
-// l % 16 in acc[nt], so each lane writes four consecutive channels of its
-// pixel (8-byte BF16 and 16-byte FP32 stores, NHWC).
-//   forward:  z = acc + bias (kept if ZOUT), a = bf16(SiLU(z))
+// pixels): lane l holds channels 8 (l/16) + 4nt + r, r = 0..3, of pixel l % 16
+// in acc[nt] (mid_row_channel).  The forward pass starts its accumulators at
+// the bias, so acc is already z.
+//   forward:  z = acc (kept if ZOUT), a = bf16(SiLU(z))
 //   backward: a = bf16(acc SiLU'(z_prev))
 template <bool BWD, bool ZOUT>
 __device__ __forceinline__ void mid_epilogue(const f32x4 (&acc)[2], size_t pix, int g,
-                                             const f32x4 (&bv)[2], float *__restrict__ zout,
-                                             bf16 *__restrict__ aout,
+                                             float *__restrict__ zout, bf16 *__restrict__ aout,
                                              const float *__restrict__ zprev) {
+    const size_t o = pix * SC + 8 * g;
+    bf16x8 out;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
-        const size_t o = pix * SC + nt * 16 + 4 * g;
-        bf16x4 out;
         if (BWD) {
-            const f32x4 zp = *reinterpret_cast<const f32x4 *>(zprev + o);
+            const f32x4 zp = *reinterpret_cast<const f32x4 *>(zprev + o + 4 * nt);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) out[r] = bf16(acc[nt][r] * dsilu(zp[r]));
+            for (int r = 0; r < 4; ++r) out[4 * nt + r] = bf16(acc[nt][r] * dsilu(zp[r]));
         } else {
-            f32x4 zz;
+            if (ZOUT) *reinterpret_cast<f32x4 *>(zout + o + 4 * nt) = acc[nt];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) zz[r] = acc[nt][r] + bv[nt][r];
-            if (ZOUT) *reinterpret_cast<f32x4 *>(zout + o) = zz;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) out[r] = bf16(silu(zz[r]));
+            for (int r = 0; r < 4; ++r) out[4 * nt + r] = bf16(silu(acc[nt][r]));
         }
-        *reinterpret_cast<bf16x4 *>(aout + o) = out;
     }
+    *reinterpret_cast<bf16x8 *>(aout + o) = out;
 }
 
 __global__ void k_mfma_probe(const float *A, const float *B, float *Cm) {
@@ -114,10 +127,13 @@ __global__ void __launch_bounds__(256) k_input(const float *__restrict__ cur,
 }
 
 // ---------------------------------------------------------------------------
-// Layer 0 (K -> C) forward, FP32: one thread per pixel.  ZOUT keeps the FP32
-// pre-activations for the backward pass (training); FUSED forms the network
-// input from the fields on the fly (inference: no X buffer, one launch less).
-// The 32 BF16 activations of a pixel go out as four 16-byte stores.
+// Layer 0 (K -> C) forward, FP32: one lane per pixel computes all 32 output
+// channels.  The weights and biases are the same for every lane, so they are
+// read through the scalar cache and enter the FMAs as scalar operands.  ZOUT
+// keeps the FP32 pre-activations for the backward pass (training); FUSED
+// forms the network input from the fields on the fly (inference: no X buffer,
+// one launch less).  A pixel's 32 BF16 activations go out as four 16-byte
+// stores.
 // ---------------------------------------------------------------------------
 template <int K, bool ZOUT, bool FUSED>
 __global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, const float *__restrict__ cur,
@@ -126,15 +142,8 @@ __global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, cons
                                                const float *__restrict__ w,
                                                const float *__restrict__ b, float *__restrict__ z,
                                                bf16 *__restrict__ a) {
-    // the layer's weights and biases, read by every lane, staged once in LDS
-    __shared__ float ws[SC * K * 9 + SC];
-    for (int i = threadIdx.x; i < SC * K * 9; i += 256) ws[i] = w[i];
-    if (threadIdx.x < SC) ws[SC * K * 9 + threadIdx.x] = b[threadIdx.x];
-    __syncthreads();
-    // four threads per pixel, eight output channels each
     const int P = B * H * W;
-    const int gid = blockIdx.x * 256 + threadIdx.x;
-    const int p = gid >> 2, cg = gid & 3;
+    const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= P) return;
     const int x = p % W, t = p / W, y = t % H, n = t / H;
     float xi[K][9];
@@ -152,19 +161,27 @@ __global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, cons
                 for (int ci = 0; ci < K; ++ci) xi[ci][ky * 3 + kx] = X[q * K + ci];
             }
         }
-    bf16x8 out;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int co = cg * 8 + j;
-        float acc = ws[SC * K * 9 + co];
+    for (int c8 = 0; c8 < SC / 8; ++c8) {
+        bf16x8 out;
+        f32x4 zq[2];
 #pragma unroll
-        for (int ci = 0; ci < K; ++ci)
+        for (int j = 0; j < 8; ++j) {
+            const int co = c8 * 8 + j;
+            float acc = b[co];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) acc += ws[(co * K + ci) * 9 + k] * xi[ci][k];
-        if constexpr (ZOUT) z[size_t(p) * SC + co] = acc;
-        out[j] = bf16(silu(acc));
+            for (int ci = 0; ci < K; ++ci)
+#pragma unroll
+                for (int k = 0; k < 9; ++k) acc += w[(co * K + ci) * 9 + k] * xi[ci][k];
+            zq[j >> 2][j & 3] = acc;
+            out[j] = bf16(silu(acc));
+        }
+        if constexpr (ZOUT) {
+            *reinterpret_cast<f32x4 *>(z + size_t(p) * SC + c8 * 8) = zq[0];
+            *reinterpret_cast<f32x4 *>(z + size_t(p) * SC + c8 * 8 + 4) = zq[1];
+        }
+        *reinterpret_cast<bf16x8 *>(a + size_t(p) * SC + c8 * 8) = out;
     }
-    *reinterpret_cast<bf16x8 *>(a + size_t(p) * SC + cg * 8) = out;
 }
 
 // ---------------------------------------------------------------------------
@@ -172,8 +189,9 @@ __global__ void __launch_bounds__(256) k_first(const float *__restrict__ X, cons
 // one image row for all 32 output channels: 9 taps x 2 tiles of 16x16x32
 // MFMA, with the packed weights held in registers.  The weights are the A
 // operand (16 output channels by 32 input channels) and the activations the B
-// operand (32 input channels by 16 pixels), so that each lane's results are
-// four consecutive channels of one pixel (mid_epilogue).
+// operand (32 input channels by 16 pixels); with the rows ordered by
+// mid_row_channel, each lane's results over the two tiles are eight
+// consecutive channels of one pixel (mid_epilogue).
 //   forward:   out = conv(a_in; W) + bias -> z (FP32), SiLU(z) (BF16)
 //   backward:  out = conv(dZ; W') (W' = tap-flipped transpose: the adjoint)
 //              -> dZ_prev = out * SiLU'(z_prev) (BF16)
@@ -193,17 +211,18 @@ __global__ void __launch_bounds__(256) k_mid(const bf16 *__restrict__ ain,
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
-            bop[t][nt] = *reinterpret_cast<const bf16x8 *>(wpk + (t * SC + nt * 16 + r16) * SC + g * 8);
+            bop[t][nt] = *reinterpret_cast<const bf16x8 *>(
+                wpk + (t * SC + mid_row_channel(nt, r16)) * SC + g * 8);
     f32x4 bv[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
     if (!BWD) {
-        bv[0] = *reinterpret_cast<const f32x4 *>(bias + 4 * g);
-        bv[1] = *reinterpret_cast<const f32x4 *>(bias + 16 + 4 * g);
+        bv[0] = *reinterpret_cast<const f32x4 *>(bias + 8 * g);
+        bv[1] = *reinterpret_cast<const f32x4 *>(bias + 8 * g + 4);
     }
     const int tiles = (B * H * W) / 16;
     for (int tile = wave; tile < tiles; tile += nwaves) {
         const int p0 = tile * 16;
         const int x0 = p0 % W, t2 = p0 / W, y = t2 % H, n = t2 / H;
-        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        f32x4 acc[2] = {bv[0], bv[1]};
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky) {
             const int rowbase = (n * H + wrapi(y + ky - 1, H)) * W;
@@ -215,7 +234,7 @@ __global__ void __launch_bounds__(256) k_mid(const bf16 *__restrict__ ain,
                 acc[1] = mfma16(bop[ky * 3 + kx][1], aop, acc[1]);
             }
         }
-        mid_epilogue<BWD, ZOUT>(acc, size_t(p0 + r16), g, bv, zout, aout, zprev);
+        mid_epilogue<BWD, ZOUT>(acc, size_t(p0 + r16), g, zout, aout, zprev);
     }
 }
 
@@ -262,11 +281,12 @@ __global__ void __launch_bounds__(256) k_mid_lds(const bf16 *__restrict__ ain,
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
-            bop[t][nt] = *reinterpret_cast<const bf16x8 *>(wpk + (t * SC + nt * 16 + r16) * SC + g * 8);
+            bop[t][nt] = *reinterpret_cast<const bf16x8 *>(
+                wpk + (t * SC + mid_row_channel(nt, r16)) * SC + g * 8);
     f32x4 bv[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
     if (!BWD) {
-        bv[0] = *reinterpret_cast<const f32x4 *>(bias + 4 * g);
-        bv[1] = *reinterpret_cast<const f32x4 *>(bias + 16 + 4 * g);
+        bv[0] = *reinterpret_cast<const f32x4 *>(bias + 8 * g);
+        bv[1] = *reinterpret_cast<const f32x4 *>(bias + 8 * g + 4);
     }
     __syncthreads();
     constexpr int TPW = MR * MW / 64;  // MFMA tiles per wave
@@ -275,7 +295,7 @@ __global__ void __launch_bounds__(256) k_mid_lds(const bf16 *__restrict__ ain,
         const int k = wave * TPW + j;
         const int row = k / (MW / 16), tx = k % (MW / 16);
         const int y = y0 + row;
-        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        f32x4 acc[2] = {bv[0], bv[1]};
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
@@ -286,58 +306,82 @@ __global__ void __launch_bounds__(256) k_mid_lds(const bf16 *__restrict__ ain,
                 acc[1] = mfma16(bop[ky * 3 + kx][1], aop, acc[1]);
             }
         const size_t p0 = size_t((n * H + y) * W + x0 + tx * 16);
-        mid_epilogue<BWD, ZOUT>(acc, p0 + r16, g, bv, zout, aout, zprev);
+        mid_epilogue<BWD, ZOUT>(acc, p0 + r16, g, zout, aout, zprev);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Last layer (C -> 1) forward, FP32 from BF16 activations.  Block (image,
-// segment) computes the segment's pixels, four lanes per pixel (eight
-// channels each, combined by lane shuffles), and writes the segment's FP64 sum
-// of y (a block-wide tree in a fixed order).
+// Last layer (C -> 1) forward on the matrix cores.  Its FP32 weights enter as
+// three BF16 parts each, w = hi + mid + lo (k_pack_last; exact for normal FP32
+// values), in rows 0..2 of the A operand (rows 3..15 zero); B is 32 channels
+// by 16 pixels for one tap, and the 9 taps accumulate.  Lane l < 16 ends with
+// the three partial sums of pixel l in acc[0..2]: y = (hi + mid) + lo + bias.
+// The products of BF16 activations with BF16 weight parts are exact and the
+// sums FP32, so y is the FP32 evaluation of the layer up to the order of the
+// sums.  Each wave takes one of the IMG_PARTS segments of an image: its
+// pixels in tiles of 16, two tiles' loads in flight at a time (lanes past the
+// segment repeat its last pixel), and the segment's FP64 sum of y (a fixed
+// lane order).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_last(const bf16 *__restrict__ a, int B, int H, int W,
-                                              const float *__restrict__ w, const float *__restrict__ b,
-                                              float *__restrict__ y, double *__restrict__ part) {
-    __shared__ double sh[4];
-    __shared__ float ws[SC * 9];  // the layer's weights, staged once
-    for (int i = threadIdx.x; i < SC * 9; i += 256) ws[i] = w[i];
-    __syncthreads();
+                                              const bf16 *__restrict__ wl3,
+                                              const float *__restrict__ b, float *__restrict__ y,
+                                              double *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int sg = blockIdx.x * 4 + (threadIdx.x >> 6);  // segment over the batch
+    bf16x8 wop[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        if (r16 < 3) {
+            wop[t] = *reinterpret_cast<const bf16x8 *>(wl3 + (t * 3 + r16) * SC + g * 8);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) wop[t][e] = bf16(0.f);
+        }
+    }
+    const float bias = b[0];
     const int HW = H * W;
-    const int img = blockIdx.x / IMG_PARTS, seg = blockIdx.x % IMG_PARTS;
+    const int img = sg / IMG_PARTS, seg = sg % IMG_PARTS;
     const int len = (HW + IMG_PARTS - 1) / IMG_PARTS;
     const int lo = seg * len, hi = min(HW, lo + len);
-    const int cg = threadIdx.x & 3;
     double s = 0.0;
-    for (int i0 = lo; i0 < hi; i0 += 64) {  // 64 pixels per pass of the block
-        const int i = i0 + (threadIdx.x >> 2);
-        const bool on = i < hi;
-        const int pl = on ? i : hi - 1;     // idle lanes repeat a valid pixel
-        const int p = img * HW + pl;
-        const int x = p % W, t = p / W, yy = t % H, n = t / H;
-        float acc = 0.f;
+    for (int i0 = lo; i0 < hi; i0 += 32) {  // wave-uniform: whole waves run the MFMAs
+        bf16x8 bop[2][9];
+        int pix[2];
+        bool on[2];
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky)
+        for (int u = 0; u < 2; ++u) {
+            const int i = i0 + 16 * u + r16;
+            on[u] = i < hi;
+            pix[u] = img * HW + (on[u] ? i : hi - 1);
+            const int p = pix[u];
+            const int x = p % W, t = p / W, yy = t % H, n = t / H;
 #pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                const int q = (n * H + wrapi(yy + ky - 1, H)) * W + wrapi(x + kx - 1, W);
-                const bf16x8 v = *reinterpret_cast<const bf16x8 *>(a + size_t(q) * SC + cg * 8);
+            for (int ky = 0; ky < 3; ++ky) {
+                const int rowbase = (n * H + wrapi(yy + ky - 1, H)) * W;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) acc += ws[(cg * 8 + e) * 9 + ky * 3 + kx] * float(v[e]);
+                for (int kx = 0; kx < 3; ++kx) {
+                    const int q = rowbase + wrapi(x + kx - 1, W);
+                    bop[u][ky * 3 + kx] = *reinterpret_cast<const bf16x8 *>(a + size_t(q) * SC + g * 8);
+                }
             }
-        acc += __shfl_xor(acc, 1, 64);
-        acc += __shfl_xor(acc, 2, 64);
-        acc += b[0];
-        if (on && cg == 0) {
-            y[p] = acc;
-            s += double(acc);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc = mfma16(wop[t], bop[u][t], acc);
+            if (g == 0 && on[u]) {
+                const float v = (acc[0] + acc[1]) + acc[2] + bias;
+                y[pix[u]] = v;
+                s += double(v);
+            }
         }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+    if (lane == 0) part[sg] = s;
 }
 
 // Per-image sums of a field in FP64, in a fixed order: stage 1 sums each of
@@ -373,7 +417,7 @@ __global__ void __launch_bounds__(64) k_img_total(const double *__restrict__ par
     const double s = image_total(part, blockIdx.x);
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
-static_assert(IMG_PARTS % 64 == 0, "a wave sums the segment sums");
+static_assert(IMG_PARTS % 64 == 0, "a wave sums the segment sums (and k_last's blocks of four)");
 
 // prediction rho_t + out_scale (y - <y>_image); block (image, segment), the
 // image's mean from its IMG_PARTS segment sums (summed as k_img_total does)
@@ -635,6 +679,24 @@ __global__ void k_pack(const float *__restrict__ w, bf16 *__restrict__ wf, bf16 
     wb[((8 - t) * SC + ci) * SC + co] = v;
 }
 
+// The last layer's FP32 weights w[c][t] (C -> 1) as three BF16 parts for the
+// matrix cores, wl3[t][part][c]: hi = bf16(w), mid = bf16(w - hi), lo =
+// bf16(w - hi - mid).  Each difference is exact in FP32, and what lo leaves
+// is zero for normal FP32 weights, so hi + mid + lo = w.
+__global__ void k_pack_last(const float *__restrict__ w, bf16 *__restrict__ wl3) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= SC * 9) return;
+    const int t = k % 9, c = k / 9;
+    const float v = w[k];
+    const bf16 hi = bf16(v);
+    const float r1 = v - float(hi);
+    const bf16 mid = bf16(r1);
+    const bf16 lo = bf16(r1 - float(mid));
+    wl3[(t * 3 + 0) * SC + c] = hi;
+    wl3[(t * 3 + 1) * SC + c] = mid;
+    wl3[(t * 3 + 2) * SC + c] = lo;
+}
+
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
                        float *__restrict__ v, int n, float lr, float b1, float b2, float eps,
                        float bc1, float bc2) {
@@ -793,6 +855,7 @@ struct fsc_sur {
     std::vector<int64_t> woff, boff;  // offsets of each layer's weights / biases
     float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
     bf16 *wf = nullptr, *wb = nullptr;  // [mid layer][9][32][32]
+    bf16 *wl3 = nullptr;                // last layer, [9][3][32] (k_pack_last)
     std::vector<float *> z;            // [layers - 1] of P x 32
     std::vector<bf16 *> a;             // [layers - 1] of P x 32
     bf16 *dzA = nullptr, *dzB = nullptr;
@@ -830,7 +893,7 @@ int nmid(const fsc_sur *s) { return s->layers - 2; }
 void sur_free(fsc_sur *s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
-    void *ptrs[] = {s->params, s->grads, s->m,    s->v,    s->wf,   s->wb, s->dzA,
+    void *ptrs[] = {s->params, s->grads, s->m,    s->v,    s->wf,   s->wb, s->wl3, s->dzA,
                     s->dzB,    s->y,     s->gbuf, s->ysum, s->gsum, s->loss, s->X, s->part};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -856,6 +919,9 @@ int pack_weights(fsc_sur *s) {
                            s->params + s->woff[l], s->wf + off, s->wb + off);
         SCHK(s, hipGetLastError());
     }
+    hipLaunchKernelGGL(k_pack_last, dim3((SC * 9 + 255) / 256), dim3(256), 0, s->stream,
+                       s->params + s->woff[s->layers - 1], s->wl3);
+    SCHK(s, hipGetLastError());
     return FSC_OK;
 }
 
@@ -881,7 +947,6 @@ int img_sums(fsc_sur *s, const float *v, int B, double *out) {
 int sur_forward_core(fsc_sur *s, const float *prev, const float *cur, int B, bool train) {
     const int P = B * s->H * s->W;
     const unsigned nb = unsigned((P + 255) / 256);
-    const unsigned nb4 = unsigned((4 * int64_t(P) + 255) / 256);  // k_first: four lanes per pixel
     const float ii = 1.f / s->in_scale, io = 1.f / s->out_scale;
     const float *w0 = s->params + s->woff[0], *b0 = s->params + s->boff[0];
     if (train) {
@@ -889,17 +954,17 @@ int sur_forward_core(fsc_sur *s, const float *prev, const float *cur, int B, boo
                            ii, io, s->X);
         SCHK(s, hipGetLastError());
         if (s->in_ch == 2)
-            hipLaunchKernelGGL((k_first<2, true, false>), dim3(nb4), dim3(256), 0, s->stream, s->X, cur,
+            hipLaunchKernelGGL((k_first<2, true, false>), dim3(nb), dim3(256), 0, s->stream, s->X, cur,
                                prev, s->mean, ii, io, B, s->H, s->W, w0, b0, s->z[0], s->a[0]);
         else
-            hipLaunchKernelGGL((k_first<1, true, false>), dim3(nb4), dim3(256), 0, s->stream, s->X, cur,
+            hipLaunchKernelGGL((k_first<1, true, false>), dim3(nb), dim3(256), 0, s->stream, s->X, cur,
                                prev, s->mean, ii, io, B, s->H, s->W, w0, b0, s->z[0], s->a[0]);
     } else {
         if (s->in_ch == 2)
-            hipLaunchKernelGGL((k_first<2, false, true>), dim3(nb4), dim3(256), 0, s->stream, s->X, cur,
+            hipLaunchKernelGGL((k_first<2, false, true>), dim3(nb), dim3(256), 0, s->stream, s->X, cur,
                                prev, s->mean, ii, io, B, s->H, s->W, w0, b0, s->z[0], s->a[0]);
         else
-            hipLaunchKernelGGL((k_first<1, false, true>), dim3(nb4), dim3(256), 0, s->stream, s->X, cur,
+            hipLaunchKernelGGL((k_first<1, false, true>), dim3(nb), dim3(256), 0, s->stream, s->X, cur,
                                prev, s->mean, ii, io, B, s->H, s->W, w0, b0, s->z[0], s->a[0]);
     }
     SCHK(s, hipGetLastError());
@@ -927,8 +992,8 @@ int sur_forward_core(fsc_sur *s, const float *prev, const float *cur, int B, boo
         SCHK(s, hipGetLastError());
     }
     const int last = s->layers - 1;
-    hipLaunchKernelGGL(k_last, dim3(unsigned(B * IMG_PARTS)), dim3(256), 0, s->stream, s->a[last - 1], B,
-                       s->H, s->W, s->params + s->woff[last], s->params + s->boff[last], s->y, s->part);
+    hipLaunchKernelGGL(k_last, dim3(unsigned(B * IMG_PARTS / 4)), dim3(256), 0, s->stream, s->a[last - 1], B,
+                       s->H, s->W, s->wl3, s->params + s->boff[last], s->y, s->part);
     SCHK(s, hipGetLastError());
     if (train) {  // the loss needs the per-image sums of y
         hipLaunchKernelGGL(k_img_total, dim3(unsigned(B)), dim3(64), 0, s->stream, s->part, s->ysum);
@@ -1046,6 +1111,7 @@ int fsc_sur_create(int layers, int in_ch, int H, int W, int max_batch, uint64_t 
               hipMalloc(&s->v, sizeof(float) * o) == hipSuccess &&
               hipMalloc(&s->wf, sizeof(bf16) * 9 * SC * SC * std::max(1, layers - 2)) == hipSuccess &&
               hipMalloc(&s->wb, sizeof(bf16) * 9 * SC * SC * std::max(1, layers - 2)) == hipSuccess &&
+              hipMalloc(&s->wl3, sizeof(bf16) * 9 * 3 * SC) == hipSuccess &&
               hipMalloc(&s->dzA, sizeof(bf16) * P * SC) == hipSuccess &&
               hipMalloc(&s->dzB, sizeof(bf16) * P * SC) == hipSuccess &&
               hipMalloc(&s->y, sizeof(float) * P) == hipSuccess &&
