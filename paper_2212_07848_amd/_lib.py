@@ -83,6 +83,14 @@ def lib():
         return _lib
     if not os.path.exists(LIBPATH):
         raise ImportError(f"{LIBPATH} is not built; run __graft_entry__.build() first")
+    # PyTorch ships its own HIP runtime (same soname, another file name).  With
+    # torch loaded first, this library binds to that runtime; loaded first, it
+    # would bring in the system one, and torch would start a second runtime in
+    # the same process that finds no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIBPATH)
     vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
     fp = C.POINTER(C.c_float)

