@@ -350,6 +350,17 @@ int fsc_sur_train_step(fsc_sur *s, const float *dev_prev, const float *dev_in,
  * fsc_sur_forward. */
 int fsc_sur_rollout(fsc_sur *s, const float *dev_prev, float *dev_traj, int batch, int passes);
 
+/* Inference (forward passes and rollouts) can run pairs of consecutive
+ * 32 -> 32 layers as one launch that keeps the first layer's activations in
+ * LDS (needs H % 4 == 0 and W % 64 == 0, else one launch per layer).  The
+ * results are bit for bit those of one launch per layer.  mode 0: never;
+ * 1: always; 2 (the default): when batch * H * W <= 8 * 128 * 128, where it
+ * measured faster (its LDS halves the blocks per CU, which costs more than
+ * it saves on larger batches).  Other modes: FSC_E_INVAL.  Changing the mode,
+ * or the normalisation (fsc_sur_set_norm), drops the captured rollout
+ * graphs (waiting for a replay still running). */
+int fsc_sur_set_fusion(fsc_sur *s, int mode);
+
 /* Training batch from a device snapshot stack S [K][R][H][W] (float; H, W
  * the surrogate's): image b (b < batch <= min(64, max_batch)) is
  *   out[b][y][x] = S[t[b] + dt][r[b]][(Y - sy) mod H][(X - sx) mod W],

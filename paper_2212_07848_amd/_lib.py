@@ -43,7 +43,7 @@ EXPORTS = [
     "fsc_linear_corr",
     "fsc_sur_create", "fsc_sur_destroy", "fsc_sur_last_error", "fsc_sur_nparams",
     "fsc_sur_set_params", "fsc_sur_get_params", "fsc_sur_set_norm", "fsc_sur_forward",
-    "fsc_sur_grad", "fsc_sur_train_step", "fsc_sur_rollout", "fsc_sur_gather",
+    "fsc_sur_grad", "fsc_sur_train_step", "fsc_sur_rollout", "fsc_sur_set_fusion", "fsc_sur_gather",
     "fsc_stack_scales", "fsc_coarsen", "fsc_ens_coarsen", "fsc_field_nbins",
     "fsc_field_sk", "fsc_field_sk_noalloc", "fsc_mfma_probe",
 ]
@@ -168,6 +168,7 @@ def lib():
         "fsc_sur_grad": ([vp, vp, vp, vp, C.c_int, fp, dp], C.c_int),
         "fsc_sur_train_step": ([vp, vp, vp, vp, C.c_int, C.c_float, dp], C.c_int),
         "fsc_sur_rollout": ([vp, vp, vp, C.c_int, C.c_int], C.c_int),
+        "fsc_sur_set_fusion": ([vp, C.c_int], C.c_int),
         "fsc_sur_gather": ([vp, vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                             C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp], C.c_int),
         "fsc_stack_scales": ([vp, C.c_int, C.c_int64, C.c_int, C.c_double, dp, dp, vp], C.c_int),
@@ -574,6 +575,12 @@ class Surrogate:
 
     def set_norm(self, mean: float, in_scale: float, out_scale: float):
         self._c(lib().fsc_sur_set_norm(self._h, mean, in_scale, out_scale))
+
+    def set_fusion(self, mode: int):
+        """Pairs of 32 -> 32 layers in one launch at inference: 0 never, 1
+        always, 2 small batches (the default); bit-identical either way (see
+        fsc_sur_set_fusion)."""
+        self._c(lib().fsc_sur_set_fusion(self._h, int(mode)))
 
     def forward(self, prev, x, out, batch: int):
         self._c(lib().fsc_sur_forward(self._h, self._ptr(prev), self._ptr(x), self._ptr(out),

@@ -312,6 +312,109 @@ __global__ void __launch_bounds__(256) k_mid_lds(const bf16 *__restrict__ ain,
     }
 }
 
+// Two consecutive C -> C layers A and B of the forward pass (inference) in
+// one launch.  A block stages the 8 x 68-pixel input window of its 4 x 64
+// output tile, computes layer A on the 6 x 66-pixel window that layer B reads
+// (the tile and a one-pixel ring: 24 row tiles of 16 pixels and one tile of
+// the 12 ring pixels in the left and right columns) into LDS, then layer B on
+// the tile, stored to memory.  Every activation is the same MFMA sequence on
+// the same operands as in two k_mid_lds launches, so the results are bit for
+// bit those of the unfused layers, without the round trip of layer A's
+// activations through memory and one launch less.  Needs H % 4 == 0 and
+// W % 64 == 0; without training (layer A's pre-activations are not kept).
+constexpr int F2R = 4, F2W = 64;
+constexpr int F2IR = F2R + 4, F2IW = F2W + 4;  // input window
+constexpr int F2MR = F2R + 2, F2MW = F2W + 2;  // layer A window
+__global__ void __launch_bounds__(256) k_mid2_lds(const bf16 *__restrict__ ain,
+                                                  const bf16 *__restrict__ wA,
+                                                  const float *__restrict__ bA,
+                                                  const bf16 *__restrict__ wB,
+                                                  const float *__restrict__ bB, int B, int H, int W,
+                                                  bf16 *__restrict__ aout) {
+    __shared__ __attribute__((aligned(16))) bf16 win[F2IR * F2IW * SC];
+    __shared__ __attribute__((aligned(16))) bf16 mid[F2MR * F2MW * SC];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int txs = W / F2W, tys = H / F2R;
+    const int bx = blockIdx.x % txs, t1 = blockIdx.x / txs;
+    const int by = t1 % tys, n = t1 / tys;
+    const int x0 = bx * F2W, y0 = by * F2R;
+    // input window: pixel (r, c) is image pixel (y0 - 2 + r, x0 - 2 + c), periodic
+    for (int k = threadIdx.x; k < F2IR * F2IW * 4; k += 256) {
+        const int piece = k & 3, pc = k >> 2;
+        const int r = pc / F2IW, c = pc % F2IW;
+        const int yy = ((y0 - 2 + r) % H + H) % H, xx = ((x0 - 2 + c) % W + W) % W;
+        const size_t q = size_t((n * H + yy) * W + xx);
+        *reinterpret_cast<bf16x8 *>(win + pc * SC + piece * 8) =
+            *reinterpret_cast<const bf16x8 *>(ain + q * SC + piece * 8);
+    }
+    bf16x8 bop[9][2];
+    f32x4 bv[2];
+    auto load_layer = [&](const bf16 *__restrict__ wpk, const float *__restrict__ bias) {
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+                bop[t][nt] = *reinterpret_cast<const bf16x8 *>(
+                    wpk + (t * SC + mid_row_channel(nt, r16)) * SC + g * 8);
+        bv[0] = *reinterpret_cast<const f32x4 *>(bias + 8 * g);
+        bv[1] = *reinterpret_cast<const f32x4 *>(bias + 8 * g + 4);
+    };
+    // acc = bias + sum over taps of W_tap x (32 channels of the tap pixel);
+    // `src` is the window and (r, c) the window position of tap (0, 0)
+    auto tile = [&](const bf16 *src, int sw, int r, int c, f32x4 (&acc)[2]) {
+        acc[0] = bv[0];
+        acc[1] = bv[1];
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const bf16x8 aop =
+                    *reinterpret_cast<const bf16x8 *>(src + ((r + ky) * sw + c + kx) * SC + g * 8);
+                acc[0] = mfma16(bop[ky * 3 + kx][0], aop, acc[0]);
+                acc[1] = mfma16(bop[ky * 3 + kx][1], aop, acc[1]);
+            }
+    };
+    load_layer(wA, bA);
+    __syncthreads();
+    // layer A: window pixel (mr, mc) is image pixel (y0 - 1 + mr, x0 - 1 + mc);
+    // its tap (0, 0) is input window pixel (mr, mc)
+    for (int t = wave; t < F2MR * (F2W / 16) + 1; t += 4) {  // wave-uniform
+        int mr, mc;
+        bool keep = true;
+        if (t < F2MR * (F2W / 16)) {
+            mr = t / (F2W / 16);
+            mc = 1 + 16 * (t % (F2W / 16)) + r16;
+        } else {  // the ring columns 0 and F2MW - 1 of the F2MR rows; 4 lanes spare
+            keep = r16 < 2 * F2MR;
+            const int e = keep ? r16 : 0;
+            mr = e >> 1;
+            mc = (e & 1) ? F2MW - 1 : 0;
+        }
+        f32x4 acc[2];
+        tile(win, F2IW, mr, mc, acc);
+        bf16x8 out;
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[4 * nt + r] = bf16(silu(acc[nt][r]));
+        if (keep) *reinterpret_cast<bf16x8 *>(mid + (mr * F2MW + mc) * SC + 8 * g) = out;
+    }
+    __syncthreads();
+    load_layer(wB, bB);
+    // layer B: output pixel (y0 + row, x0 + cx), its tap (0, 0) is layer-A
+    // window pixel (row, cx)
+#pragma unroll
+    for (int j = 0; j < F2R * F2W / 64; ++j) {
+        const int k = wave * (F2R * F2W / 64) + j;
+        const int row = k / (F2W / 16), cx = 16 * (k % (F2W / 16)) + r16;
+        f32x4 acc[2];
+        tile(mid, F2MW, row, cx, acc);
+        const size_t p = size_t((n * H + y0 + row) * W + x0 + cx);
+        mid_epilogue<false, false>(acc, p, g, nullptr, aout, nullptr);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Last layer (C -> 1) forward on the matrix cores.  Its FP32 weights enter as
 // three BF16 parts each, w = hi + mid + lo (k_pack_last; exact for normal FP32
@@ -870,6 +973,7 @@ struct fsc_sur {
     hipStream_t cap_stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::map<std::tuple<const float *, float *, int, int>, hipGraphExec_t> rollouts;
+    int fuse = 2;  // pairs of C -> C layers as one k_mid2_lds: 0 never, 1 always, 2 small batches
     std::string err;
 };
 
@@ -912,6 +1016,26 @@ void sur_free(fsc_sur *s) {
     if (s->ev_out) (void)hipEventDestroy(s->ev_out);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
+}
+
+// Fused pairs of C -> C layers (k_mid2_lds) hold 60 KB of LDS per block, so
+// 2 blocks per CU instead of 4: measured on 9-layer passes over 128^2 images,
+// they win up to 8 images (62.5 against 73.3 us for one, 87.0 against 100.3
+// for eight) and lose from 16 (135.9 against 128.3).  Mode 2 fuses up to
+// FUSE_MAX_PIXELS pixels per batch.
+constexpr int64_t FUSE_MAX_PIXELS = 8 * 128 * 128;
+bool fuse_pairs(const fsc_sur *s, int B) {
+    return s->fuse == 1 || (s->fuse == 2 && int64_t(B) * s->H * s->W <= FUSE_MAX_PIXELS);
+}
+
+// Destroys the captured rollout graphs (after any replay still running), so
+// that the next rollout captures the current settings.
+int drop_rollouts(fsc_sur *s) {
+    if (s->rollouts.empty()) return FSC_OK;
+    if (s->cap_stream) SCHK(s, hipStreamSynchronize(s->cap_stream));
+    for (auto &kv : s->rollouts) (void)hipGraphExecDestroy(kv.second);
+    s->rollouts.clear();
+    return FSC_OK;
 }
 
 int pack_weights(fsc_sur *s) {
@@ -976,6 +1100,16 @@ int sur_forward_core(fsc_sur *s, const float *prev, const float *cur, int B, boo
         const size_t off = size_t(l - 1) * 9 * SC * SC;
         const bf16 *ain = s->a[l - 1], *wl = s->wf + off;
         const float *bl = s->params + s->boff[l];
+        if (!train && fuse_pairs(s, B) && l + 1 <= nmid(s) && s->H % F2R == 0 && s->W % F2W == 0) {
+            // layers l and l + 1 in one launch; a[l] is not written
+            const dim3 g(unsigned(B * (s->H / F2R) * (s->W / F2W)));
+            hipLaunchKernelGGL(k_mid2_lds, g, dim3(256), 0, s->stream, ain, wl, bl,
+                               s->wf + off + size_t(9) * SC * SC, s->params + s->boff[l + 1], B,
+                               s->H, s->W, s->a[l + 1]);
+            SCHK(s, hipGetLastError());
+            ++l;
+            continue;
+        }
         if (lds_tiles(s)) {
             const dim3 g(unsigned(B * (s->H / MR) * (s->W / MW)));
             if (train)
@@ -1182,9 +1316,24 @@ int fsc_sur_get_params(fsc_sur *s, float *host, int64_t n) {
 
 int fsc_sur_set_norm(fsc_sur *s, float mean, float in_scale, float out_scale) {
     if (!s || !(in_scale > 0.f) || !(out_scale > 0.f)) return FSC_E_INVAL;
+    if (mean != s->mean || in_scale != s->in_scale || out_scale != s->out_scale) {
+        // the captured rollouts hold the old values as kernel arguments
+        int rc = drop_rollouts(s);
+        if (rc) return rc;
+    }
     s->mean = mean;
     s->in_scale = in_scale;
     s->out_scale = out_scale;
+    return FSC_OK;
+}
+
+int fsc_sur_set_fusion(fsc_sur *s, int mode) {
+    if (!s || mode < 0 || mode > 2) return FSC_E_INVAL;
+    if (mode != s->fuse) {
+        int rc = drop_rollouts(s);  // captured with another kernel sequence
+        if (rc) return rc;
+    }
+    s->fuse = mode;
     return FSC_OK;
 }
 

@@ -213,6 +213,52 @@ def test_rollout_graph_equals_repeated_forward_passes():
     sur.close()
 
 
+@pytest.mark.parametrize("layers,in_ch,shape", [(9, 2, (2, 32, 64)), (5, 1, (1, 8, 128)),
+                                                (4, 2, (2, 16, 128)), (3, 1, (2, 16, 64)),
+                                                (5, 2, (2, 32, 32))])
+def test_fused_layer_pairs_equal_unfused_layers(layers, in_ch, shape):
+    # inference can run pairs of 32 -> 32 layers as one launch with the first
+    # layer's activations in LDS (9 layers: three pairs and one single layer;
+    # 4 layers: one pair; 3 layers: a single layer; W = 32: no fusion): the
+    # forward pass and a rollout are bit-identical in every mode (these
+    # batches are small enough for mode 2 to fuse).  Switching drops the
+    # captured rollout graph, and so does a new normalisation, whose values
+    # the graph holds as kernel arguments.
+    B, H, W = shape
+    rng = np.random.default_rng(21)
+    p = _net(6, L=layers, in_ch=in_ch).astype(np.float32)
+    rho = (1.0 + 0.3 * rng.normal(size=shape)).astype(np.float32)
+    prev = _dev((rho + 0.05 * rng.normal(size=shape)).astype(np.float32)) if in_ch == 2 else None
+    sur = fsc.Surrogate(layers, H, W, B, seed=0, in_ch=in_ch)
+    sur.set_params(p)
+    out = {}
+    for norm in ((1.0, 0.3, 0.05), (0.9, 0.25, 0.04)):
+        sur.set_norm(*norm)
+        for fuse in (1, 0, 2):
+            sur.set_fusion(fuse)
+            y = torch.zeros((B, H, W), dtype=torch.float32, device="cuda")
+            sur.forward(prev, _dev(rho), y, B)
+            traj = torch.zeros((4, B, H, W), dtype=torch.float32, device="cuda")
+            traj[0].copy_(_dev(rho))
+            sur.rollout(prev, traj, B, 3)
+            torch.cuda.synchronize()
+            assert torch.equal(traj[1], y)
+            out.setdefault(norm, []).append(traj.clone())
+    sur.close()
+    for norm, runs in out.items():
+        for t in runs[1:]:
+            assert torch.equal(t, runs[0]), norm
+    # the second normalisation gives another trajectory (no stale graph)
+    a, b = out.values()
+    assert not torch.equal(a[0], b[0])
+    with pytest.raises(fsc.FscError):
+        sur2 = fsc.Surrogate(3, H, W, B, seed=0, in_ch=in_ch)
+        try:
+            sur2.set_fusion(3)
+        finally:
+            sur2.close()
+
+
 def test_gather_is_the_shifted_and_transposed_snapshot():
     rng = np.random.default_rng(13)
     K, R, m, batch = 7, 5, 64, 9
