@@ -156,14 +156,14 @@ __global__ void __launch_bounds__(TX + 64)
         while (v >= ns) v -= ns;
         return v;
     };
-    auto load_row = [&](int row, real (&out)[Q]) {
-        const int pc = wrap_row(row);
+    auto load_wrapped = [&](int pc, real (&out)[Q]) {  // lattice row pc in [0, ns)
         const int pp = pc + 1 == ns ? 0 : pc + 1, pm = pc == 0 ? ns - 1 : pc - 1;
         const uint32_t pb[3] = {uint32_t(pp) * pbytes, uint32_t(pc) * pbytes, uint32_t(pm) * pbytes};
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             out[i] = bload<real>(src, xo[L::c(i, 0) + 1], uint32_t(i) * pop_bytes + pb[L::c(i, 1) + 1]);
     };
+    auto load_row = [&](int row, real (&out)[Q]) { load_wrapped(wrap_row(row), out); };
     auto dpsi_of = [&](const real (&fv)[Q]) {
         real dn = real(0);
 #pragma unroll
@@ -180,12 +180,14 @@ __global__ void __launch_bounds__(TX + 64)
     auto lrow = [&](int k) { return first + dir * (k - R - 1); };  // lattice row of l_k
     const int H1 = H + 2 * R + 2;                          // level-1 rows
 
-    auto put_a = [&](int k, real v) {  // psi(t) of l_k
-        const int sl = (k + SA) % SA;
+    // ring slot t of a ring of n rows, for t within one ring length of [0, n)
+    auto wrapc = [](int t, int n) { return t < 0 ? t + n : (t >= n ? t - n : t); };
+    auto put_slot = [&](int sl, real v) {  // psi(t) of the row in slot sl of A
         if (wa) A[sl][x1 + OA] = v;
         if (ia_lo >= 0) A[sl][ia_lo] = v;
         if (ia_hi >= 0) A[sl][ia_hi] = v;
     };
+    auto put_a = [&](int k, real v) { put_slot((k + SA) % SA, v); };  // psi(t) of l_k
 
     // ---- prologue: psi(t) of l_{-R} .. l_{R-1}; pulled rows l_0 .. l_{R-1} ----
     real F[NR][Q];
@@ -212,35 +214,37 @@ __global__ void __launch_bounds__(TX + 64)
 
     // ---- the three pieces of an iteration ---------------------------------------
     // level 2: pull f(t+1) of l_k from B into the register ring, psi(t+1) -> C
-    auto psi_stage = [&](int k, int gs) {
-        const int sb[3] = {(k + dir) % SB, k % SB, (k - dir + SB) % SB};  // c_y + 1 -> row - c_y
+    // (kb, kc: the slots of l_k in B and C)
+    auto psi_stage = [&](int kb, int kc, int gs) {
+        const int sb[3] = {wrapc(kb + dir, SB), kb, wrapc(kb - dir, SB)};  // c_y + 1 -> row - c_y
         real(&g2)[Q] = G2[gs];
 #pragma unroll
         for (int i = 0; i < Q; ++i) g2[i] = B[sb[L::c(i, 1) + 1]][i][x2 - L::c(i, 0) + OB];
         const real v = dpsi_of(g2);
-        const int sl = k % SC;
+        const int sl = kc;
         if (wc) Cs[sl][x2 + OC] = v;
         if (ic_lo >= 0) Cs[sl][ic_lo] = v;
         if (ic_hi >= 0) Cs[sl][ic_hi] = v;
     };
     // level 1: force and collision of l_j (pulled populations in F[fs]) -> B
-    auto level1 = [&](int j, int fs, const real (&z)[NN]) {
+    // (ja, jb: the slots of l_j in A and B)
+    auto level1 = [&](int ja, int jb, int fs, const real (&z)[NN]) {
         real g[3] = {real(0), real(0), real(0)};
 #pragma unroll
         for (int a = 0; a < ST::NH; ++a) {
             const int ex = ST::e(a, 0), es = dir * ST::e(a, 1);
-            const real diff = A[(j + es + SA) % SA][x1 + ex + OA] - A[(j - es + SA) % SA][x1 - ex + OA];
+            const real diff = A[wrapc(ja + es, SA)][x1 + ex + OA] - A[wrapc(ja - es, SA)][x1 - ex + OA];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int eq = ST::e(a, q);
                 if (eq != 0) g[q] += real(ST::w(a) * eq) * diff;
             }
         }
-        const real pre = G * (psi0 + A[(j + SA) % SA][x1 + OA]);
+        const real pre = G * (psi0 + A[ja][x1 + OA]);
         const real Fv[3] = {pre * g[0], pre * g[1], pre * g[2]};
         real(&fv)[Q] = F[fs];
         collide_d2q9<real, NOISE>(fv, rho0, Fv, lc, ac, z);
-        const int sl = j % SB;
+        const int sl = jb;
         if (wb) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) B[sl][i][x1 + OB] = fv[i];
@@ -255,23 +259,24 @@ __global__ void __launch_bounds__(TX + 64)
         }
     };
     // level 2: force and collision of l_k (pulled populations in G2[gs]) -> HBM
-    auto level2 = [&](int k, int gs, const real (&z)[NN]) {
+    // (kc: the slot of l_k in C; krow: its lattice row)
+    auto level2 = [&](int kc, int gs, int krow, const real (&z)[NN]) {
         real g[3] = {real(0), real(0), real(0)};
 #pragma unroll
         for (int a = 0; a < ST::NH; ++a) {
             const int ex = ST::e(a, 0), es = dir * ST::e(a, 1);
-            const real diff = Cs[(k + es + SC) % SC][x2 + ex + OC] - Cs[(k - es + SC) % SC][x2 - ex + OC];
+            const real diff = Cs[wrapc(kc + es, SC)][x2 + ex + OC] - Cs[wrapc(kc - es, SC)][x2 - ex + OC];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int eq = ST::e(a, q);
                 if (eq != 0) g[q] += real(ST::w(a) * eq) * diff;
             }
         }
-        const real pre = G * (psi0 + Cs[k % SC][x2 + OC]);
+        const real pre = G * (psi0 + Cs[kc][x2 + OC]);
         const real Fv[3] = {pre * g[0], pre * g[1], pre * g[2]};
         real(&fv)[Q] = G2[gs];
         collide_d2q9<real, NOISE>(fv, rho0, Fv, lc, ac, z);
-        const uint32_t so = uint32_t(wrap_row(lrow(k))) * pbytes + lane_store;
+        const uint32_t so = uint32_t(krow) * pbytes + lane_store;
 #pragma unroll
         for (int i = 0; i < Q; ++i) bstore(dst, so, uint32_t(i) * pop_bytes, fv[i]);
     };
@@ -287,6 +292,17 @@ __global__ void __launch_bounds__(TX + 64)
     constexpr int LAG = BARS == 1 ? 3 : 1;
     constexpr int LAG2 = BARS == 1 ? R : R + 1;
     const int J = H + R + LAG + LAG2 + 1;  // iterations: the last one collides km = H + R
+    // wrapped lattice rows of l_{j+R} (loads), l_j (level 1) and l_km (level
+    // 2), advanced by one row per iteration instead of wrapped anew
+    auto next_row = [&](int r) {
+        r += dir;
+        return r >= ns ? r - ns : (r < 0 ? r + ns : r);
+    };
+    int row_ld = wrap_row(lrow(R)), row_1 = wrap_row(lrow(0)), row_2 = wrap_row(lrow(-LAG - LAG2));
+    // ring slots, advanced likewise: l_j in A and B, l_kp in B and C, l_km in C
+    auto slot0 = [](int k, int n) { return (k % n + n) % n; };
+    int sa_j = 0, sb_j = 0, sb_p = slot0(-LAG, SB), sc_p = slot0(-LAG, SC),
+        sc_m = slot0(-LAG - LAG2, SC);
     for (int j0 = 0; j0 < J; j0 += NR) {
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
@@ -304,15 +320,14 @@ __global__ void __launch_bounds__(TX + 64)
 
             // loads of level-1 row l_{j+R} (consumed by its psi below and by
             // its collision R iterations later)
-            if (lev1 && !idle) load_row(lrow(j + R), F[fs_new]);
+            if (lev1 && !idle) load_wrapped(row_ld, F[fs_new]);
             // noise of both levels (independent of memory and LDS)
             real z1[NN], z2[NN];
             if constexpr (NOISE) {
-                if (lev1 && !idle) node_normals<L, real>(uint32_t(gx1 + nx * wrap_row(lrow(j))), step1,
-                                                         d.seed_hi, d.key0, d.key1, z1);
+                if (lev1 && !idle) node_normals<L, real>(uint32_t(gx1 + nx * row_1), step1, d.seed_hi,
+                                                         d.key0, d.key1, z1);
                 if (lev2 && st2)
-                    node_normals<L, real>(uint32_t(gx2 + nx * wrap_row(lrow(km))), step2, d.seed_hi,
-                                          d.key0, d.key1, z2);
+                    node_normals<L, real>(uint32_t(gx2 + nx * row_2), step2, d.seed_hi, d.key0, d.key1, z2);
             }
             if constexpr (!NOISE) {
 #pragma unroll
@@ -320,21 +335,29 @@ __global__ void __launch_bounds__(TX + 64)
             }
             if constexpr (BARS == 1) {
                 // B rows kp - 1 .. kp + 1 were written at least two iterations ago
-                if (psi2 && p2) psi_stage(kp, gs_new);
-                if (lev1) put_a(j + R, idle ? real(0) : dpsi_of(F[fs_new]));
+                if (psi2 && p2) psi_stage(sb_p, sc_p, gs_new);
+                if (lev1) put_slot(wrapc(sa_j + R, SA), idle ? real(0) : dpsi_of(F[fs_new]));
                 __syncthreads();
-                if (lev1 && c1) level1(j, u, z1);
-                if (lev2 && st2) level2(km, gs_use, z2);
+                if (lev1 && c1) level1(sa_j, sb_j, u, z1);
+                if (lev2 && st2) level2(sc_m, gs_use, row_2, z2);
             } else {
-                if (lev1) put_a(j + R, idle ? real(0) : dpsi_of(F[fs_new]));
+                if (lev1) put_slot(wrapc(sa_j + R, SA), idle ? real(0) : dpsi_of(F[fs_new]));
                 __syncthreads();
-                if (lev1 && c1) level1(j, u, z1);
+                if (lev1 && c1) level1(sa_j, sb_j, u, z1);
                 __syncthreads();
                 // the collision frees the ring slot that the pull then refills
                 // (gs_use == gs_new, as kp - km = R + 1)
-                if (lev2 && st2) level2(km, gs_use, z2);
-                if (psi2 && p2) psi_stage(kp, gs_new);
+                if (lev2 && st2) level2(sc_m, gs_use, row_2, z2);
+                if (psi2 && p2) psi_stage(sb_p, sc_p, gs_new);
             }
+            row_ld = next_row(row_ld);
+            row_1 = next_row(row_1);
+            row_2 = next_row(row_2);
+            sa_j = sa_j + 1 == SA ? 0 : sa_j + 1;
+            sb_j = sb_j + 1 == SB ? 0 : sb_j + 1;
+            sb_p = sb_p + 1 == SB ? 0 : sb_p + 1;
+            sc_p = sc_p + 1 == SC ? 0 : sc_p + 1;
+            sc_m = sc_m + 1 == SC ? 0 : sc_m + 1;
         }
     }
 }
