@@ -347,7 +347,8 @@ int fsc_sur_train_step(fsc_sur *s, const float *dev_prev, const float *dev_in,
  * passes) into a hipGraph and replayed, so the launches of a rollout run
  * back to back; the replay is ordered after earlier and before later work
  * on the surrogate's stream.  Results equal `passes` calls of
- * fsc_sur_forward. */
+ * fsc_sur_forward.  At most 8 captures are kept per surrogate: a ninth
+ * drops the oldest (after waiting for a replay of it still running). */
 int fsc_sur_rollout(fsc_sur *s, const float *dev_prev, float *dev_traj, int batch, int passes);
 
 /* Inference (forward passes and rollouts) can run pairs of consecutive

@@ -21,6 +21,7 @@
 // Activations are NHWC: pixel p = (n H + y) W + x, channel fastest.
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <string>
 #include <tuple>
@@ -973,6 +974,7 @@ struct fsc_sur {
     hipStream_t cap_stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::map<std::tuple<const float *, float *, int, int>, hipGraphExec_t> rollouts;
+    std::deque<std::tuple<const float *, float *, int, int>> rollout_order;  // oldest first
     int fuse = 2;  // pairs of C -> C layers as one k_mid2_lds: 0 never, 1 always, 2 small batches
     std::string err;
 };
@@ -1035,8 +1037,14 @@ int drop_rollouts(fsc_sur *s) {
     if (s->cap_stream) SCHK(s, hipStreamSynchronize(s->cap_stream));
     for (auto &kv : s->rollouts) (void)hipGraphExecDestroy(kv.second);
     s->rollouts.clear();
+    s->rollout_order.clear();
     return FSC_OK;
 }
+
+// Captured rollouts kept per surrogate; beyond that the oldest capture is
+// dropped (a caller that hands over fresh buffers every time would otherwise
+// grow the cache without bound).
+constexpr size_t ROLLOUT_CACHE_MAX = 8;
 
 int pack_weights(fsc_sur *s) {
     for (int l = 1; l <= nmid(s); ++l) {
@@ -1450,7 +1458,15 @@ int fsc_sur_rollout(fsc_sur *s, const float *dev_prev, float *dev_traj, int batc
         (void)hipGraphDestroy(graph);
         if (ec != hipSuccess)
             return sur_fail(s, FSC_E_HIP, std::string("rollout instantiate: ") + hipGetErrorString(ec));
+        if (s->rollouts.size() >= ROLLOUT_CACHE_MAX) {
+            SCHK(s, hipStreamSynchronize(s->cap_stream));  // no replay of it still running
+            auto old = s->rollouts.find(s->rollout_order.front());
+            (void)hipGraphExecDestroy(old->second);
+            s->rollouts.erase(old);
+            s->rollout_order.pop_front();
+        }
         it = s->rollouts.emplace(key, exec).first;
+        s->rollout_order.push_back(key);
     }
     // ordered after the caller's stream and before its later work
     SCHK(s, hipEventRecord(s->ev_in, s->stream));

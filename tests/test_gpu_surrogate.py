@@ -259,6 +259,29 @@ def test_fused_layer_pairs_equal_unfused_layers(layers, in_ch, shape):
             sur2.close()
 
 
+def test_rollout_cache_drops_the_oldest_capture():
+    # fresh trajectory buffers for every rollout: each is captured anew, at
+    # most 8 are kept (the oldest dropped), and every replay, including one
+    # of a buffer whose capture was dropped, equals the pass-by-pass forward
+    rng = np.random.default_rng(14)
+    B, H, W, layers, passes = 2, 16, 64, 3, 2
+    sur = fsc.Surrogate(layers, H, W, B, seed=0, in_ch=1)
+    sur.set_params(_net(9, L=layers, in_ch=1).astype(np.float32))
+    sur.set_norm(1.0, 0.3, 0.05)
+    rho = _dev((1.0 + 0.3 * rng.normal(size=(B, H, W))).astype(np.float32))
+    ref = torch.zeros((passes + 1, B, H, W), dtype=torch.float32, device="cuda")
+    ref[0].copy_(rho)
+    for k in range(passes):
+        sur.forward(None, ref[k], ref[k + 1], B)
+    trajs = [torch.zeros_like(ref) for _ in range(11)]
+    for t in trajs + trajs[:2]:
+        t[0].copy_(rho)
+        sur.rollout(None, t, B, passes)
+        torch.cuda.synchronize()
+        assert torch.equal(t, ref)
+    sur.close()
+
+
 def test_gather_is_the_shifted_and_transposed_snapshot():
     rng = np.random.default_rng(13)
     K, R, m, batch = 7, 5, 64, 9
