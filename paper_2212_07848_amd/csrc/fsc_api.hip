@@ -636,6 +636,7 @@ std::string tune_key(const fsc_ens *e) {
 }
 
 int ens_autotune(fsc_ens *e) {
+    TraceRange trace_("fsc autotune");
     const std::string key = tune_key(e);
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
@@ -725,6 +726,7 @@ int ens_autotune(fsc_ens *e) {
 }
 
 int ens_run(fsc_ens *e, int64_t nsteps, int64_t sk_every) {
+    TraceRange trace_("fsc run");
     if (nsteps < 0) return fail(e, FSC_E_INVAL, "nsteps < 0");
     if (nsteps == 0) return FSC_OK;
     if (e->step + nsteps > (int64_t(1) << 32)) return fail(e, FSC_E_INVAL, "step counter would pass 2^32");
@@ -758,6 +760,7 @@ int ens_run(fsc_ens *e, int64_t nsteps, int64_t sk_every) {
         auto key = std::make_pair(parity, std::make_pair(chunk, sk_every));
         auto it = e->graphs.find(key);
         if (it == e->graphs.end()) {
+            TraceRange trace_capture("fsc capture chunk");
             GraphEntry ge;
             hipGraph_t graph;
             HIPCHK(e, hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
@@ -1232,6 +1235,7 @@ int fsc_sk_reset(fsc_ctx *ctx) {
 }
 
 int fsc_measure_sk(fsc_ctx *ctx) {
+    TraceRange trace_("fsc measure_sk");
     if (!ctx) return FSC_E_INVAL;
     fsc_ens *e = ctx->e;
     Rep &r = e->reps[0];

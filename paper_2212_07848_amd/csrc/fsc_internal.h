@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 
 #include <vector>
@@ -9,6 +10,15 @@
 #include "fsc_device.h"
 
 namespace fsc {
+
+// Host-side range around a library call, shown by profilers that collect
+// markers (rocprofv3 --marker-trace); without one attached it costs a call.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 // Tile shape of the fused step kernel: a TX x TY cross-section (TY = 1 in 2D)
 // marching along the slowest axis.

@@ -1347,6 +1347,7 @@ int fsc_sur_set_fusion(fsc_sur *s, int mode) {
 
 int fsc_sur_forward(fsc_sur *s, const float *dev_prev, const float *dev_in, float *dev_out,
                     int batch) {
+    TraceRange trace_("fsc sur_forward");
     if (!s || !dev_out) return FSC_E_INVAL;
     int rc = check_inputs(s, dev_prev, dev_in);
     if (rc) return rc;
@@ -1383,6 +1384,7 @@ int fsc_sur_grad(fsc_sur *s, const float *dev_prev, const float *dev_in, const f
 
 int fsc_sur_train_step(fsc_sur *s, const float *dev_prev, const float *dev_in,
                        const float *dev_target, int batch, float lr, double *loss) {
+    TraceRange trace_("fsc sur_train_step");
     if (!s || !dev_target || !(lr > 0.f)) return FSC_E_INVAL;
     int rc = check_inputs(s, dev_prev, dev_in);
     if (rc) return rc;
@@ -1412,6 +1414,7 @@ int fsc_sur_train_step(fsc_sur *s, const float *dev_prev, const float *dev_in,
 }
 
 int fsc_sur_rollout(fsc_sur *s, const float *dev_prev, float *dev_traj, int batch, int passes) {
+    TraceRange trace_("fsc sur_rollout");
     if (!s || !dev_traj || passes < 1) return FSC_E_INVAL;
     int rc = check_batch(s, batch);
     if (rc) return rc;
