@@ -15,7 +15,9 @@ import sys
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(_HERE, "libfsc.so")
+# FSC_LIB selects another build of the library (a debug build, say); by
+# default the one built in the package directory
+LIBPATH = os.environ.get("FSC_LIB") or os.path.join(_HERE, "libfsc.so")
 
 FSC_E4, FSC_E8 = 4, 8
 FSC_FP32_SHIFTED, FSC_FP64 = 0, 1

@@ -134,6 +134,38 @@ def build(verbose: bool = False, jobs: int | None = None, incremental: bool = Fa
     return LIB
 
 
+def build_lds_poison(out: str | None = None) -> str:
+    """Debug build with FSC_LDS_POISON: every kernel's LDS starts as NaN, so a
+    read of a slot not yet written by the launch shows up in the results.
+    Objects go to _build/lds_poison/; run the GPU tests on it with
+    FSC_LIB=<out> (the binding then loads it instead of libfsc.so)."""
+    out = out or os.path.join(BUILD, "libfsc_lds_poison.so")
+    odir = os.path.join(BUILD, "lds_poison")
+    os.makedirs(odir, exist_ok=True)
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+
+    def one(src):
+        obj = os.path.join(odir, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC, "-c", *CFLAGS, "-DFSC_LDS_POISON", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=min(len(srcs), 8)) as ex:
+        objs = list(ex.map(one, srcs))
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", out,
+           "-L", os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    return out
+
+
 if __name__ == "__main__":
-    build(verbose=True, incremental="--incremental" in sys.argv)
+    if "--lds-poison" in sys.argv:
+        i = sys.argv.index("--lds-poison")
+        print(build_lds_poison(sys.argv[i + 1] if i + 1 < len(sys.argv) else None))
+    else:
+        build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

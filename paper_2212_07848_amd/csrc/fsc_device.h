@@ -305,4 +305,19 @@ __host__ __device__ inline int wrap_any(int v, int n) {
     return r < 0 ? r + n : r;
 }
 
+
+// Debug builds with FSC_LDS_POISON fill a kernel's LDS with NaN before use
+// (then a barrier): a read of a slot that the launch has not written yet
+// carries the NaN into the results, where the parity and bit-identity tests
+// see it.  Off in normal builds.
+template <typename T>
+__device__ __forceinline__ void lds_poison(T *p, int n) {
+#ifdef FSC_LDS_POISON
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = T(__builtin_nanf(""));
+#else
+    (void)p;
+    (void)n;
+#endif
+}
+
 }  // namespace fsc

@@ -61,6 +61,12 @@ __global__ void __launch_bounds__(TX + 64)
     __shared__ real A[SA][WA];
     __shared__ real B[SB][Q][WB];
     __shared__ real Cs[SC][WC];
+#ifdef FSC_LDS_POISON
+    lds_poison(&A[0][0], SA * WA);
+    lds_poison(&B[0][0][0], SB * Q * WB);
+    lds_poison(&Cs[0][0], SC * WC);
+    __syncthreads();
+#endif
 
     // ---- which replica / tile (as in the single-step kernel) ----------------
     const int lb = xcd_remap(blockIdx.x, gridDim.x);

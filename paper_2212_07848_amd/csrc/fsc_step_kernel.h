@@ -319,6 +319,10 @@ __global__ void __launch_bounds__(TX *TY)
     static_assert(MAXRING <= NT, "one ring node per thread at most");
     constexpr uint32_t ES = sizeof(real);
     __shared__ real lds[S][EXTY][EXTX];
+#ifdef FSC_LDS_POISON
+    lds_poison(&lds[0][0][0], S * EXTY * EXTX);
+    __syncthreads();
+#endif
 
     // ---- which replica / tile -------------------------------------------
     const int lb = xcd_remap(blockIdx.x, gridDim.x);

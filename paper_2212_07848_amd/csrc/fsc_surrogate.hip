@@ -263,6 +263,10 @@ __global__ void __launch_bounds__(256) k_mid_lds(const bf16 *__restrict__ ain,
                                                  const float *__restrict__ zprev) {
     constexpr int LW = MW + 2;
     __shared__ __attribute__((aligned(16))) bf16 tile_in[(MR + 2) * LW * SC];
+#ifdef FSC_LDS_POISON
+    lds_poison(tile_in, (MR + 2) * LW * SC);
+    __syncthreads();
+#endif
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, g = lane >> 4;
     const int txs = W / MW, tys = H / MR;
@@ -334,6 +338,11 @@ __global__ void __launch_bounds__(256) k_mid2_lds(const bf16 *__restrict__ ain,
                                                   bf16 *__restrict__ aout) {
     __shared__ __attribute__((aligned(16))) bf16 win[F2IR * F2IW * SC];
     __shared__ __attribute__((aligned(16))) bf16 mid[F2MR * F2MW * SC];
+#ifdef FSC_LDS_POISON
+    lds_poison(win, F2IR * F2IW * SC);
+    lds_poison(mid, F2MR * F2MW * SC);
+    __syncthreads();
+#endif
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, g = lane >> 4;
     const int txs = W / F2W, tys = H / F2R;
