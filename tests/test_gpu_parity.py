@@ -449,6 +449,13 @@ def test_full_size_two_step_launch_matches_oracle():
         got = lat.get_populations()
         G = lat.G
     print("tiling", tiling, flush=True)
+    assert tiling["steps"] == 2
+    # the same two steps as two single-step launches: bit for bit
+    with fsc.Lattice(p) as lat:
+        lat.set_populations(f0, 4321)
+        lat.set_tiling(128, 1, 1, 1, 1024)
+        lat.step(2)
+        assert np.array_equal(lat.get_populations(), got)
     ref = O.step(f0, 2, G=G, kind=c["stencil"], kBT=c["kBT"], seed=c["seed"], t0=4321)
     del f0
     assert_pop_close(got, ref, 2, c["rho0"], c["precision"])
