@@ -181,3 +181,26 @@ def test_two_step_checkpoint_resumes_bit_exactly(tmp_path):
         assert np.array_equal(a.get_populations(k), c.get_populations(k))
     for e in (a, b, c):
         e.close()
+
+
+@pytest.mark.parametrize("D,shape,stencil", [(2, (41, 300), 4), (2, (41, 300), 8), (3, (13, 20, 37), 4)])
+def test_unequal_rates_give_identical_tilings(D, shape, stencil):
+    # bulk, shear and ghost rates all different, so that each moment class
+    # has its own rate and noise amplitude in every kernel (both levels of the
+    # two-step kernel included)
+    nz, ny, nx = shape if D == 3 else (1,) + shape
+    p = fsc.make_params(D=D, nx=nx, ny=ny, nz=nz, stencil=stencil, precision="fp32", T_hat=0.8,
+                        rho0=0.9, lam=(0.7, 1.3, 1.8), kBT=1e-4, seed=5)
+    Q = 9 if D == 2 else 19
+    f0 = I.smooth_density_populations(Q, shape, 0.9, 0.05, 3, seed=8)
+    shapes = fsc.tile_shapes(D, stencil, "fp32")
+    want = None
+    for (tx, ty, pf, steps) in shapes:
+        with fsc.Lattice(p) as lat:
+            lat.set_populations(f0, 11)
+            lat.set_tiling(tx, ty, pf, steps, 37)
+            lat.step(6)
+            got = lat.get_populations()
+        if want is None:
+            want = got
+        assert np.array_equal(got, want), (tx, ty, pf, steps)
