@@ -87,7 +87,9 @@ def _compile(src: str, incremental: bool = False) -> str:
         if t > os.path.getmtime(os.path.join(CSRC, src)) and t > _newest_header():
             return obj
     check = src in STEP_SOURCES
-    extra = ["-Rpass-analysis=kernel-resource-usage"] if check else []
+    # step kernels: resource report, and no FP contraction beyond the written
+    # fused multiply-adds (every kernel then rounds the same way)
+    extra = ["-Rpass-analysis=kernel-resource-usage", "-ffp-contract=off"] if check else []
     cmd = [HIPCC, "-c", *CFLAGS, *extra, os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -146,7 +148,8 @@ def build_lds_poison(out: str | None = None) -> str:
 
     def one(src):
         obj = os.path.join(odir, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, "-c", *CFLAGS, "-DFSC_LDS_POISON", os.path.join(CSRC, src), "-o", obj]
+        extra = ["-ffp-contract=off"] if src in STEP_SOURCES else []
+        cmd = [HIPCC, "-c", *CFLAGS, *extra, "-DFSC_LDS_POISON", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")

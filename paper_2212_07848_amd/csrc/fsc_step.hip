@@ -32,11 +32,12 @@ int tile_shapes(int D, int stencil, int precision, TileShape *out, int max) {
                                    {192, 1, 0, 2}, {192, 1, 1, 2}};
     static const TileShape d2[] = {{128, 1, 1}};
     static const TileShape f3[] = {{32, 8, 1},  {32, 8, 2}, {64, 4, 1},  {64, 4, 2}, {64, 8, 1},
-                                   {32, 16, 1}, {128, 4, 1}, {128, 4, 0}, {64, 8, 0}, {64, 4, 0}};
+                                   {32, 16, 1}, {128, 4, 1}, {128, 4, 0}, {64, 8, 0}, {64, 4, 0},
+                                   {256, 4, 0}};
     static const TileShape d3[] = {{32, 8, 0}, {32, 8, 1}};
     (void)stencil;
     const TileShape *t = D == 2 ? (precision == 0 ? f2 : d2) : (precision == 0 ? f3 : d3);
-    const int n = D == 2 ? (precision == 0 ? 11 : 1) : (precision == 0 ? 10 : 2);
+    const int n = D == 2 ? (precision == 0 ? 11 : 1) : (precision == 0 ? 11 : 2);
     for (int i = 0; i < n && i < max; ++i) out[i] = t[i];
     return n;
 }

@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(TX + 64)
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int eq = ST::e(a, q);
-                if (eq != 0) g[q] += real(ST::w(a) * eq) * diff;
+                if (eq != 0) g[q] = fmadd(real(ST::w(a) * eq), diff, g[q]);
             }
         }
         const real pre = G * (psi0 + A[ja][x1 + OA]);
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(TX + 64)
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int eq = ST::e(a, q);
-                if (eq != 0) g[q] += real(ST::w(a) * eq) * diff;
+                if (eq != 0) g[q] = fmadd(real(ST::w(a) * eq), diff, g[q]);
             }
         }
         const real pre = G * (psi0 + Cs[kc][x2 + OC]);

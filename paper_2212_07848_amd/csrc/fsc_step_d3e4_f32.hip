@@ -25,6 +25,10 @@ hipError_t launch_step_d3e4_f32(const StepLaunch &P, hipStream_t s) {
     if (P.tile.tx == 128 && P.tile.ty == 4 && P.tile.pf == 1)
         return P.noise ? launch_one<D3Q19, StencilE4_3D, float, true, 128, 4, 1>(P, s)
                        : launch_one<D3Q19, StencilE4_3D, float, false, 128, 4, 1>(P, s);
+    // whole 256-wide rows, four per tile (one 16-wave workgroup per CU)
+    if (P.tile.tx == 256 && P.tile.ty == 4 && P.tile.pf == 0)
+        return P.noise ? launch_one<D3Q19, StencilE4_3D, float, true, 256, 4, 0>(P, s)
+                       : launch_one<D3Q19, StencilE4_3D, float, false, 256, 4, 0>(P, s);
     // no prefetch (ring of R + 1 planes): fewer registers, more waves per SIMD
     if (P.tile.tx == 128 && P.tile.ty == 4 && P.tile.pf == 0)
         return P.noise ? launch_one<D3Q19, StencilE4_3D, float, true, 128, 4, 0>(P, s)

@@ -78,6 +78,15 @@ __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, d
                                           FSC_STORE_POLICY);
 }
 
+// Fused multiply-add, written out wherever the step arithmetic uses one.  The
+// step kernels are compiled with FP contraction off (-ffp-contract=off and the
+// pragma below), so that no kernel rounds a product differently from another:
+// left to itself the compiler fuses multiplies and adds differently in
+// different kernels, and the tilings would then differ in the last bit.
+#pragma clang fp contract(off)
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -105,19 +114,19 @@ __device__ __forceinline__ void collide_d2q9(real (&f)[9], real rho0, const real
     const real dn = f[0] + Ax + Dg;
     const real u1 = d57 - d68, u2 = d57 + d68;
     const real jx = d13 + u1, jy = d24 + u2;
-    const real m3 = real(4) * Dg + Ax - real(2) * f[0];
+    const real m3 = fmadd(real(-2), f[0], fmadd(real(4), Dg, Ax));
     const real m4 = s13 - s24;
     const real m5 = s57 - s68;
-    const real m6 = real(2) * u1 - d13;
-    const real m7 = real(2) * u2 - d24;
-    const real m8 = real(8) * Dg - real(4) * Ax + real(2) * f[0];
+    const real m6 = fmadd(real(2), u1, -d13);
+    const real m7 = fmadd(real(2), u2, -d24);
+    const real m8 = fmadd(real(8), Dg, fmadd(real(-4), Ax, real(2) * f[0]));
 
     const real rho = rho0 + dn;
     const real ir = fast_rcp(rho);
-    const real ux = (jx + real(0.5) * F[0]) * ir;
-    const real uy = (jy + real(0.5) * F[1]) * ir;
-    const real uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
-    const real uFx = ux * F[0], uFy = uy * F[1];
+    const real ux = fmadd(real(0.5), F[0], jx) * ir;
+    const real uy = fmadd(real(0.5), F[1], jy) * ir;
+    const real uyy = uy * uy, uxy = ux * uy;
+    const real uFy = uy * F[1];
 
     // noise: row a of class c adds sqrt(b_a) amp_c sqrt(n) xi_a
     constexpr RowScale<D2Q9> sb{};
@@ -130,39 +139,42 @@ __device__ __forceinline__ void collide_d2q9(real (&f)[9], real rho0, const real
     }
     auto relax = [&](int a, real m, real meq, real src, real zz) {
         const real l = lc[D2Q9::cls(a)];
-        real o = m + l * (meq - m) + (real(1) - real(0.5) * l) * src;
-        if constexpr (NOISE) o += real(sb.v[a]) * sa[D2Q9::cls(a)] * zz;
+        real o = fmadd(l, meq - m, m);
+        o = fmadd(fmadd(real(-0.5), l, real(1)), src, o);
+        if constexpr (NOISE) o = fmadd(real(sb.v[a]) * sa[D2Q9::cls(a)], zz, o);
         return o;
     };
     auto ghost = [&](int a, real m, real zz) {
         real o = (real(1) - lc[3]) * m;
-        if constexpr (NOISE) o += real(sb.v[a]) * sa[3] * zz;
+        if constexpr (NOISE) o = fmadd(real(sb.v[a]) * sa[3], zz, o);
         return o;
     };
-    // post-collision moments, each divided by its norm b_a
+    // conserved moments (mass; momentum with the full force) divided by b_a
     const real n0 = dn;
     const real n1 = (jx + F[0]) * real(3);
     const real n2 = (jy + F[1]) * real(3);
-    const real n3 = relax(3, m3, real(3) * rho * (uxx + uyy), real(6) * (uFx + uFy), z[0]) * real(0.25);
-    const real n4 = relax(4, m4, rho * (uxx - uyy), real(2) * (uFx - uFy), z[1]) * real(2.25);
-    const real n5 = relax(5, m5, rho * uxy, ux * F[1] + uy * F[0], z[2]) * real(9);
-    const real n6 = ghost(6, m6, z[3]) * real(1.5);
-    const real n7 = ghost(7, m7, z[4]) * real(1.5);
-    const real n8 = ghost(8, m8, z[5]) * real(0.0625);
+    // post-collision moments o_a; n_a = o_a / b_a enters the back-transform
+    // through the factors below (b_3..b_8 = 4, 4/9, 1/9, 2/3, 2/3, 16)
+    const real o3 = relax(3, m3, real(3) * rho * fmadd(ux, ux, uyy), real(6) * fmadd(ux, F[0], uFy), z[0]);
+    const real o4 = relax(4, m4, rho * fmadd(ux, ux, -uyy), real(2) * fmadd(ux, F[0], -uFy), z[1]);
+    const real o5 = relax(5, m5, rho * uxy, fmadd(ux, F[1], uy * F[0]), z[2]);
+    const real o6 = ghost(6, m6, z[3]);
+    const real o7 = ghost(7, m7, z[4]);
+    const real o8 = ghost(8, m8, z[5]);
 
     // back-transform f_i = w_i sum_a M_ai n_a
     const real w0 = real(4.0 / 9.0), w1 = real(1.0 / 9.0), w5 = real(1.0 / 36.0);
-    f[0] = w0 * (n0 - real(2) * n3 + real(2) * n8);
-    const real ba = n0 + n3 - real(4) * n8;
-    const real ap = ba + n4, am = ba - n4;
-    const real px = n1 - n6, py = n2 - n7;
+    f[0] = w0 * fmadd(real(0.125), o8, fmadd(real(-0.5), o3, n0));
+    const real ba = fmadd(real(-0.25), o8, fmadd(real(0.25), o3, n0));
+    const real ap = fmadd(real(2.25), o4, ba), am = fmadd(real(-2.25), o4, ba);
+    const real px = fmadd(real(-1.5), o6, n1), py = fmadd(real(-1.5), o7, n2);
     f[1] = w1 * (ap + px);
     f[3] = w1 * (ap - px);
     f[2] = w1 * (am + py);
     f[4] = w1 * (am - py);
-    const real bd = n0 + real(4) * n3 + real(8) * n8;
-    const real bp = bd + n5, bm = bd - n5;
-    const real X = n1 + real(2) * n6, Y = n2 + real(2) * n7;
+    const real bd = fmadd(real(0.5), o8, n0 + o3);
+    const real bp = fmadd(real(9), o5, bd), bm = fmadd(real(-9), o5, bd);
+    const real X = fmadd(real(3), o6, n1), Y = fmadd(real(3), o7, n2);
     const real XpY = X + Y, XmY = X - Y;
     f[5] = w5 * (bp + XpY);
     f[7] = w5 * (bp - XpY);
@@ -197,22 +209,22 @@ __device__ __forceinline__ void collide_d3q19(real (&f)[19], real rho0, const re
     const real Dz4 = D3 - D4 + D5 - D6;
     const real jx = dx + Dx4, jy = dy + Dy4, jz = dz + Dz4;
     const real m4 = Sd - f[0];
-    const real m5 = real(2) * sx - sy - sz + Sxy + Sxz - real(2) * Syz;
+    const real m5 = fmadd(real(-2), Syz, fmadd(real(2), sx, -sy) - sz + Sxy + Sxz);
     const real m6 = sy - sz + Sxy - Sxz;
     const real m7 = S1 - S2, m8 = S5 - S6, m9 = S3 - S4;
-    const real m10 = Dx4 - real(2) * dx, m11 = Dy4 - real(2) * dy, m12 = Dz4 - real(2) * dz;
+    const real m10 = fmadd(real(-2), dx, Dx4), m11 = fmadd(real(-2), dy, Dy4), m12 = fmadd(real(-2), dz, Dz4);
     const real m13 = D1 + D2 - D3 - D4;
     const real m14 = D2 - D1 + D5 + D6;
     const real m15 = D3 - D4 - D5 + D6;
-    const real m16 = f[0] - real(2) * Sa + Sd;
-    const real m17 = sy + sz - real(2) * sx + Sxy + Sxz - real(2) * Syz;
+    const real m16 = fmadd(real(-2), Sa, f[0]) + Sd;
+    const real m17 = fmadd(real(-2), Syz, fmadd(real(-2), sx, sy + sz) + Sxy + Sxz);
     const real m18 = sz - sy + Sxy - Sxz;
 
     const real rho = rho0 + dn;
     const real ir = fast_rcp(rho);
-    const real ux = (jx + real(0.5) * F[0]) * ir;
-    const real uy = (jy + real(0.5) * F[1]) * ir;
-    const real uz = (jz + real(0.5) * F[2]) * ir;
+    const real ux = fmadd(real(0.5), F[0], jx) * ir;
+    const real uy = fmadd(real(0.5), F[1], jy) * ir;
+    const real uz = fmadd(real(0.5), F[2], jz) * ir;
     const real uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
     const real uFx = ux * F[0], uFy = uy * F[1], uFz = uz * F[2];
 
@@ -226,63 +238,69 @@ __device__ __forceinline__ void collide_d3q19(real (&f)[19], real rho0, const re
     }
     auto relax = [&](int a, real m, real meq, real src, real zz) {
         const real l = lc[D3Q19::cls(a)];
-        real o = m + l * (meq - m) + (real(1) - real(0.5) * l) * src;
-        if constexpr (NOISE) o += real(sb.v[a]) * sa[D3Q19::cls(a)] * zz;
+        real o = fmadd(l, meq - m, m);
+        o = fmadd(fmadd(real(-0.5), l, real(1)), src, o);
+        if constexpr (NOISE) o = fmadd(real(sb.v[a]) * sa[D3Q19::cls(a)], zz, o);
         return o;
     };
     auto ghost = [&](int a, real m, real zz) {
         real o = (real(1) - lc[3]) * m;
-        if constexpr (NOISE) o += real(sb.v[a]) * sa[3] * zz;
+        if constexpr (NOISE) o = fmadd(real(sb.v[a]) * sa[3], zz, o);
         return o;
     };
-    // post-collision moments divided by their norms
+    // conserved moments divided by b_a; the others as o_a, with n_a = o_a / b_a
+    // entering the back-transform through the factors below (b_4..b_18 =
+    // 2/3, 4/3, 4/9, 1/9 (3), 2/3 (3), 2/9 (3), 2, 4/3, 4/9)
     const real n0 = dn;
     const real n1 = (jx + F[0]) * real(3), n2 = (jy + F[1]) * real(3), n3 = (jz + F[2]) * real(3);
-    const real n4 = relax(4, m4, rho * (uxx + uyy + uzz), real(2) * (uFx + uFy + uFz), z[0]) * real(1.5);
-    const real n5 = relax(5, m5, rho * (real(2) * uxx - uyy - uzz),
-                          real(2) * (real(2) * uFx - uFy - uFz), z[1]) * real(0.75);
-    const real n6 = relax(6, m6, rho * (uyy - uzz), real(2) * (uFy - uFz), z[2]) * real(2.25);
-    const real n7 = relax(7, m7, rho * ux * uy, ux * F[1] + uy * F[0], z[3]) * real(9);
-    const real n8 = relax(8, m8, rho * uy * uz, uy * F[2] + uz * F[1], z[4]) * real(9);
-    const real n9 = relax(9, m9, rho * uz * ux, uz * F[0] + ux * F[2], z[5]) * real(9);
-    const real n10 = ghost(10, m10, z[6]) * real(1.5);
-    const real n11 = ghost(11, m11, z[7]) * real(1.5);
-    const real n12 = ghost(12, m12, z[8]) * real(1.5);
-    const real n13 = ghost(13, m13, z[9]) * real(4.5);
-    const real n14 = ghost(14, m14, z[10]) * real(4.5);
-    const real n15 = ghost(15, m15, z[11]) * real(4.5);
-    const real n16 = ghost(16, m16, z[12]) * real(0.5);
-    const real n17 = ghost(17, m17, z[13]) * real(0.75);
-    const real n18 = ghost(18, m18, z[14]) * real(2.25);
+    const real o4 = relax(4, m4, rho * fmadd(ux, ux, fmadd(uy, uy, uzz)),
+                          real(2) * fmadd(ux, F[0], fmadd(uy, F[1], uFz)), z[0]);
+    const real o5 = relax(5, m5, rho * fmadd(real(2), uxx, -uyy - uzz),
+                          real(2) * fmadd(real(2), uFx, -uFy - uFz), z[1]);
+    const real o6 = relax(6, m6, rho * fmadd(uy, uy, -uzz), real(2) * fmadd(uy, F[1], -uFz), z[2]);
+    const real o7 = relax(7, m7, rho * ux * uy, fmadd(ux, F[1], uy * F[0]), z[3]);
+    const real o8 = relax(8, m8, rho * uy * uz, fmadd(uy, F[2], uz * F[1]), z[4]);
+    const real o9 = relax(9, m9, rho * uz * ux, fmadd(uz, F[0], ux * F[2]), z[5]);
+    const real o10 = ghost(10, m10, z[6]);
+    const real o11 = ghost(11, m11, z[7]);
+    const real o12 = ghost(12, m12, z[8]);
+    const real o13 = ghost(13, m13, z[9]);
+    const real o14 = ghost(14, m14, z[10]);
+    const real o15 = ghost(15, m15, z[11]);
+    const real o16 = ghost(16, m16, z[12]);
+    const real o17 = ghost(17, m17, z[13]);
+    const real o18 = ghost(18, m18, z[14]);
 
     // back-transform f_i = w_i sum_a M_ai n_a, pairwise
     const real w0 = real(1.0 / 3.0), w1 = real(1.0 / 18.0), w2 = real(1.0 / 36.0);
-    f[0] = w0 * (n0 - n4 + n16);
-    const real e0 = n0 - real(2) * n16;
-    const real Ex = e0 + real(2) * (n5 - n17), Ox = n1 - real(2) * n10;
-    const real eyz = e0 - n5 + n17;
-    const real Ey = eyz + n6 - n18, Oy = n2 - real(2) * n11;
-    const real Ez = eyz - n6 + n18, Oz = n3 - real(2) * n12;
+    f[0] = w0 * fmadd(real(0.5), o16, fmadd(real(-1.5), o4, n0));
+    const real e0 = n0 - o16;
+    const real p517 = o5 - o17, q517 = o5 + o17, p618 = o6 - o18, q618 = o6 + o18;
+    const real Ex = fmadd(real(1.5), p517, e0), Ox = fmadd(real(-3), o10, n1);
+    const real eyz = fmadd(real(-0.75), p517, e0);
+    const real Ey = fmadd(real(2.25), p618, eyz), Oy = fmadd(real(-3), o11, n2);
+    const real Ez = fmadd(real(-2.25), p618, eyz), Oz = fmadd(real(-3), o12, n3);
     f[1] = w1 * (Ex + Ox);
     f[2] = w1 * (Ex - Ox);
     f[3] = w1 * (Ey + Oy);
     f[4] = w1 * (Ey - Oy);
     f[5] = w1 * (Ez + Oz);
     f[6] = w1 * (Ez - Oz);
-    const real ed = n0 + n4 + n16;
-    const real exy = ed + n5 + n6 + n17 + n18;   // pairs 1, 2 (before the +-n7 term)
-    const real exz = ed + n5 - n6 + n17 - n18;   // pairs 3, 4 (+-n9)
-    const real eyz2 = ed - real(2) * (n5 + n17); // pairs 5, 6 (+-n8)
-    const real E1 = exy + n7, E2 = exy - n7;
-    const real E3 = exz + n9, E4 = exz - n9;
-    const real E5 = eyz2 + n8, E6 = eyz2 - n8;
-    const real ax = n1 + n10, ay = n2 + n11, az = n3 + n12;
-    const real O1 = ax + ay + n13 - n14;
-    const real O2 = ax - ay + n13 + n14;
-    const real O3 = ax + az - n13 + n15;
-    const real O4 = ax - az - n13 - n15;
-    const real O5 = ay + az + n14 - n15;
-    const real O6 = ay - az + n14 + n15;
+    const real ed = fmadd(real(0.5), o16, fmadd(real(1.5), o4, n0));
+    const real e5 = fmadd(real(0.75), q517, ed);
+    const real exy = fmadd(real(2.25), q618, e5);    // pairs 1, 2 (before the +-n7 term)
+    const real exz = fmadd(real(-2.25), q618, e5);   // pairs 3, 4 (+-n9)
+    const real eyz2 = fmadd(real(-1.5), q517, ed);   // pairs 5, 6 (+-n8)
+    const real E1 = fmadd(real(9), o7, exy), E2 = fmadd(real(-9), o7, exy);
+    const real E3 = fmadd(real(9), o9, exz), E4 = fmadd(real(-9), o9, exz);
+    const real E5 = fmadd(real(9), o8, eyz2), E6 = fmadd(real(-9), o8, eyz2);
+    const real ax = fmadd(real(1.5), o10, n1), ay = fmadd(real(1.5), o11, n2), az = fmadd(real(1.5), o12, n3);
+    const real O1 = fmadd(real(4.5), o13 - o14, ax + ay);
+    const real O2 = fmadd(real(4.5), o13 + o14, ax - ay);
+    const real O3 = fmadd(real(4.5), o15 - o13, ax + az);
+    const real O4 = fmadd(real(-4.5), o13 + o15, ax - az);
+    const real O5 = fmadd(real(4.5), o14 - o15, ay + az);
+    const real O6 = fmadd(real(4.5), o14 + o15, ay - az);
     f[7] = w2 * (E1 + O1);
     f[8] = w2 * (E1 - O1);
     f[9] = w2 * (E2 + O2);
@@ -556,7 +574,7 @@ __global__ void __launch_bounds__(TX *TY)
 #pragma unroll
                 for (int q = 0; q < D; ++q) {
                     const int eq = ST::e(a, q);
-                    if (eq != 0) g[q] += real(ST::w(a) * eq) * diff;
+                    if (eq != 0) g[q] = fmadd(real(ST::w(a) * eq), diff, g[q]);
                 }
             }
             const real pre = G * (psi0 + lds[sl[R]][ty + RY][tx + R]);
