@@ -62,12 +62,24 @@ def kernel_name(stencil: str, noise: bool, tiling: dict, lattice: str = "D2Q9") 
     """Name of the step kernel a tiling launches (as rocprofv3 reports it)."""
     n = "true" if noise else "false"
     if tiling.get("steps", 1) == 2:  # prefetch field 0/1: one or two barriers per row
-        return f"k_step2<{stencil}, float, {n}, {tiling['tx']}, {tiling['pf'] + 1}>"
+        hin = "true" if in_tile_halo(tiling) else "false"
+        return f"k_step2<{stencil}, float, {n}, {tiling['tx']}, {tiling['pf'] + 1}, {hin}>"
     # the last argument: buffers below 4 GiB (one buffer resource for all populations)
     return f"k_step<{lattice}, {stencil}, float, {n}, {tiling['tx']}, {tiling['ty']}, {tiling['pf']}, false>"
 
 
+# two-step tile widths whose workgroups hold the halo columns in the tile's own
+# lanes (tx + 4R + 2 = 256 lanes: E4 R = 1, E8 R = 2); the others add an edge wave
+IN_TILE_HALO = {250: 6, 246: 10}
+
+
+def in_tile_halo(tiling: dict) -> bool:
+    return tiling.get("steps", 1) == 2 and tiling["tx"] in IN_TILE_HALO
+
+
 def grid_threads(tiling: dict) -> int:
+    if in_tile_halo(tiling):
+        return tiling["blocks"] * (tiling["tx"] + IN_TILE_HALO[tiling["tx"]])
     extra = 64 if tiling.get("steps", 1) == 2 else 0  # the two-step kernel's edge wave
     return tiling["blocks"] * (tiling["tx"] * tiling["ty"] + extra)
 
@@ -219,7 +231,8 @@ def summarize_trace(trace_dir: str, log_path: str, out_path: str):
         t = rf["tiling"]
         grid = grid_threads(t)
         kname = rf["kernel"]
-        key = next((k for k in shapes if k[1] == grid and k[0].endswith(kname)), None)
+        key = next((k for k in shapes if k[1] == grid and k[0].replace("fsc::", "").endswith(kname)),
+                   None)
         lines += [f"## Benchmarked launch ({bench['config']['workload']}, {t.get('steps', 1)} "
                   f"step(s) per launch)", "",
                   f"- kernel: `{kname}`, {t['blocks']} blocks ({grid} threads)",

@@ -442,7 +442,9 @@ int fsc_ens_get_tiling(const fsc_ens *ens, int *out5);
  * results equal two single steps bit for bit.  Runs then go in pairs of steps,
  * with single steps where an S(k) sample falls between two steps.  For these
  * tilings the prefetch field selects the on-chip schedule (0: one barrier per
- * row; 1: two barriers per row and 3/4 of the LDS). */
+ * row; 1: two barriers per row and 3/4 of the LDS).  The two-step widths 246
+ * (E8) and 250 (E4) keep the tile's 4R + 2 halo columns in its own 256 lanes
+ * instead of an extra wave. */
 int fsc_tile_shapes(int D, int stencil, int precision, int *out4, int max);
 
 /* Fixes the tiling instead of tuning it: one of the compiled tilings, and a

@@ -653,11 +653,11 @@ def tile_shapes(D: int, stencil: int, precision: str = "fp32"):
     lattice kind; the first is the default."""
     prec = {"fp32": FSC_FP32_SHIFTED, "fp64": FSC_FP64}[precision] if isinstance(precision, str) \
         else int(precision)
-    out = (C.c_int * 64)()
-    n = lib().fsc_tile_shapes(int(D), int(stencil), prec, out, 16)
+    out = (C.c_int * 128)()
+    n = lib().fsc_tile_shapes(int(D), int(stencil), prec, out, 32)
     if n < 0:
         raise FscError(n, "unsupported lattice kind")
-    return [tuple(out[4 * i:4 * i + 4]) for i in range(min(n, 16))]
+    return [tuple(out[4 * i:4 * i + 4]) for i in range(min(n, 32))]
 
 
 def linear_sk(p: Params, kvecs) -> np.ndarray:

@@ -649,8 +649,8 @@ int ens_autotune(fsc_ens *e) {
             return upload_desc(e);
         }
     }
-    TileShape shapes[16];
-    const int nshape = tile_shapes(e->D, e->stencil, e->precision, shapes, 16);
+    TileShape shapes[32];
+    const int nshape = tile_shapes(e->D, e->stencil, e->precision, shapes, 32);
     // block counts of one round of resident workgroups (a multiple of the
     // 256 CUs: 1-8 per CU, depending on the kernel's LDS and registers) and
     // of several rounds
@@ -832,8 +832,8 @@ int ens_create(const fsc_params *ps, int nrep, void *stream, void *ext_a, void *
     e->D = rp[0].D;
     e->stencil = rp[0].stencil;
     e->precision = rp[0].precision;
-    TileShape shapes[16];
-    tile_shapes(e->D, e->stencil, e->precision, shapes, 16);
+    TileShape shapes[32];
+    tile_shapes(e->D, e->stencil, e->precision, shapes, 32);
     e->tile = shapes[0];
     if (const char *env = std::getenv("FSC_AUTOTUNE")) e->autotune = std::atoi(env) ? -2 : 0;
     e->reps.resize(nrep);
@@ -1394,8 +1394,8 @@ int fsc_tile_shapes(int D, int stencil, int precision, int *out4, int max) {
     if (!((D == 2 && (stencil == FSC_E4 || stencil == FSC_E8)) || (D == 3 && stencil == FSC_E4)) ||
         (precision != FSC_FP32_SHIFTED && precision != FSC_FP64) || max < 0 || (max > 0 && !out4))
         return FSC_E_INVAL;
-    TileShape t[16];
-    const int n = tile_shapes(D, stencil, precision, t, 16);
+    TileShape t[32];
+    const int n = tile_shapes(D, stencil, precision, t, 32);
     for (int i = 0; i < n && i < max; ++i) {
         out4[4 * i] = t[i].tx;
         out4[4 * i + 1] = t[i].ty;
@@ -1407,8 +1407,8 @@ int fsc_tile_shapes(int D, int stencil, int precision, int *out4, int max) {
 
 static int set_tiling(fsc_ens *e, int tx, int ty, int pf, int steps, int64_t target_blocks) {
     if (target_blocks < 1) return fail(e, FSC_E_INVAL, "target_blocks < 1");
-    TileShape t[16];
-    const int n = tile_shapes(e->D, e->stencil, e->precision, t, 16);
+    TileShape t[32];
+    const int n = tile_shapes(e->D, e->stencil, e->precision, t, 32);
     for (int i = 0; i < n; ++i)
         if (t[i].tx == tx && t[i].ty == ty && t[i].pf == pf && t[i].steps == steps) {
             if (steps == 2 && !two_step_ok(e))

@@ -30,15 +30,25 @@ int tile_shapes(int D, int stencil, int precision, TileShape *out, int max) {
                                    {128, 1, 1},    {256, 1, 1},    {128, 1, 0, 2},
                                    {256, 1, 0, 2}, {128, 1, 1, 2}, {256, 1, 1, 2},
                                    {192, 1, 0, 2}, {192, 1, 1, 2}};
+    // two-step tilings whose lanes hold the tile's columns and both halos
+    // (4R + 2 columns, so the width depends on the stencil), and their
+    // single-step partners
+    static const TileShape f2e4[] = {{250, 1, 0, 2}, {250, 1, 1, 2}, {250, 1, 1}};
+    static const TileShape f2e8[] = {{246, 1, 0, 2}, {246, 1, 1, 2}, {246, 1, 1}};
     static const TileShape d2[] = {{128, 1, 1}};
     static const TileShape f3[] = {{32, 8, 1},  {32, 8, 2}, {64, 4, 1},  {64, 4, 2}, {64, 8, 1},
                                    {32, 16, 1}, {128, 4, 1}, {128, 4, 0}, {64, 8, 0}, {64, 4, 0},
                                    {256, 4, 0}};
     static const TileShape d3[] = {{32, 8, 0}, {32, 8, 1}};
-    (void)stencil;
     const TileShape *t = D == 2 ? (precision == 0 ? f2 : d2) : (precision == 0 ? f3 : d3);
     const int n = D == 2 ? (precision == 0 ? 11 : 1) : (precision == 0 ? 11 : 2);
     for (int i = 0; i < n && i < max; ++i) out[i] = t[i];
+    if (D == 2 && precision == 0) {
+        const TileShape *x = stencil == 8 ? f2e8 : f2e4;
+        for (int i = 0; i < 3; ++i)
+            if (n + i < max) out[n + i] = x[i];
+        return n + 3;
+    }
     return n;
 }
 

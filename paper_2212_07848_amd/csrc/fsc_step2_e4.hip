@@ -23,6 +23,12 @@ hipError_t launch_step2_e4(const StepLaunch &P, hipStream_t s) {
                               : launch_two<StencilE4_2D, float, true, 256, 1>(P, s))
                        : (two ? launch_two<StencilE4_2D, float, false, 256, 2>(P, s)
                               : launch_two<StencilE4_2D, float, false, 256, 1>(P, s));
+    // tile columns and their halos in the same lanes: 250 output columns per 250 + 4R + 2 = 256 lanes
+    if (P.tile.tx == 250)
+        return P.noise ? (two ? launch_two<StencilE4_2D, float, true, 250, 2, true>(P, s)
+                              : launch_two<StencilE4_2D, float, true, 250, 1, true>(P, s))
+                       : (two ? launch_two<StencilE4_2D, float, false, 250, 2, true>(P, s)
+                              : launch_two<StencilE4_2D, float, false, 250, 1, true>(P, s));
     return hipErrorInvalidValue;
 }
 

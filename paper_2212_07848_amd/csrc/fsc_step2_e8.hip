@@ -23,6 +23,12 @@ hipError_t launch_step2_e8(const StepLaunch &P, hipStream_t s) {
                               : launch_two<StencilE8_2D, float, true, 256, 1>(P, s))
                        : (two ? launch_two<StencilE8_2D, float, false, 256, 2>(P, s)
                               : launch_two<StencilE8_2D, float, false, 256, 1>(P, s));
+    // tile columns and their halos in the same lanes: 246 output columns per 246 + 4R + 2 = 256 lanes
+    if (P.tile.tx == 246)
+        return P.noise ? (two ? launch_two<StencilE8_2D, float, true, 246, 2, true>(P, s)
+                              : launch_two<StencilE8_2D, float, true, 246, 1, true>(P, s))
+                       : (two ? launch_two<StencilE8_2D, float, false, 246, 2, true>(P, s)
+                              : launch_two<StencilE8_2D, float, false, 246, 1, true>(P, s));
     return hipErrorInvalidValue;
 }
 

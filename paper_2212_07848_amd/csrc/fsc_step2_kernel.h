@@ -23,6 +23,14 @@
 // the tile lanes near either end also write their LDS values at the periodic
 // image columns, so the halo reads stay plain offsets.
 //
+// In-tile halos (template HIN): the workgroup has TX + 4R + 2 lanes and lane l
+// owns column l - (2R + 1), so the halo columns sit in the same waves as the
+// tile's own; every stage keeps the lanes whose column lies in its range
+// (psi(t) [-2R-1, TXe+2R], level 1 [-R-1, TXe+R], psi(t+1) [-R, TXe+R-1],
+// level 2 [0, TXe-1]).  The edge wave's mostly idle lanes disappear: per
+// output column a launch issues about a tenth fewer wave instructions.  Whole
+// rows use the mapping above without the extra wave.
+//
 // March of a chunk of H output rows o_0..o_{H-1} (direction alternating by
 // chunk as in the single-step kernel): level 1 runs over the rows
 // l_k = o_{k-R-1}, k = 0..H+2R+1, with the pulled rows of f(t) in a register
@@ -47,8 +55,15 @@
 
 namespace fsc {
 
-template <class ST, typename real, bool NOISE, int TX, int BARS>
-__global__ void __launch_bounds__(TX + 64)
+// Threads of a workgroup: TX tile lanes and the edge wave, or (HIN) the tile's
+// TX output columns with their 2R + 1 halo columns on either side.
+template <class ST, int TX, bool HIN>
+constexpr int step2_lanes() {
+    return HIN ? TX + 4 * ST::R + 2 : TX + 64;
+}
+
+template <class ST, typename real, bool NOISE, int TX, int BARS, bool HIN = false>
+__global__ void __launch_bounds__((step2_lanes<ST, TX, HIN>()))
     k_step2(const RepDesc *__restrict__ reps, const int *__restrict__ tile_begin, int nrep,
             int parity, const uint64_t *__restrict__ step_base, uint32_t step_off) {
     using L = D2Q9;
@@ -89,20 +104,38 @@ __global__ void __launch_bounds__(TX + 64)
     const bool full = d.tiles_x == 1;  // TXe == nx: the tile holds whole periodic rows
 
     const int tid = threadIdx.x;
-    const bool ewave = tid >= TX;
+    // HIN with a tile that is not a whole row: lane tid owns column tid - (2R + 1)
+    const bool shifted = HIN && !full;  // wave-uniform
+    const bool ewave = !HIN && tid >= TX;
     const int e = tid - TX;
     const bool eidle = ewave && full;  // wave-uniform
-    // a tile wave wholly past the tile's last column (a tile narrower than TX)
-    // has no node of its own: it only takes part in the barriers
-    const bool tidle = !ewave && (tid & ~63) >= TXe;  // wave-uniform
+    // A wave wholly past the columns the tile needs (a tile narrower than TX)
+    // has no node of its own: it only takes part in the barriers.
+    const bool tidle = !ewave && (shifted ? (tid & ~63) >= TXe + 4 * R + 2 : (tid & ~63) >= TXe);
     const bool idle = eidle || tidle;
 
     // level-1 node: column offset x1, collides (c1), writes to A (wa) and B (wb)
     int x1 = 0;
     bool c1 = !ewave && !tidle, wa = false, wb = false;
-    if (!ewave) {
+    // level-2 node: column offset x2, forms psi(t+1) (p2), writes to C (wc);
+    // collides and stores to HBM (st2)
+    int x2 = 0;
+    bool p2 = !ewave && !tidle, wc = false, st2 = !ewave && !tidle;
+    if (shifted) {
+        // the tile's columns and both halos in one range of lanes; lanes past
+        // its end duplicate the last column and write nothing
+        const int c = tid - (2 * R + 1);
+        x1 = min(c, TXe + 2 * R);
+        wa = c < TXe + 2 * R + 1;
+        c1 = wb = c >= -R - 1 && c < TXe + R + 1;
+        x2 = x1;
+        p2 = wc = c >= -R && c < TXe + R;
+        st2 = c >= 0 && c < TXe;
+    } else if (!ewave) {
         x1 = min(tid, TXe - 1);
         wa = wb = tid < TXe;
+        x2 = x1;
+        wc = tid < TXe;
     } else if (!full && e < 2 * R + 2) {
         x1 = e < R + 1 ? -R - 1 + e : TXe + (e - R - 1);
         c1 = wa = wb = true;
@@ -111,15 +144,7 @@ __global__ void __launch_bounds__(TX + 64)
         x1 = k < R ? -2 * R - 1 + k : TXe + R + 1 + (k - R);
         wa = true;
     }
-    // level-2 node: column offset x2, forms psi(t+1) (p2), writes to C (wc);
-    // tile lanes collide and store to HBM
-    int x2 = 0;
-    bool p2 = !ewave && !tidle, wc = false;
-    const bool st2 = !ewave && !tidle;  // collides and stores a level-2 node
-    if (!ewave) {
-        x2 = x1;
-        wc = tid < TXe;
-    } else if (!full && e < 2 * R) {
+    if (ewave && !full && e < 2 * R) {
         x2 = e < R ? -R + e : TXe + (e - R);
         p2 = wc = true;
     }
@@ -368,10 +393,11 @@ __global__ void __launch_bounds__(TX + 64)
     }
 }
 
-template <class ST, typename real, bool NOISE, int TX, int BARS>
+template <class ST, typename real, bool NOISE, int TX, int BARS, bool HIN = false>
 inline hipError_t launch_two(const StepLaunch &P, hipStream_t s) {
-    hipLaunchKernelGGL((k_step2<ST, real, NOISE, TX, BARS>), dim3(P.total_tiles), dim3(TX + 64), 0, s, P.reps,
-                       P.tile_begin, P.nrep, P.parity, P.step_base, P.step_off);
+    hipLaunchKernelGGL((k_step2<ST, real, NOISE, TX, BARS, HIN>), dim3(P.total_tiles),
+                       dim3(step2_lanes<ST, TX, HIN>()), 0, s, P.reps, P.tile_begin, P.nrep, P.parity,
+                       P.step_base, P.step_off);
     return hipGetLastError();
 }
 

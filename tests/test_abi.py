@@ -56,14 +56,20 @@ def test_tiling_table_is_host_only_and_consistent():
     for D, st, prec in ((2, 4, "fp32"), (2, 8, "fp32"), (3, 4, "fp32"), (2, 4, "fp64"), (3, 4, "fp64")):
         shapes = fsc.tile_shapes(D, st, prec)
         assert shapes and len(set(shapes)) == len(shapes)
+        # widths whose two-step workgroups hold the 4R + 2 halo columns in
+        # the tile's own lanes (256 of them), and their single-step partners
+        hin = 256 - (4 * (2 if st == 8 else 1) + 2)
         for tx, ty, pf, steps in shapes:
-            assert tx % 32 == 0 and tx * ty <= 512 and steps in (1, 2)
+            assert (tx % 32 == 0 or tx == hin) and tx * ty <= 1024 and steps in (1, 2)
             assert (ty == 1) == (D == 2)
         two = [s for s in shapes if s[3] == 2]
         # the temporally blocked kernel exists for 2D FP32 only, in both LDS schedules
         assert bool(two) == (D == 2 and prec == "fp32")
         if two:
-            assert {s[2] for s in two} == {0, 1} and {s[0] for s in two} == {128, 192, 256}
+            assert {s[2] for s in two} == {0, 1} and {s[0] for s in two} == {128, 192, 256, hin}
+            # every two-step width has a single-step tiling of the same width
+            # (for steps that cannot be paired)
+            assert {s[0] for s in two} <= {s[0] for s in shapes if s[3] == 1} | {192}
         assert shapes[0][3] == 1  # the default is a single-step tiling
     with pytest.raises(fsc.FscError):
         fsc.tile_shapes(3, 8, "fp32")

@@ -23,7 +23,7 @@ def test_kernel_names_match_the_profiler_names():
     names = {e["kernel"] for e in _profile()["entries"]}
     # the ensemble's two-step launch, and single-step kernels of both lattices
     two = dict(tx=256, ty=1, pf=1, blocks=741, steps=2)
-    assert bench.kernel_name("StencilE4_2D", True, two) == "k_step2<StencilE4_2D, float, true, 256, 2>"
+    assert bench.kernel_name("StencilE4_2D", True, two) == "k_step2<StencilE4_2D, float, true, 256, 2, false>"
     assert bench.kernel_name("StencilE4_2D", True, two) in names
     one3 = dict(tx=64, ty=4, pf=0, blocks=512, steps=1)
     assert bench.kernel_name("StencilE4_3D", True, one3, "D3Q19") in names
@@ -34,9 +34,16 @@ def test_kernel_names_match_the_profiler_names():
 def test_grid_threads_counts_the_edge_wave_of_the_two_step_kernel():
     assert bench.grid_threads(dict(tx=256, ty=1, pf=1, blocks=741, steps=2)) == 741 * 320
     assert bench.grid_threads(dict(tx=64, ty=4, pf=0, blocks=512, steps=1)) == 512 * 256
+    # the tilings whose lanes hold the halo columns: 246 + 10 (E8), 250 + 6 (E4)
+    hin = dict(tx=246, ty=1, pf=0, blocks=765, steps=2)
+    assert bench.grid_threads(hin) == 765 * 256
+    assert bench.kernel_name("StencilE8_2D", True, hin) == "k_step2<StencilE8_2D, float, true, 246, 1, true>"
+    assert bench.grid_threads(dict(tx=250, ty=1, pf=1, blocks=10, steps=2)) == 10 * 256
+    # the single-step partner of a 246-wide tiling has no edge wave
+    assert bench.grid_threads(dict(tx=246, ty=1, pf=1, blocks=10, steps=1)) == 10 * 246
     # and the profile holds the benchmarked launch under that size
     sizes = {e["grid_threads"] for e in _profile()["entries"]
-             if e["kernel"] == "k_step2<StencilE4_2D, float, true, 256, 2>"}
+             if e["kernel"] == "k_step2<StencilE4_2D, float, true, 256, 2, false>"}
     assert 741 * 320 in sizes
 
 
@@ -53,7 +60,7 @@ def test_ingest_scales_the_counters_by_the_copy_calibration(tmp_path):
     # FETCH_SIZE reads half the true bytes of a 1 GiB copy (as on this part),
     # WRITE_SIZE reads them exactly; a step kernel's readings scale alike
     copy = "void fsc::k_copy(uint4 const*, uint4*, long)"
-    step = "void fsc::k_step2<fsc::StencilE4_2D, float, true, 256, 2>(fsc::RepDesc const*, int const*, int, int, unsigned long const*, unsigned int)"
+    step = "void fsc::k_step2<fsc::StencilE4_2D, float, true, 256, 2, false>(fsc::RepDesc const*, int const*, int, int, unsigned long const*, unsigned int)"
     kib = float(1 << 20)  # 1 GiB in KiB
     f, w, v = tmp_path / "f.csv", tmp_path / "w.csv", tmp_path / "v.csv"
     _write_csv(f, "FETCH_SIZE", [(copy, 1 << 26, kib / 2)] * 3 + [(step, 237120, 1000.0), (step, 237120, 1002.0)])
@@ -64,7 +71,7 @@ def test_ingest_scales_the_counters_by_the_copy_calibration(tmp_path):
     assert doc["calibration"]["fetch_scale"] == pytest.approx(2.0)
     assert doc["calibration"]["write_scale"] == pytest.approx(1.0)
     (e,) = doc["entries"]
-    assert e["kernel"] == "k_step2<StencilE4_2D, float, true, 256, 2>" and e["grid_threads"] == 237120
+    assert e["kernel"] == "k_step2<StencilE4_2D, float, true, 256, 2, false>" and e["grid_threads"] == 237120
     assert e["fetch_bytes"] == int(1001.0 * 1024 * 2.0)
     assert e["write_bytes"] == int(500.0 * 1024)
     assert e["bytes_per_launch"] == int(1001.0 * 1024 * 2.0 + 500.0 * 1024)
@@ -84,7 +91,7 @@ def test_kernel_view_prices_a_launch_by_its_nodes():
     q = dict(D=2, nx=4096, ny=4096, nz=1, stencil=8, precision="fp32")
     two = dict(tx=192, ty=1, pf=0, blocks=1012, steps=2)
     kv = bench.kernel_view(q, two, t_step=200e-6)
-    assert kv["kernel"] == "k_step2<StencilE8_2D, float, true, 192, 1>"
+    assert kv["kernel"] == "k_step2<StencilE8_2D, float, true, 192, 1, false>"
     assert kv["nodes_per_launch"] == 4096 * 4096 and kv["lups_per_launch"] == 2 * 4096 * 4096
     assert kv["algorithmic_bytes_per_launch"] == 72 * 4096 * 4096
     assert kv["avg_launch_us"] == pytest.approx(400.0)
