@@ -315,7 +315,7 @@ def test_quench_early_sk_growth_matches_exact_linear_theory():
     ens = fsc.Ensemble(plist)
     try:
         ens.init_uniform()
-        ens.set_tiling(192, 1, 0, 2)
+        ens.set_tiling(246, 1, 0, 2)  # the headline tiling (halo columns in the tile lanes)
         ens.run(steps, every)
         s = sum(ens.read_sk(r, fsc.FSC_SK_AXIS)[0] for r in range(nrep))
         cnt = sum(ens.read_sk(r, fsc.FSC_SK_AXIS)[2] for r in range(nrep))
