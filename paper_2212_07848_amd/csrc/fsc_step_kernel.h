@@ -91,7 +91,26 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float fexpm1(float x) { return expm1f(x); }
+// exp(x) - 1 in FP32 for the pseudopotential: for |x| < 1/2 the Taylor series
+// through x^9 (truncation below 6e-10 relative), else the hardware exp2 minus
+// one, where exp(x) is far enough from 1 that the subtraction loses at most a
+// few ulp (about 2e-7 relative over the range at most).  Both branches are
+// evaluated and one is selected, which is cheaper than the library's
+// general expm1f with its special cases (the argument here is bounded above by
+// 1 / n0 and NaN propagates).
+__device__ __forceinline__ float fexpm1(float x) {
+    float q = 1.0f / 362880.0f;
+    q = fmadd(q, x, 1.0f / 40320.0f);
+    q = fmadd(q, x, 1.0f / 5040.0f);
+    q = fmadd(q, x, 1.0f / 720.0f);
+    q = fmadd(q, x, 1.0f / 120.0f);
+    q = fmadd(q, x, 1.0f / 24.0f);
+    q = fmadd(q, x, 1.0f / 6.0f);
+    q = fmadd(q, x, 0.5f);
+    const float taylor = fmadd(x * x, q, x);
+    const float viaexp = __builtin_amdgcn_exp2f(x * 1.44269504088896341f) - 1.0f;
+    return __builtin_fabsf(x) < 0.5f ? taylor : viaexp;
+}
 __device__ __forceinline__ double fexpm1(double x) { return expm1(x); }
 
 // ---------------------------------------------------------------------------
