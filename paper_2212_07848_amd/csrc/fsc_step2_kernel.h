@@ -69,7 +69,11 @@ __global__ void __launch_bounds__((step2_lanes<ST, TX, HIN>()))
     using L = D2Q9;
     constexpr int Q = 9, R = ST::R, NN = L::NNORM;
     constexpr int NR = R + 1;                       // register rings (rows)
-    constexpr int SA = 2 * R + 2, SB = BARS == 1 ? 4 : 3, SC = 2 * R + 2;
+    // psi rings of 2R + 2 rows, rounded up to a power of two in the in-tile
+    // halo form with one barrier (its LDS still allows three workgroups per
+    // CU), so that ring slots wrap with a mask
+    constexpr int SPSI = (HIN && BARS == 1) ? ((2 * R + 2) <= 4 ? 4 : 8) : 2 * R + 2;
+    constexpr int SA = SPSI, SB = BARS == 1 ? 4 : 3, SC = SPSI;
     constexpr int OA = 2 * R + 1, OB = R + 1, OC = R;  // column of offset 0
     constexpr int WA = TX + 4 * R + 2, WB = TX + 2 * R + 2, WC = TX + 2 * R;
     constexpr uint32_t ES = sizeof(real);
@@ -212,7 +216,10 @@ __global__ void __launch_bounds__((step2_lanes<ST, TX, HIN>()))
     const int H1 = H + 2 * R + 2;                          // level-1 rows
 
     // ring slot t of a ring of n rows, for t within one ring length of [0, n)
-    auto wrapc = [](int t, int n) { return t < 0 ? t + n : (t >= n ? t - n : t); };
+    auto wrapc = [](int t, int n) {
+        if ((n & (n - 1)) == 0) return t & (n - 1);  // power of two (n is a constant)
+        return t < 0 ? t + n : (t >= n ? t - n : t);
+    };
     auto put_slot = [&](int sl, real v) {  // psi(t) of the row in slot sl of A
         if (wa) A[sl][x1 + OA] = v;
         if (ia_lo >= 0) A[sl][ia_lo] = v;
@@ -384,11 +391,11 @@ __global__ void __launch_bounds__((step2_lanes<ST, TX, HIN>()))
             row_ld = next_row(row_ld);
             row_1 = next_row(row_1);
             row_2 = next_row(row_2);
-            sa_j = sa_j + 1 == SA ? 0 : sa_j + 1;
-            sb_j = sb_j + 1 == SB ? 0 : sb_j + 1;
-            sb_p = sb_p + 1 == SB ? 0 : sb_p + 1;
-            sc_p = sc_p + 1 == SC ? 0 : sc_p + 1;
-            sc_m = sc_m + 1 == SC ? 0 : sc_m + 1;
+            sa_j = wrapc(sa_j + 1, SA);
+            sb_j = wrapc(sb_j + 1, SB);
+            sb_p = wrapc(sb_p + 1, SB);
+            sc_p = wrapc(sc_p + 1, SC);
+            sc_m = wrapc(sc_m + 1, SC);
         }
     }
 }
