@@ -82,6 +82,25 @@ def random_populations(Q: int, shape, rho0: float, amp: float, seed: int) -> np.
     return (rho0 / Q) * (1.0 + amp * rng.uniform(-1.0, 1.0, size=(Q,) + tuple(shape)))
 
 
+def wide_density_populations(Q: int, shape, lo: float, hi: float, modes: int,
+                             seed: int) -> np.ndarray:
+    """Populations rho(x)/Q (with 2% independent jitter) where rho sweeps the
+    whole range [lo, hi] in a few long waves: a state with the density
+    contrast of a phase-separated lattice, gas and liquid both present."""
+    rng = np.random.default_rng(seed)
+    grids = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    field = np.zeros(shape)
+    for _ in range(modes):
+        k = [2 * np.pi * rng.integers(1, 4) / s for s in shape]
+        field = field + np.cos(sum(kk * g for kk, g in zip(k, grids)) + rng.uniform(0, 2 * np.pi))
+    field = (field - field.min()) / (field.max() - field.min())
+    rho = lo + (hi - lo) * field
+    f = np.empty((Q,) + tuple(shape))
+    for i in range(Q):
+        f[i] = rho / Q * (1.0 + 0.02 * rng.uniform(-1, 1, size=shape))
+    return f
+
+
 def smooth_density_populations(Q: int, shape, rho0: float, amp: float, modes: int,
                                seed: int) -> np.ndarray:
     """Populations rho(x)/Q with rho a sum of a few random long-wave cosines of

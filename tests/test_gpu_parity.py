@@ -114,6 +114,34 @@ def test_steps_from_random_state(D, shape, stencil, precision):
     assert_pop_close(g3, r3, D, rho0, precision)
 
 
+@pytest.mark.parametrize("D,shape,stencil,precision,tiling", [
+    (2, (37, 300), 8, "fp32", (246, 1, 0, 2)),   # the headline's two-step tiling
+    (2, (37, 300), 8, "fp32", (128, 1, 1, 1)),
+    (2, (29, 41), 4, "fp32", (250, 1, 1, 2)),
+    (3, (9, 20, 37), 4, "fp32", (256, 4, 0, 1)),
+    (2, (29, 41), 8, "fp64", None),
+    (3, (9, 20, 37), 4, "fp64", None),
+])
+def test_phase_separated_densities_match_oracle(D, shape, stencil, precision, tiling):
+    # densities from 0.3 to 2.5 around n0 = 1: the pseudopotential's argument
+    # dn / (n0 n) runs from -2.3 to 0.6, through both branches of the FP32
+    # kernels' expm1 (|x| < 1/2 and beyond) and both signs of the force
+    Q = 9 if D == 2 else 19
+    f0 = I.wide_density_populations(Q, shape, 0.3, 2.5, 3, seed=31)
+    p = _params(D, shape, stencil, precision, T_hat=0.7, rho0=1.0, kBT=1e-4, seed=9)
+    with fsc.Lattice(p) as lat:
+        lat.set_populations(f0, 77)
+        if tiling is not None:
+            lat.set_tiling(*tiling, 1 << 20)
+        lat.step(2)
+        got = lat.get_populations()
+        G = lat.G
+    n0 = O.density(f0)
+    assert n0.min() < 0.35 and n0.max() > 2.4
+    ref = O.step(f0, 2, G=G, kind=stencil, kBT=1e-4, seed=9, t0=77)
+    assert_pop_close(got, ref, D, 1.0, precision)
+
+
 def test_coupling_from_reduced_temperature():
     with fsc.Lattice(_params(2, (8, 8), 4, "fp32", T_hat=0.8)) as lat:
         assert lat.G == pytest.approx(O.coupling_from_reduced_temperature(0.8), rel=1e-15)
