@@ -20,6 +20,8 @@ CASES = [
     (2, (13, 1100), 4, "fp32"),  # a last tile 76 wide: whole waves of it idle
     (2, (9, 6), 8, "fp32"),      # narrowest two-step width for E8 (2R + 2)
     (2, (41, 256), 8, "fp32"),
+    (2, (11, 247), 8, "fp32"),   # 246-column in-tile-halo tiles: a last tile one column wide
+    (2, (9, 251), 4, "fp32"),    # the same for E4's 250-column tiles
     (3, (23, 45, 37), 4, "fp32"),
     (3, (2, 3, 5), 4, "fp32"),   # thinner than the halo in every direction: all wraps
     (2, (40, 77), 8, "fp64"),
