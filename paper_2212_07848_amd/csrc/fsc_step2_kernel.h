@@ -28,8 +28,9 @@
 // tile's own; every stage keeps the lanes whose column lies in its range
 // (psi(t) [-2R-1, TXe+2R], level 1 [-R-1, TXe+R], psi(t+1) [-R, TXe+R-1],
 // level 2 [0, TXe-1]).  The edge wave's mostly idle lanes disappear: per
-// output column a launch issues about a tenth fewer wave instructions.  Whole
-// rows use the mapping above without the extra wave.
+// output column a launch issues about a tenth fewer wave instructions.  A
+// whole row takes the same mapping, its halo columns wrapped periodically, so
+// no mirrored writes are needed.
 //
 // March of a chunk of H output rows o_0..o_{H-1} (direction alternating by
 // chunk as in the single-step kernel): level 1 runs over the rows
@@ -105,11 +106,13 @@ __global__ void __launch_bounds__((step2_lanes<ST, TX, HIN>()))
     const int H = s_end - s_begin;
     const int x0 = tix * TX;
     const int TXe = min(TX, nx - x0);
-    const bool full = d.tiles_x == 1;  // TXe == nx: the tile holds whole periodic rows
+    // TXe == nx: the tile holds whole periodic rows (mirrored LDS writes; the
+    // in-tile-halo form instead wraps its halo columns, which fit its lanes)
+    const bool full = !HIN && d.tiles_x == 1;
 
     const int tid = threadIdx.x;
-    // HIN with a tile that is not a whole row: lane tid owns column tid - (2R + 1)
-    const bool shifted = HIN && !full;  // wave-uniform
+    // HIN: lane tid owns column tid - (2R + 1), whole rows included
+    const bool shifted = HIN;
     const bool ewave = !HIN && tid >= TX;
     const int e = tid - TX;
     const bool eidle = ewave && full;  // wave-uniform
