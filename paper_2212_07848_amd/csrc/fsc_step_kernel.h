@@ -149,56 +149,55 @@ __device__ __forceinline__ void collide_d2q9(real (&f)[9], real rho0, const real
 
     // noise: row a of class c adds sqrt(b_a) amp_c sqrt(n) xi_a
     constexpr RowScale<D2Q9> sb{};
-    real sa[4] = {real(0), real(0), real(0), real(0)};
-    if constexpr (NOISE) {
-        const real sr = fsqrt(rho);
-        sa[1] = ac[1] * sr;
-        sa[2] = ac[2] * sr;
-        sa[3] = ac[3] * sr;
-    }
-    auto relax = [&](int a, real m, real meq, real src, real zz) {
+    const real sr = NOISE ? fsqrt(rho) : real(0);
+    // second-moment row a: equilibrium rho q (q its quadratic form of u), Guo
+    // source ks s (ks: the row's source constant times 1 - l/2, a per-class
+    // constant formed outside the node loop)
+    auto relax = [&](int a, real m, real q, real ks, real s, real zz) {
         const real l = lc[D2Q9::cls(a)];
-        real o = fmadd(l, meq - m, m);
-        o = fmadd(fmadd(real(-0.5), l, real(1)), src, o);
-        if constexpr (NOISE) o = fmadd(real(sb.v[a]) * sa[D2Q9::cls(a)], zz, o);
+        real o = fmadd(l, fmadd(rho, q, -m), m);
+        o = fmadd(ks, s, o);
+        if constexpr (NOISE) o = fmadd(real(sb.v[a]) * ac[D2Q9::cls(a)] * sr, zz, o);
         return o;
     };
     auto ghost = [&](int a, real m, real zz) {
         real o = (real(1) - lc[3]) * m;
-        if constexpr (NOISE) o = fmadd(real(sb.v[a]) * sa[3], zz, o);
+        if constexpr (NOISE) o = fmadd(real(sb.v[a]) * ac[3] * sr, zz, o);
         return o;
     };
-    // conserved moments (mass; momentum with the full force) divided by b_a
-    const real n0 = dn;
-    const real n1 = (jx + F[0]) * real(3);
-    const real n2 = (jy + F[1]) * real(3);
+    const real k1 = fmadd(real(-0.5), lc[1], real(1)), k2 = fmadd(real(-0.5), lc[2], real(1));
     // post-collision moments o_a; n_a = o_a / b_a enters the back-transform
     // through the factors below (b_3..b_8 = 4, 4/9, 1/9, 2/3, 2/3, 16)
-    const real o3 = relax(3, m3, real(3) * rho * fmadd(ux, ux, uyy), real(6) * fmadd(ux, F[0], uFy), z[0]);
-    const real o4 = relax(4, m4, rho * fmadd(ux, ux, -uyy), real(2) * fmadd(ux, F[0], -uFy), z[1]);
-    const real o5 = relax(5, m5, rho * uxy, fmadd(ux, F[1], uy * F[0]), z[2]);
+    const real o3 = relax(3, m3, real(3) * fmadd(ux, ux, uyy), real(6) * k1, fmadd(ux, F[0], uFy), z[0]);
+    const real o4 = relax(4, m4, fmadd(ux, ux, -uyy), real(2) * k2, fmadd(ux, F[0], -uFy), z[1]);
+    const real o5 = relax(5, m5, uxy, k2, fmadd(ux, F[1], uy * F[0]), z[2]);
     const real o6 = ghost(6, m6, z[3]);
     const real o7 = ghost(7, m7, z[4]);
     const real o8 = ghost(8, m8, z[5]);
 
-    // back-transform f_i = w_i sum_a M_ai n_a
+    // back-transform f_i = w_i sum_a M_ai n_a, the weights folded in: with
+    // t = j + F (the conserved momentum over b_1 = 1/3 is 3 t),
+    // w_1 (3 t_x - 1.5 o_6) = t_x / 3 - o_6 / 6 and w_5 (3 t_x + 3 o_6) = (t_x + o_6) / 12
+    const real n0 = dn;
+    const real tx = jx + F[0], ty = jy + F[1];
     const real w0 = real(4.0 / 9.0), w1 = real(1.0 / 9.0), w5 = real(1.0 / 36.0);
     f[0] = w0 * fmadd(real(0.125), o8, fmadd(real(-0.5), o3, n0));
     const real ba = fmadd(real(-0.25), o8, fmadd(real(0.25), o3, n0));
     const real ap = fmadd(real(2.25), o4, ba), am = fmadd(real(-2.25), o4, ba);
-    const real px = fmadd(real(-1.5), o6, n1), py = fmadd(real(-1.5), o7, n2);
-    f[1] = w1 * (ap + px);
-    f[3] = w1 * (ap - px);
-    f[2] = w1 * (am + py);
-    f[4] = w1 * (am - py);
+    const real px = fmadd(real(-1.0 / 6.0), o6, tx * real(1.0 / 3.0));
+    const real py = fmadd(real(-1.0 / 6.0), o7, ty * real(1.0 / 3.0));
+    f[1] = fmadd(w1, ap, px);
+    f[3] = fmadd(w1, ap, -px);
+    f[2] = fmadd(w1, am, py);
+    f[4] = fmadd(w1, am, -py);
     const real bd = fmadd(real(0.5), o8, n0 + o3);
     const real bp = fmadd(real(9), o5, bd), bm = fmadd(real(-9), o5, bd);
-    const real X = fmadd(real(3), o6, n1), Y = fmadd(real(3), o7, n2);
-    const real XpY = X + Y, XmY = X - Y;
-    f[5] = w5 * (bp + XpY);
-    f[7] = w5 * (bp - XpY);
-    f[6] = w5 * (bm - XmY);
-    f[8] = w5 * (bm + XmY);
+    const real X = tx + o6, Y = ty + o7;
+    const real XpY = (X + Y) * real(1.0 / 12.0), XmY = (X - Y) * real(1.0 / 12.0);
+    f[5] = fmadd(w5, bp, XpY);
+    f[7] = fmadd(w5, bp, -XpY);
+    f[6] = fmadd(w5, bm, -XmY);
+    f[8] = fmadd(w5, bm, XmY);
 }
 
 // ---------------------------------------------------------------------------
