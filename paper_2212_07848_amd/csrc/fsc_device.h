@@ -182,7 +182,13 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
-__host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+// a ^ b ^ c as one gfx950 three-input bit operation (truth table 0x96: the
+// parity of the three inputs) instead of two XORs
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
     constexpr uint32_t MA = 0xD2511F53u, MB = 0xCD9E8D57u;
     constexpr uint32_t WA = 0x9E3779B9u, WB = 0xBB67AE85u;
 #pragma unroll
@@ -190,9 +196,16 @@ __host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
         const uint64_t pa = uint64_t(MA) * c.x;
         const uint64_t pb = uint64_t(MB) * c.z;
         U4 n;
-        n.x = uint32_t(pb >> 32) ^ c.y ^ k0;
+        if (r < 2) {
+            // the first two rounds see wave-uniform counter words (step, block,
+            // seed), whose XORs the scalar unit takes
+            n.x = uint32_t(pb >> 32) ^ c.y ^ k0;
+            n.z = uint32_t(pa >> 32) ^ c.w ^ k1;
+        } else {
+            n.x = xor3(uint32_t(pb >> 32), c.y, k0);
+            n.z = xor3(uint32_t(pa >> 32), c.w, k1);
+        }
         n.y = uint32_t(pb);
-        n.z = uint32_t(pa >> 32) ^ c.w ^ k1;
         n.w = uint32_t(pa);
         c = n;
         k0 += WA;
@@ -214,20 +227,29 @@ __host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 //                                  (high half first)
 //   (z_2k, z_2k+1) = sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b); normal k goes
 //   to the k-th non-conserved moment.  Both uniforms are exact in float.
+// UNIT = false (the FP32 step kernels): the normals come divided by
+// sqrt(2 ln 2), so that the radius is sqrt(-log2 u_a), one multiply fewer per
+// pair; those kernels fold BM_SCALE into their noise amplitudes.
+constexpr float BM_SCALE = 1.17741002251547469f;  // sqrt(2 ln 2)
+
+template <bool UNIT = true>
 __device__ __forceinline__ void box_muller(float ua, float ub, float &z0, float &z1) {
 #ifdef FSC_ACCURATE_BOX_MULLER
-    const float rad = sqrtf(-2.0f * logf(ua));
+    const float rad = UNIT ? sqrtf(-2.0f * logf(ua)) : sqrtf(-log2f(ua));
     float s, c;
     sincospif(2.0f * ub, &s, &c);
 #else
     // hardware log2, sqrt and sin/cos (argument in revolutions)
-    const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ua));
+    const float l2 = __builtin_amdgcn_logf(ua);
+    const float rad = __builtin_amdgcn_sqrtf(UNIT ? -1.3862943611198906f * l2 : -l2);
     const float s = __builtin_amdgcn_sinf(ub), c = __builtin_amdgcn_cosf(ub);
 #endif
     z0 = rad * c;
     z1 = rad * s;
 }
+template <bool UNIT = true>
 __device__ __forceinline__ void box_muller(double ua, double ub, double &z0, double &z1) {
+    static_assert(UNIT, "FP64 normals are always unit");
     const double rad = sqrt(-2.0 * log(ua));
     double s, c;
     sincospi(2.0 * ub, &s, &c);
@@ -235,7 +257,7 @@ __device__ __forceinline__ void box_muller(double ua, double ub, double &z0, dou
     z1 = rad * s;
 }
 
-template <class L, typename real>
+template <class L, typename real, bool UNIT = true>
 __device__ __forceinline__ void node_normals(uint32_t node, uint32_t step, uint32_t seed_hi,
                                              uint32_t k0, uint32_t k1, real (&z)[L::NNORM]) {
     constexpr int NN = L::NNORM;
@@ -257,10 +279,20 @@ __device__ __forceinline__ void node_normals(uint32_t node, uint32_t step, uint3
             h = k == 0 ? (w[3] >> 16) : (k == 1 ? (w[3] & 0xffffu) : (((w[0] & 0xffu) << 8) | (w[1] & 0xffu)));
         else
             h = (k & 1) ? (w[8 + k / 2] & 0xffffu) : (w[8 + k / 2] >> 16);
-        const real ua = real((w[k] >> 8) | 1u) * real(5.9604644775390625e-08);     // (2m+1) 2^-24
-        const real ub = real(2u * h + 1u) * real(7.62939453125e-06);                  // (2h+1) 2^-17
+        real ua, ub;
+        if constexpr (sizeof(real) == 4) {
+            // the same values from the bits, each an exact subtraction: the float
+            // 1 + m 2^-23 (m = w_k >> 9 as its mantissa) minus 1 - 2^-24, and
+            // 1 + (2h + 1) 2^-17 minus 1
+            const uint32_t fa = __builtin_amdgcn_alignbit(0x7Fu, w[k], 9u);
+            ua = __builtin_bit_cast(float, fa) - (1.0f - 5.9604644775390625e-08f);
+            ub = __builtin_bit_cast(float, (h << 7) | 0x3F800040u) - 1.0f;
+        } else {
+            ua = real((w[k] >> 8) | 1u) * real(5.9604644775390625e-08);  // (2m+1) 2^-24
+            ub = real(2u * h + 1u) * real(7.62939453125e-06);             // (2h+1) 2^-17
+        }
         real z0, z1;
-        box_muller(ua, ub, z0, z1);
+        box_muller<UNIT>(ua, ub, z0, z1);
         z[2 * k] = z0;
         if (2 * k + 1 < NN) z[2 * k + 1] = z1;
     }

@@ -179,7 +179,8 @@ __global__ void __launch_bounds__((step2_lanes<ST, TX, HIN>()))
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         lc[k] = F32 ? real(d.lamcf[k]) : real(d.lamc[k]);
-        ac[k] = F32 ? real(d.ampcf[k]) : real(d.ampc[k]);
+        // FP32: the normals come in units of BM_SCALE (see box_muller)
+        ac[k] = F32 ? real(d.ampcf[k] * BM_SCALE) : real(d.ampc[k]);
     }
 
     // ---- pull offsets of the level-1 node (bytes within a row) ---------------
@@ -365,10 +366,10 @@ __global__ void __launch_bounds__((step2_lanes<ST, TX, HIN>()))
             // noise of both levels (independent of memory and LDS)
             real z1[NN], z2[NN];
             if constexpr (NOISE) {
-                if (lev1 && !idle) node_normals<L, real>(uint32_t(gx1 + nx * row_1), step1, d.seed_hi,
+                if (lev1 && !idle) node_normals<L, real, !F32>(uint32_t(gx1 + nx * row_1), step1, d.seed_hi,
                                                          d.key0, d.key1, z1);
                 if (lev2 && st2)
-                    node_normals<L, real>(uint32_t(gx2 + nx * row_2), step2, d.seed_hi, d.key0, d.key1, z2);
+                    node_normals<L, real, !F32>(uint32_t(gx2 + nx * row_2), step2, d.seed_hi, d.key0, d.key1, z2);
             }
             if constexpr (!NOISE) {
 #pragma unroll

@@ -92,15 +92,14 @@ __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 // exp(x) - 1 in FP32 for the pseudopotential: for |x| < 1/2 the Taylor series
-// through x^9 (truncation below 6e-10 relative), else the hardware exp2 minus
-// one, where exp(x) is far enough from 1 that the subtraction loses at most a
-// few ulp (about 2e-7 relative over the range at most).  Both branches are
-// evaluated and one is selected, which is cheaper than the library's
-// general expm1f with its special cases (the argument here is bounded above by
-// 1 / n0 and NaN propagates).
+// through x^8 (truncation below 1.5e-8 relative, a quarter of an FP32 ulp),
+// else the hardware exp2 minus one, where exp(x) is far enough from 1 that the
+// subtraction loses at most a few ulp (about 2e-7 relative over the range at
+// most).  Both branches are evaluated and one is selected, which is cheaper
+// than the library's general expm1f with its special cases (the argument here
+// is bounded above by 1 / n0 and NaN propagates).
 __device__ __forceinline__ float fexpm1(float x) {
-    float q = 1.0f / 362880.0f;
-    q = fmadd(q, x, 1.0f / 40320.0f);
+    float q = 1.0f / 40320.0f;
     q = fmadd(q, x, 1.0f / 5040.0f);
     q = fmadd(q, x, 1.0f / 720.0f);
     q = fmadd(q, x, 1.0f / 120.0f);
@@ -411,7 +410,8 @@ __global__ void __launch_bounds__(TX *TY)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         lc[k] = F32 ? real(d.lamcf[k]) : real(d.lamc[k]);
-        ac[k] = F32 ? real(d.ampcf[k]) : real(d.ampc[k]);
+        // FP32: the normals come in units of BM_SCALE (see box_muller)
+        ac[k] = F32 ? real(d.ampcf[k] * BM_SCALE) : real(d.ampc[k]);
     }
 
     // ---- per-lane pull offsets (bytes, within a plane), by (c_x, c_y) ------
@@ -562,7 +562,7 @@ __global__ void __launch_bounds__(TX *TY)
             real z[NN];
             if constexpr (NOISE) {
                 const uint32_t node = uint32_t(x + nx * (y + (D == 3 ? ny * s : s)));
-                node_normals<L, real>(node, step32, d.seed_hi, d.key0, d.key1, z);
+                node_normals<L, real, !F32>(node, step32, d.seed_hi, d.key0, d.key1, z);
             } else {
 #pragma unroll
                 for (int k = 0; k < NN; ++k) z[k] = real(0);
