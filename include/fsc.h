@@ -420,9 +420,11 @@ int fsc_mfma_probe(const float *host_a, const float *host_b, float *host_c);
 
 /* Times every compiled tile shape (cross-section tile, register prefetch
  * depth) and marching length on the context's own buffers and keeps the
- * fastest; the choice is cached per process and geometry.  The state is not
- * changed (a trial launch only writes the buffer that holds no live data) and
- * results do not depend on the tiling.  fsc_step / fsc_run tune automatically
+ * fastest; the choice is cached per process and geometry.  Trial launches
+ * alternate between the two buffers as a run does, on a temporary device copy
+ * of the state that is put back afterwards (without room for the copy, every
+ * trial reads the current buffer and writes the other).  The state is not
+ * changed and results do not depend on the tiling.  fsc_step / fsc_run tune automatically
  * on first use when the lattice (or ensemble) has at least 2^20 nodes, unless
  * the environment sets FSC_AUTOTUNE=0 (FSC_AUTOTUNE=1 tunes at any size). */
 int fsc_autotune(fsc_ctx *ctx);

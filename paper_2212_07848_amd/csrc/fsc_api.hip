@@ -615,10 +615,14 @@ bool two_step_ok(const fsc_ens *e) {
 
 // -------------------------------------------------------------------------
 // Autotuner: times every compiled tile shape and marching-length target on the
-// ensemble's own buffers and keeps the fastest.  A step launch only reads the
-// current state and writes the other buffer, which holds nothing needed, and
-// the step counter is not advanced, so tuning leaves the state untouched.
-// The per-node arithmetic does not depend on the tiling, so neither do results.
+// ensemble's own buffers and keeps the fastest.  Trial launches alternate
+// between the two buffers as a run does (each reads what the one before
+// wrote); the state is copied aside first and put back afterwards, and the
+// step counter is not advanced, so tuning leaves the state untouched.  Without
+// room for the copy every trial launch reads the current buffer and writes the
+// other, which holds nothing needed (that times the caches differently from a
+// run and can prefer a slower march length).  The per-node arithmetic does not
+// depend on the tiling, so neither do results.
 // -------------------------------------------------------------------------
 struct TuneChoice {
     TileShape tile;
@@ -661,20 +665,55 @@ int ens_autotune(fsc_ens *e) {
     HIPCHK(e, hipEventCreate(&b));
     TuneChoice choice{e->tile, e->target_blocks};
     const int parity = e->cur;
+    // the state, copied aside for the alternating trials and put back on every
+    // way out of this function
+    struct StateCopy {
+        fsc_ens *e;
+        int parity;
+        std::vector<void *> saved;
+        static size_t bytes(const Rep &r) { return size_t(r.Q) * size_t(r.N) * r.esz; }
+        ~StateCopy() {
+            for (size_t i = 0; i < saved.size(); ++i)
+                (void)hipMemcpyAsync(e->reps[i].buf[parity], saved[i], bytes(e->reps[i]),
+                                     hipMemcpyDeviceToDevice, e->stream);
+            if (!saved.empty()) (void)hipStreamSynchronize(e->stream);
+            for (void *q : saved) (void)hipFree(q);
+        }
+    } copy{e, parity, {}};
+    bool alternate = true;
+    for (const Rep &r : e->reps) {
+        void *q = nullptr;
+        if (hipMalloc(&q, StateCopy::bytes(r)) != hipSuccess) {
+            (void)hipGetLastError();
+            alternate = false;
+            break;
+        }
+        const hipError_t ce = hipMemcpyAsync(q, r.buf[parity], StateCopy::bytes(r), hipMemcpyDeviceToDevice, e->stream);
+        if (ce != hipSuccess) {  // only complete copies are put back
+            (void)hipFree(q);
+            return fail(e, FSC_E_HIP, std::string("autotune state copy: ") + hipGetErrorString(ce));
+        }
+        copy.saved.push_back(q);
+    }
+    if (!alternate) {
+        HIPCHK(e, hipStreamSynchronize(e->stream));
+        for (void *q : copy.saved) (void)hipFree(q);
+        copy.saved.clear();
+    }
     // the fastest of `windows` windows of `per` launches, per step (robust to
-    // a transient slowdown of one window); the launches write the other
-    // buffer from the current one, so the state does not change
+    // a transient slowdown of one window)
     auto time_choice = [&](const TuneChoice &c, int windows, int per, float *ms_out) -> int {
         e->tile = c.tile;
         e->target_blocks = c.target;
         int rc = upload_desc(e);
         if (rc) return rc;
-        const StepLaunch L = make_launch(e, parity, 0);
-        for (int k = 0; k < 2; ++k) HIPCHK(e, launch_step(L, e->stream));
+        const StepLaunch L[2] = {make_launch(e, parity, 0), make_launch(e, alternate ? parity ^ 1 : parity, 0)};
+        int n = 0;  // launches so far: buffer parity of the next one
+        for (int k = 0; k < 2; ++k) HIPCHK(e, launch_step(L[n++ & 1], e->stream));
         float ms = 1e30f;
         for (int w = 0; w < windows; ++w) {
             HIPCHK(e, hipEventRecord(a, e->stream));
-            for (int k = 0; k < per; ++k) HIPCHK(e, launch_step(L, e->stream));
+            for (int k = 0; k < per; ++k) HIPCHK(e, launch_step(L[n++ & 1], e->stream));
             HIPCHK(e, hipEventRecord(b, e->stream));
             HIPCHK(e, hipEventSynchronize(b));
             float t = 0.f;
@@ -695,18 +734,19 @@ int ens_autotune(fsc_ens *e) {
         }
     // The leaders often lie within a percent or two of each other, where
     // one short timing can swap them: the three fastest are timed again,
-    // round-robin (a drift of the clock then affects them alike), with longer
-    // windows, and the fastest of those wins.
+    // round-robin (a drift of the clock then affects them alike), in longer
+    // windows, and the lowest mean over the rounds wins (a run's speed is its
+    // mean; the best single window favoured a march length that runs slower).
     std::stable_sort(timed.begin(), timed.end(),
                      [](const auto &x, const auto &y) { return x.first < y.first; });
     const size_t lead = std::min<size_t>(3, timed.size());
-    std::vector<float> best_ms(lead, 1e30f);
-    for (int round = 0; round < 3; ++round)
+    std::vector<float> best_ms(lead, 0.f);
+    for (int round = 0; round < 4; ++round)
         for (size_t c = 0; c < lead; ++c) {
             float ms = 0.f;
-            int rc = time_choice(timed[c].second, 2, 6, &ms);
+            int rc = time_choice(timed[c].second, 1, 12, &ms);
             if (rc) return rc;
-            best_ms[c] = std::min(best_ms[c], ms);
+            best_ms[c] += ms;
         }
     size_t win = 0;
     for (size_t c = 1; c < lead; ++c)

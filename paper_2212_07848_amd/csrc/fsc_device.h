@@ -214,6 +214,42 @@ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
     return c;
 }
 
+// The 20 round keys of Philox4x32-10 (k0 of round r at rk[2r], k1 at rk[2r+1])
+// formed once, held in vector registers: an identity DPP move makes the
+// compiler keep them per lane, where the round XORs read them directly, instead
+// of forming them anew with scalar adds for every draw (there are too many to
+// keep in scalar registers beside the rest of a step kernel).
+struct PhiloxKeys {
+    uint32_t rk[20];
+};
+__device__ __forceinline__ PhiloxKeys philox_keys(uint32_t k0, uint32_t k1) {
+    constexpr uint32_t WA = 0x9E3779B9u, WB = 0xBB67AE85u;
+    PhiloxKeys K;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        K.rk[2 * r] = uint32_t(__builtin_amdgcn_mov_dpp(int(k0), 0xE4, 0xF, 0xF, false));
+        K.rk[2 * r + 1] = uint32_t(__builtin_amdgcn_mov_dpp(int(k1), 0xE4, 0xF, 0xF, false));
+        k0 += WA;
+        k1 += WB;
+    }
+    return K;
+}
+__device__ inline U4 philox4x32_10(U4 c, const PhiloxKeys &K) {
+    constexpr uint32_t MA = 0xD2511F53u, MB = 0xCD9E8D57u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = uint64_t(MA) * c.x;
+        const uint64_t pb = uint64_t(MB) * c.z;
+        U4 n;
+        n.x = xor3(uint32_t(pb >> 32), c.y, K.rk[2 * r]);
+        n.y = uint32_t(pb);
+        n.z = xor3(uint32_t(pa >> 32), c.w, K.rk[2 * r + 1]);
+        n.w = uint32_t(pa);
+        c = n;
+    }
+    return c;
+}
+
 // Noise normals of one node.  The paper fixes only that the thermal noise is
 // Gaussian and uncorrelated in space and time; the bit layout below is this
 // library's definition (the oracle implements the same one):
@@ -257,16 +293,16 @@ __device__ __forceinline__ void box_muller(double ua, double ub, double &z0, dou
     z1 = rad * s;
 }
 
-template <class L, typename real, bool UNIT = true>
+template <class L, typename real, bool UNIT = true, typename... Key>
 __device__ __forceinline__ void node_normals(uint32_t node, uint32_t step, uint32_t seed_hi,
-                                             uint32_t k0, uint32_t k1, real (&z)[L::NNORM]) {
+                                             real (&z)[L::NNORM], const Key &...key) {
     constexpr int NN = L::NNORM;
     constexpr int P = (NN + 1) / 2;
     constexpr int NB = L::D == 2 ? 1 : 3;
     uint32_t w[4 * NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        const U4 r = philox4x32_10(U4{node, step, uint32_t(b), seed_hi}, k0, k1);
+        const U4 r = philox4x32_10(U4{node, step, uint32_t(b), seed_hi}, key...);
         w[4 * b] = r.x;
         w[4 * b + 1] = r.y;
         w[4 * b + 2] = r.z;

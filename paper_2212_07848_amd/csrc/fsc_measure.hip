@@ -768,8 +768,8 @@ __global__ void k_normals(uint64_t seed, uint32_t replica, const int64_t *node,
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
     real z[NN];
-    node_normals<L, real>(uint32_t(node[k]), uint32_t(step[k]), uint32_t(seed >> 32),
-                          uint32_t(seed), replica, z);
+    node_normals<L, real>(uint32_t(node[k]), uint32_t(step[k]), uint32_t(seed >> 32), z,
+                          uint32_t(seed), replica);
     for (int q = 0; q < NN; ++q) out[k * NN + q] = double(z[q]);
 }
 

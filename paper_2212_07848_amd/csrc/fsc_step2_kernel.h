@@ -212,6 +212,15 @@ __global__ void __launch_bounds__((step2_lanes<ST, TX, HIN>()))
 
     const uint64_t step = step_base[0] + step_off;
     const uint32_t step1 = uint32_t(step), step2 = uint32_t(step + 1);
+    // Philox round keys held per lane (20 VGPRs) where LDS already limits the
+    // workgroups per CU (the one-barrier in-tile-halo form); elsewhere the
+    // registers would cost occupancy, and the keys are formed per draw
+    constexpr bool VKEYS = HIN && BARS == 1;
+    const PhiloxKeys PK = VKEYS ? philox_keys(d.key0, d.key1) : PhiloxKeys{};
+    auto normals = [&](uint32_t node, uint32_t st, real (&z)[NN]) {
+        if constexpr (VKEYS) node_normals<L, real, !F32>(node, st, d.seed_hi, z, PK);
+        else node_normals<L, real, !F32>(node, st, d.seed_hi, z, d.key0, d.key1);
+    };
 
     // ---- march order ----------------------------------------------------------
     const int dir = (chunk & 1) ? -1 : 1;
@@ -366,10 +375,8 @@ __global__ void __launch_bounds__((step2_lanes<ST, TX, HIN>()))
             // noise of both levels (independent of memory and LDS)
             real z1[NN], z2[NN];
             if constexpr (NOISE) {
-                if (lev1 && !idle) node_normals<L, real, !F32>(uint32_t(gx1 + nx * row_1), step1, d.seed_hi,
-                                                         d.key0, d.key1, z1);
-                if (lev2 && st2)
-                    node_normals<L, real, !F32>(uint32_t(gx2 + nx * row_2), step2, d.seed_hi, d.key0, d.key1, z2);
+                if (lev1 && !idle) normals(uint32_t(gx1 + nx * row_1), step1, z1);
+                if (lev2 && st2) normals(uint32_t(gx2 + nx * row_2), step2, z2);
             }
             if constexpr (!NOISE) {
 #pragma unroll

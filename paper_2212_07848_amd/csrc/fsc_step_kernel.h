@@ -562,7 +562,7 @@ __global__ void __launch_bounds__(TX *TY)
             real z[NN];
             if constexpr (NOISE) {
                 const uint32_t node = uint32_t(x + nx * (y + (D == 3 ? ny * s : s)));
-                node_normals<L, real, !F32>(node, step32, d.seed_hi, d.key0, d.key1, z);
+                node_normals<L, real, !F32>(node, step32, d.seed_hi, z, d.key0, d.key1);
             } else {
 #pragma unroll
                 for (int k = 0; k < NN; ++k) z[k] = real(0);
