@@ -385,7 +385,33 @@ def test_autotune_leaves_state_and_results_unchanged():
         b.step(23)
         assert np.array_equal(a.get_populations(), b.get_populations())
         t = b.tiling
-        assert t["blocks"] > 0 and t["tx"] in (64, 128, 256)
+        assert t["blocks"] > 0 and (t["tx"], t["ty"], t["pf"], t["steps"]) in fsc.tile_shapes(2, 8, "fp32")
+
+
+def test_ensemble_autotune_restores_every_replica():
+    # the autotuner's trial launches alternate the two buffers of every replica
+    # on a copy of the state, which it puts back: uneven replicas at an odd step
+    # (state in the second buffer) keep their populations, and continue exactly
+    # as an untuned twin
+    specs = [((96, 80), 0.8, 1.0), ((64, 200), 0.75, 1.2), ((130, 70), 0.9, 0.8)]
+    plist = [_params(2, sh, 8, "fp32", T_hat=th, rho0=r0, kBT=1e-4, seed=11, replica=k)
+             for k, (sh, th, r0) in enumerate(specs)]
+    a, b = fsc.Ensemble(plist), fsc.Ensemble(plist)
+    try:
+        a.init_uniform()
+        b.init_uniform()
+        a.run(30, 0)
+        b.run(13, 0)
+        before = [b.get_populations(k) for k in range(len(specs))]
+        b.autotune()
+        for k in range(len(specs)):
+            assert np.array_equal(before[k], b.get_populations(k)), k
+        b.run(17, 0)
+        for k in range(len(specs)):
+            assert np.array_equal(a.get_populations(k), b.get_populations(k)), k
+    finally:
+        a.close()
+        b.close()
 
 
 def test_checkpoint_resume_is_bit_exact(tmp_path):
