@@ -329,7 +329,7 @@ __global__ void __launch_bounds__((step2_lanes<ST, TX, HIN>()))
         collide_d2q9<real, NOISE>(fv, rho0, Fv, lc, ac, z);
         const uint32_t so = uint32_t(krow) * pbytes + lane_store;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) bstore(dst, so, uint32_t(i) * pop_bytes, fv[i]);
+        for (int i = 0; i < Q; ++i) bstore<HIN ? 0 : FSC_STORE_POLICY>(dst, so, uint32_t(i) * pop_bytes, fv[i]);
     };
 
     // Level 2 trails level 1.  Its pull (and psi(t+1)) of iteration j is row

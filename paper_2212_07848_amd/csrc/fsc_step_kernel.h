@@ -64,18 +64,20 @@ __device__ __forceinline__ double bload<double>(rsrc_t r, uint32_t voff, uint32_
 }
 // Cache policy of the population stores: 2 sets the non-temporal bit on
 // gfx950 (the stored planes are not read again within the step; measured a
-// few percent faster than the default policy, 0).
+// few percent faster than the default policy, 0, for the single-step kernels
+// and the two-step kernels with an edge wave).  The in-tile-halo two-step
+// kernels store with the default policy, which measured 4-5% faster for them.
 #ifndef FSC_STORE_POLICY
 #define FSC_STORE_POLICY 2
 #endif
+template <int POL = FSC_STORE_POLICY>
 __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff,
-                                          FSC_STORE_POLICY);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, POL);
 }
+template <int POL = FSC_STORE_POLICY>
 __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, double v) {
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff,
-                                          FSC_STORE_POLICY);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, POL);
 }
 
 // Fused multiply-add, written out wherever the step arithmetic uses one.  The
